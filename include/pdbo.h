@@ -1,0 +1,251 @@
+/*
+ * pdbo.h - C ABI of the PDBO hot path on MI355X (gfx950).
+ *
+ * PDBO (primal-dual binary optimisation) minimises F(x) over x in {0,1}^n
+ * (Eq. 1) by running Algorithm 1 - simultaneous projected gradient
+ * descent-ascent on the Lagrangian L(x,y) = f(x) + sum_i y_i g(x_i), with a
+ * perturbation away from 1/2 - from B independent starting points at once, and
+ * keeping the best rounded solution over all restarts (Sec. 5.2, Model
+ * Settings).  f is the multilinear extension of F (Def. 2.2; closed form by
+ * Prop. 2.2) and g a binarity constraint function (Sec. 3.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a pdbo_status; nothing aborts, exits or throws
+ *   across the ABI.  On failure a message is available from pdbo_last_error()
+ *   (per context) or pdbo_last_global_error() (when no context exists yet).
+ * - Arrays of iterates are restart-major: an (B, n) array holds restart b in
+ *   elements [b*n, (b+1)*n).  Unless stated otherwise these are HOST pointers;
+ *   they are read (or written) during the call only and remain caller-owned.
+ * - A context owns all device memory it allocates; pdbo_destroy() frees it.
+ *   The HIP stream passed at init is borrowed, never created or destroyed; all
+ *   device work of the context is enqueued on it.  One context per stream;
+ *   calls on one context must not overlap.
+ * - Objectives are always those of the ORIGINAL instance (Q, c) or clause
+ *   weights, evaluated exactly in int64, never of the scaled or quantised data.
+ * - Alg. 1 requires y^0 > 0, alpha, beta > 0 and delta > 0 (its Require line);
+ *   this library additionally requires delta < 1/2 and scale > 0.
+ */
+#ifndef PDBO_H
+#define PDBO_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PDBO_API __attribute__((visibility("default")))
+#else
+#define PDBO_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PDBO_OK = 0,
+  PDBO_EINVAL = 1,       /* an argument violates the documented contract   */
+  PDBO_ENOMEM = 2,       /* host or device allocation failed               */
+  PDBO_EDEVICE = 3,      /* a HIP runtime call failed (text in last_error) */
+  PDBO_ERANGE = 4,       /* an exactness guard of the integer paths failed */
+  PDBO_ESTATE = 5,       /* call not valid for this context or its state   */
+  PDBO_EUNSUPPORTED = 6  /* valid request outside what this build supports */
+} pdbo_status;
+
+typedef struct pdbo_ctx pdbo_ctx;
+
+enum { PDBO_DENSE = 0, PDBO_CSR = 1 };
+enum { PDBO_G_QUAD = 0, PDBO_G_ENTROPY = 1 };
+enum { PDBO_FP32 = 0, PDBO_BF16 = 1, PDBO_FP8 = 2 };
+
+/*
+ * QUBO instance (Eq. 1 with quadratic F): minimise F(x) = x^T Q x + c^T x over
+ * x in {0,1}^n.  Q may be asymmetric and may have a diagonal; the library works
+ * on the multilinear extension f(x) = 1/2 x^T A x + c'^T x with
+ * A = offdiag(Q + Q^T), c' = c + diag(Q) (Prop. 2.2), which equals F on {0,1}^n.
+ *   format == PDBO_DENSE: q points to n*n int32, row-major (Q_ij at q[i*n+j]).
+ *   format == PDBO_CSR:   row_ptr[n+1], col_idx[nnz], q = values[nnz] (int32),
+ *                         rows sorted by column, no duplicate (i,j) in a row.
+ *   c: n int64 linear coefficients, or NULL for c = 0.
+ * All pointers are host pointers.
+ */
+typedef struct {
+  int32_t n;
+  int32_t format;
+  const int32_t* q;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  int64_t nnz;
+  const int64_t* c;
+} pdbo_qubo;
+
+/*
+ * Weighted Max-k-SAT (Sec. 5.1, Max-k-SAT): minimise the total weight of the
+ * unsatisfied clauses.  lits holds m*k int32 literals, clause j in
+ * lits[j*k .. j*k+k), DIMACS convention: +v is x_v, -v is not x_v, v in 1..n;
+ * the k variables of a clause must be distinct.  w: m clause weights in
+ * [0, 2^24), or NULL for all ones.  Host pointers.
+ */
+typedef struct {
+  int32_t n;
+  int32_t m;
+  int32_t k;
+  const int32_t* lits;
+  const int32_t* w;
+} pdbo_maxsat;
+
+/*
+ * Parameters of Alg. 1 and of the execution.
+ *   B          number of restarts, >= 1.
+ *   alpha,beta primal / dual step sizes (> 0).
+ *   y0         initial dual value y^0 = y0 * 1 (> 0).
+ *   delta      perturbation tolerance, in (0, 1/2).
+ *   scale      s > 0: the method runs on f/s (gradient (A x + c')/s); the
+ *              objective is still reported unscaled.
+ *   g_kind     PDBO_G_QUAD (x^2 - x) or PDBO_G_ENTROPY (x log x + (1-x) log(1-x),
+ *              derivative taken at x clipped to [2^-20, 1 - 2^-20]).
+ *   precision  operand type of the dense gradient product A.X (FP32 accumulate
+ *              always): PDBO_FP32, PDBO_BF16 (A and a bf16 copy of X), PDBO_FP8
+ *              (A as OCP e4m3 with one fp32 scale per row, X as e4m3).
+ *              Ignored by the CSR and MaxSAT paths, whose integer weights are
+ *              stored exactly.
+ *   eval_every evaluate round(x^t) every eval_every iterations (>= 1); the
+ *              persistent CSR and MaxSAT paths require 1.
+ *   tile       dense tile configuration id (0 = default for the shape).
+ *   graph_chunk  dense path: 0 = eager launches; K > 0 (even) = capture K
+ *              iterations in one hipGraph and replay it.
+ *   x0         HOST (B, n) float64 starting points in [0,1] (required).
+ */
+typedef struct {
+  int32_t B;
+  int32_t g_kind;
+  int32_t precision;
+  int32_t eval_every;
+  double alpha;
+  double beta;
+  double y0;
+  double delta;
+  double scale;
+  int32_t tile;
+  int32_t graph_chunk;
+  const double* x0;
+} pdbo_params;
+
+/* Incumbent of a run: the lexicographic minimum of (F, t, b) over all
+ * evaluated rounded iterates x_r = [x^t > 1/2], t >= 1. */
+typedef struct {
+  int64_t best_obj;       /* exact F of best_x (weighted unsat count for MaxSAT) */
+  int32_t best_restart;   /* b, or -1 when nothing has been evaluated yet        */
+  int32_t _pad;
+  int64_t best_iter;      /* iteration t (1-based) at which it was first reached */
+  double time_to_best_s;  /* device clock, from the start of the first step      */
+  int64_t steps_done;     /* iterations run so far                               */
+  uint8_t* best_x;        /* caller-owned host buffer of n bytes, or NULL        */
+} pdbo_result;
+
+/* ---- QUBO (dense MFMA path or CSR persistent path) ------------------------ */
+
+/* Validates, canonicalises (Prop. 2.2) and uploads the instance, sets
+ * X^0 = x0 and Y^0 = y0 (Alg. 1 input), and returns a context.  EINVAL for any
+ * contract violation (checked before any HIP call); ERANGE when the exact
+ * int64 evaluation cannot be guaranteed (|Q_ij| >= 2^30, or a row of |A| or
+ * |c'| summing to 2^31 or more); EUNSUPPORTED for a CSR instance too large for
+ * the on-chip resident kernel.  `stream` is a hipStream_t (NULL = default). */
+PDBO_API pdbo_status qubo_gda_init(const pdbo_qubo* prob, const pdbo_params* par, void* stream,
+                          pdbo_ctx** out);
+
+/* Enqueues nsteps >= 0 iterations of Alg. 1 on the context's stream,
+ * asynchronously.  After each iteration t the rounded iterate of every
+ * restart is evaluated exactly and the incumbent updated. */
+PDBO_API pdbo_status qubo_gda_step(pdbo_ctx* ctx, int32_t nsteps);
+
+/* Synchronises the stream and reports the incumbent (result->best_x, if not
+ * NULL, receives n bytes). */
+PDBO_API pdbo_status qubo_gda_result(pdbo_ctx* ctx, pdbo_result* result);
+
+/* Copies the current iterate (x, y: host (B, n) float32, either may be NULL)
+ * and iteration count.  Synchronises. */
+PDBO_API pdbo_status qubo_gda_get_state(pdbo_ctx* ctx, float* x, float* y, int64_t* t);
+
+/* Replaces the iterate (host (B, n) float32, x in [0,1]) and the iteration
+ * count t >= 0; the incumbent is kept.  Synchronises. */
+PDBO_API pdbo_status qubo_gda_set_state(pdbo_ctx* ctx, const float* x, const float* y, int64_t t);
+
+/* Exact objectives (host int64[B]) of the rounded iterate evaluated last. */
+PDBO_API pdbo_status qubo_gda_objectives(pdbo_ctx* ctx, int64_t* F);
+
+/* Gradient of f/s, (A x + c')/s, at the host (B, n) float32 points x, written
+ * to the host (B, n) float32 array G, computed by the same GEMM (dense: same
+ * precision and tiles) that the step uses.  Does not change the iterate. */
+PDBO_API pdbo_status qubo_gda_grad(pdbo_ctx* ctx, const float* x, float* G);
+
+/* Exact objectives F (host int64[nb]) of nb host binary vectors xr (nb, n)
+ * bytes in {0,1}, nb <= B, through the step's evaluation kernels. */
+PDBO_API pdbo_status qubo_gda_eval(pdbo_ctx* ctx, const uint8_t* xr, int32_t nb, int64_t* F);
+
+/* init + step(T) + result + destroy. */
+PDBO_API pdbo_status qubo_gda_solve(const pdbo_qubo* prob, const pdbo_params* par, int32_t T,
+                           void* stream, pdbo_result* result);
+
+/* Many dense instances of uneven n stepped together: each iteration of all k
+ * instances is ONE grouped launch per kernel (grouped != 0) or k launches per
+ * kernel (grouped == 0), optionally captured in a hipGraph (par[0].graph_chunk).
+ * par[i] gives instance i's parameters; B, precision, g_kind and eval_every
+ * must agree across instances.  results[i] (with its own best_x) receives
+ * instance i's incumbent. */
+PDBO_API pdbo_status qubo_gda_batch_init(int32_t k, const pdbo_qubo* probs, const pdbo_params* par,
+                                int32_t grouped, void* stream, pdbo_ctx** out);
+PDBO_API pdbo_status qubo_gda_batch_result(pdbo_ctx* ctx, int32_t inst, pdbo_result* result);
+PDBO_API pdbo_status qubo_gda_batch_solve(int32_t k, const pdbo_qubo* probs, const pdbo_params* par,
+                                 int32_t T, int32_t grouped, void* stream, pdbo_result* results);
+
+/* ---- weighted MaxSAT (persistent, restart-resident kernel) ---------------- */
+
+/* Like qubo_gda_init for a MaxSAT formula; g_kind is usually PDBO_G_ENTROPY
+ * (the paper's choice for Max-k-SAT).  Step, result, get/set_state,
+ * objectives and grad use the qubo_gda_* entry points or the aliases below. */
+PDBO_API pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* par, void* stream,
+                            pdbo_ctx** out);
+PDBO_API pdbo_status maxsat_gda_step(pdbo_ctx* ctx, int32_t nsteps);
+PDBO_API pdbo_status maxsat_gda_result(pdbo_ctx* ctx, pdbo_result* result);
+PDBO_API pdbo_status maxsat_gda_solve(const pdbo_maxsat* prob, const pdbo_params* par, int32_t T,
+                             void* stream, pdbo_result* result);
+
+/* Lagrangian of a MaxSAT context for nb restarts given as DEVICE arrays:
+ * L[b] = f(x_b)/s + sum_i y_bi g(x_bi)  (Sec. 3.1; f as in Sec. 5.1).
+ * x, y: device (nb, n) float32 (x in [0,1]); L: device float32[nb].
+ * Enqueued on `stream` (hipStream_t); asynchronous. */
+PDBO_API pdbo_status maxsat_lagrangian_fwd(pdbo_ctx* ctx, const float* x, const float* y, int32_t nb,
+                                  float* L, void* stream);
+
+/* Adjoint of maxsat_lagrangian_fwd: given dL (device float32[nb]) writes
+ * dx = dL_b * (grad f(x_b)/s + y_b * g'(x_b)) and dy = dL_b * g(x_b) as device
+ * (nb, n) float32 arrays.  Deterministic (no atomics). */
+PDBO_API pdbo_status maxsat_lagrangian_bwd(pdbo_ctx* ctx, const float* x, const float* y,
+                                  const float* dL, int32_t nb, float* dx, float* dy,
+                                  void* stream);
+
+/* ---- instrumentation ------------------------------------------------------ */
+
+enum { PDBO_K_STEP = 0, PDBO_K_EVAL = 1, PDBO_K_ARGMIN = 2, PDBO_K_PERSISTENT = 3,
+       PDBO_K_COUNT = 4 };
+
+/* Enables (1) or disables (0) HIP-event timing of every kernel launch of the
+ * context, on the context's stream.  Clears the accumulated times. */
+PDBO_API pdbo_status pdbo_timing(pdbo_ctx* ctx, int32_t enable);
+
+/* Accumulated device time (ms) and launch count of kernel class `which`
+ * (PDBO_K_*) since timing was enabled.  Synchronises. */
+PDBO_API pdbo_status pdbo_kernel_time(pdbo_ctx* ctx, int32_t which, double* total_ms, int64_t* launches);
+
+/* Name of the tile configuration the dense path uses (static string). */
+PDBO_API const char* pdbo_tile_name(const pdbo_ctx* ctx);
+
+PDBO_API void pdbo_destroy(pdbo_ctx* ctx);
+PDBO_API const char* pdbo_status_str(pdbo_status s);
+PDBO_API const char* pdbo_last_error(const pdbo_ctx* ctx);
+PDBO_API const char* pdbo_last_global_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDBO_H */

@@ -1,0 +1,361 @@
+"""PDBO hot path on MI355X: Python binding of libpdbo (include/pdbo.h).
+
+The functions below carry the names of the C entry points and only marshal
+arguments (numpy arrays for host data, torch tensors for device data, the
+current torch stream); every step of Alg. 1 runs in the HIP kernels of the
+library.  There is no CPU path: a missing libpdbo.so raises on first use.
+
+Instances are duck-typed: a QUBO has ``n`` and either a dense int32 ``Q`` or CSR
+``row_ptr``/``col_idx``/``vals``, plus ``c`` (int64 or None); a MaxSAT formula
+has ``n``, ``lits`` (m, k) DIMACS int32 and ``w`` (m,) int32.  Parameters are a
+dict with B, alpha, beta, y0, delta, scale, g ("quad"/"entropy"), and
+optionally precision ("fp32"/"bf16"/"fp8"), eval_every, tile, graph_chunk.
+Starting points x0 are float64 arrays of shape (B, n).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _abi
+from ._abi import (PDBO_BF16, PDBO_CSR, PDBO_DENSE, PDBO_FP8, PDBO_FP32, PDBO_G_ENTROPY,
+                   PDBO_G_QUAD, PDBO_K_ARGMIN, PDBO_K_EVAL, PDBO_K_PERSISTENT, PDBO_K_STEP,
+                   PdboError, check, load)
+
+__all__ = [
+    "load", "PdboError", "Context", "qubo_gda_init", "qubo_gda_step", "qubo_gda_result",
+    "qubo_gda_get_state", "qubo_gda_set_state", "qubo_gda_objectives", "qubo_gda_grad",
+    "qubo_gda_eval", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
+    "qubo_gda_batch_solve", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
+    "maxsat_gda_solve", "maxsat_lagrangian_fwd", "maxsat_lagrangian_bwd", "MaxSATLagrangian",
+    "PDBO_FP32", "PDBO_BF16", "PDBO_FP8", "PDBO_K_STEP", "PDBO_K_EVAL", "PDBO_K_ARGMIN",
+    "PDBO_K_PERSISTENT",
+]
+
+_PREC = {"fp32": PDBO_FP32, "bf16": PDBO_BF16, "fp8": PDBO_FP8}
+_G = {"quad": PDBO_G_QUAD, "entropy": PDBO_G_ENTROPY}
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # torch without a GPU: the library uses the null stream
+        pass
+    return None
+
+
+class _Keep:
+    """Holds the numpy buffers a ctypes struct points into."""
+
+    def __init__(self):
+        self.bufs = []
+
+    def arr(self, a, dtype):
+        if a is None:
+            return None
+        b = np.ascontiguousarray(a, dtype=dtype)
+        self.bufs.append(b)
+        return b
+
+
+def _qubo_struct(q, keep: _Keep) -> _abi.pdbo_qubo:
+    s = _abi.pdbo_qubo()
+    s.n = int(q.n)
+    if getattr(q, "Q", None) is not None:
+        s.format = PDBO_DENSE
+        s.q = _ptr(keep.arr(q.Q, np.int32))
+        s.nnz = 0
+    else:
+        s.format = PDBO_CSR
+        s.row_ptr = _ptr(keep.arr(q.row_ptr, np.int32))
+        s.col_idx = _ptr(keep.arr(q.col_idx, np.int32))
+        s.q = _ptr(keep.arr(q.vals, np.int32))
+        s.nnz = int(len(q.col_idx))
+    c = getattr(q, "c", None)
+    s.c = _ptr(keep.arr(c, np.int64)) if c is not None else None
+    return s
+
+
+def _maxsat_struct(f, keep: _Keep) -> _abi.pdbo_maxsat:
+    s = _abi.pdbo_maxsat()
+    lits = keep.arr(f.lits, np.int32)
+    s.n, s.m, s.k = int(f.n), int(lits.shape[0]), int(lits.shape[1])
+    s.lits = _ptr(lits)
+    s.w = _ptr(keep.arr(f.w, np.int32)) if getattr(f, "w", None) is not None else None
+    return s
+
+
+def _params_struct(p: dict, x0, keep: _Keep) -> _abi.pdbo_params:
+    s = _abi.pdbo_params()
+    s.B = int(p["B"])
+    s.g_kind = _G[p.get("g", "quad")]
+    s.precision = _PREC[p.get("precision", "fp32")]
+    s.eval_every = int(p.get("eval_every", 1))
+    s.alpha, s.beta, s.y0 = float(p["alpha"]), float(p["beta"]), float(p["y0"])
+    s.delta, s.scale = float(p["delta"]), float(p.get("scale", 1.0))
+    s.tile = int(p.get("tile", 0))
+    s.graph_chunk = int(p.get("graph_chunk", 0))
+    s.x0 = _ptr(keep.arr(x0, np.float64)) if x0 is not None else None
+    return s
+
+
+def _result_dict(r: _abi.pdbo_result, best_x) -> dict:
+    return dict(best_obj=int(r.best_obj), best_restart=int(r.best_restart),
+                best_iter=int(r.best_iter), time_to_best_s=float(r.time_to_best_s),
+                steps_done=int(r.steps_done), best_x=best_x)
+
+
+class Context:
+    """Owner of a pdbo_ctx*; the methods call the entry points of the same name."""
+
+    def __init__(self, handle, n, B, kind, ninst=1, ns=None):
+        self.h = handle
+        self.n, self.B, self.kind, self.ninst = n, B, kind, ninst
+        self.ns = ns or [n]
+
+    def __del__(self):
+        self.destroy()
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            load().pdbo_destroy(self.h)
+            self.h = None
+
+    def step(self, nsteps):
+        return qubo_gda_step(self, nsteps)
+
+    def result(self):
+        return qubo_gda_result(self)
+
+    def get_state(self):
+        return qubo_gda_get_state(self)
+
+    def set_state(self, x=None, y=None, t=0):
+        return qubo_gda_set_state(self, x, y, t)
+
+    def objectives(self):
+        return qubo_gda_objectives(self)
+
+    def grad(self, x):
+        return qubo_gda_grad(self, x)
+
+    def eval(self, xr):
+        return qubo_gda_eval(self, xr)
+
+    def timing(self, enable=True):
+        check(load().pdbo_timing(self.h, int(bool(enable))), self.h)
+
+    def kernel_time(self, which):
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        check(load().pdbo_kernel_time(self.h, which, ctypes.byref(ms), ctypes.byref(cnt)), self.h)
+        return ms.value, cnt.value
+
+    @property
+    def tile_name(self):
+        return load().pdbo_tile_name(self.h).decode()
+
+
+def qubo_gda_init(q, params: dict, x0, stream=None) -> Context:
+    lib, keep = load(), _Keep()
+    prob = _qubo_struct(q, keep)
+    par = _params_struct(params, x0, keep)
+    h = ctypes.c_void_p()
+    st = lib.qubo_gda_init(ctypes.byref(prob), ctypes.byref(par),
+                           stream if stream is not None else _current_stream(), ctypes.byref(h))
+    check(st)
+    return Context(h, int(q.n), int(params["B"]), "qubo")
+
+
+def qubo_gda_step(ctx: Context, nsteps: int):
+    check(load().qubo_gda_step(ctx.h, int(nsteps)), ctx.h)
+
+
+def qubo_gda_result(ctx: Context) -> dict:
+    bx = np.zeros(ctx.n, dtype=np.uint8)
+    r = _abi.pdbo_result()
+    r.best_x = _ptr(bx)
+    check(load().qubo_gda_result(ctx.h, ctypes.byref(r)), ctx.h)
+    return _result_dict(r, bx)
+
+
+def qubo_gda_get_state(ctx: Context):
+    x = np.zeros((ctx.B, ctx.n), dtype=np.float32)
+    y = np.zeros((ctx.B, ctx.n), dtype=np.float32)
+    t = ctypes.c_int64()
+    check(load().qubo_gda_get_state(ctx.h, _ptr(x), _ptr(y), ctypes.byref(t)), ctx.h)
+    return x, y, t.value
+
+
+def qubo_gda_set_state(ctx: Context, x=None, y=None, t=0):
+    xa = None if x is None else np.ascontiguousarray(x, dtype=np.float32)
+    ya = None if y is None else np.ascontiguousarray(y, dtype=np.float32)
+    check(load().qubo_gda_set_state(ctx.h, _ptr(xa), _ptr(ya), int(t)), ctx.h)
+
+
+def qubo_gda_objectives(ctx: Context) -> np.ndarray:
+    F = np.zeros(ctx.B, dtype=np.int64)
+    check(load().qubo_gda_objectives(ctx.h, _ptr(F)), ctx.h)
+    return F
+
+
+def qubo_gda_grad(ctx: Context, x) -> np.ndarray:
+    xa = np.ascontiguousarray(x, dtype=np.float32)
+    G = np.zeros((ctx.B, ctx.n), dtype=np.float32)
+    check(load().qubo_gda_grad(ctx.h, _ptr(xa), _ptr(G)), ctx.h)
+    return G
+
+
+def qubo_gda_eval(ctx: Context, xr) -> np.ndarray:
+    xa = np.ascontiguousarray(xr, dtype=np.uint8)
+    xa = xa.reshape(-1, ctx.n)
+    F = np.zeros(xa.shape[0], dtype=np.int64)
+    check(load().qubo_gda_eval(ctx.h, _ptr(xa), int(xa.shape[0]), _ptr(F)), ctx.h)
+    return F
+
+
+def qubo_gda_solve(q, params: dict, x0, T: int, stream=None) -> dict:
+    lib, keep = load(), _Keep()
+    prob = _qubo_struct(q, keep)
+    par = _params_struct(params, x0, keep)
+    bx = np.zeros(int(q.n), dtype=np.uint8)
+    r = _abi.pdbo_result()
+    r.best_x = _ptr(bx)
+    check(lib.qubo_gda_solve(ctypes.byref(prob), ctypes.byref(par), int(T),
+                             stream if stream is not None else _current_stream(), ctypes.byref(r)))
+    return _result_dict(r, bx)
+
+
+def _batch_arrays(qs, params_list, x0s, keep):
+    k = len(qs)
+    probs = (_abi.pdbo_qubo * k)(*[_qubo_struct(q, keep) for q in qs])
+    pars = (_abi.pdbo_params * k)(*[_params_struct(p, x, keep) for p, x in zip(params_list, x0s)])
+    return k, probs, pars
+
+
+def qubo_gda_batch_init(qs, params_list, x0s, grouped=True, stream=None) -> Context:
+    lib, keep = load(), _Keep()
+    k, probs, pars = _batch_arrays(qs, params_list, x0s, keep)
+    h = ctypes.c_void_p()
+    check(lib.qubo_gda_batch_init(k, probs, pars, int(bool(grouped)),
+                                  stream if stream is not None else _current_stream(),
+                                  ctypes.byref(h)))
+    return Context(h, int(qs[0].n), int(params_list[0]["B"]), "batch", k, [int(q.n) for q in qs])
+
+
+def qubo_gda_batch_result(ctx: Context, inst: int) -> dict:
+    bx = np.zeros(ctx.ns[inst], dtype=np.uint8)
+    r = _abi.pdbo_result()
+    r.best_x = _ptr(bx)
+    check(load().qubo_gda_batch_result(ctx.h, int(inst), ctypes.byref(r)), ctx.h)
+    return _result_dict(r, bx)
+
+
+def qubo_gda_batch_solve(qs, params_list, x0s, T: int, grouped=True, stream=None) -> list:
+    lib, keep = load(), _Keep()
+    k, probs, pars = _batch_arrays(qs, params_list, x0s, keep)
+    bxs = [np.zeros(int(q.n), dtype=np.uint8) for q in qs]
+    res = (_abi.pdbo_result * k)()
+    for i in range(k):
+        res[i].best_x = _ptr(bxs[i])
+    check(lib.qubo_gda_batch_solve(k, probs, pars, int(T), int(bool(grouped)),
+                                   stream if stream is not None else _current_stream(), res))
+    return [_result_dict(res[i], bxs[i]) for i in range(k)]
+
+
+def maxsat_gda_init(f, params: dict, x0, stream=None) -> Context:
+    lib, keep = load(), _Keep()
+    prob = _maxsat_struct(f, keep)
+    par = _params_struct(params, x0, keep)
+    h = ctypes.c_void_p()
+    check(lib.maxsat_gda_init(ctypes.byref(prob), ctypes.byref(par),
+                              stream if stream is not None else _current_stream(), ctypes.byref(h)))
+    return Context(h, int(f.n), int(params["B"]), "maxsat")
+
+
+def maxsat_gda_step(ctx: Context, nsteps: int):
+    check(load().maxsat_gda_step(ctx.h, int(nsteps)), ctx.h)
+
+
+def maxsat_gda_result(ctx: Context) -> dict:
+    return qubo_gda_result(ctx)
+
+
+def maxsat_gda_solve(f, params: dict, x0, T: int, stream=None) -> dict:
+    lib, keep = load(), _Keep()
+    prob = _maxsat_struct(f, keep)
+    par = _params_struct(params, x0, keep)
+    bx = np.zeros(int(f.n), dtype=np.uint8)
+    r = _abi.pdbo_result()
+    r.best_x = _ptr(bx)
+    check(lib.maxsat_gda_solve(ctypes.byref(prob), ctypes.byref(par), int(T),
+                               stream if stream is not None else _current_stream(), ctypes.byref(r)))
+    return _result_dict(r, bx)
+
+
+def _dev_f32(t):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def maxsat_lagrangian_fwd(ctx: Context, x, y):
+    """L[b] = f(x_b)/s + sum_i y_bi g(x_bi) for (nb, n) float32 GPU tensors."""
+    import torch
+    L = torch.empty(x.shape[0], device=x.device, dtype=torch.float32)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+    check(load().maxsat_lagrangian_fwd(ctx.h, _dev_f32(x), _dev_f32(y), int(x.shape[0]),
+                                       _dev_f32(L), stream), ctx.h)
+    return L
+
+
+def maxsat_lagrangian_bwd(ctx: Context, x, y, dL):
+    import torch
+    dx = torch.empty_like(x)
+    dy = torch.empty_like(y)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+    check(load().maxsat_lagrangian_bwd(ctx.h, _dev_f32(x), _dev_f32(y), _dev_f32(dL),
+                                       int(x.shape[0]), _dev_f32(dx), _dev_f32(dy), stream), ctx.h)
+    return dx, dy
+
+
+def _autograd_class():
+    import torch
+
+    class _MaxSATLagrangian(torch.autograd.Function):
+        """L(x, y) of a MaxSAT context with the hand-written HIP adjoint as backward."""
+
+        @staticmethod
+        def forward(fctx, x, y, pctx):
+            x = x.contiguous()
+            y = y.contiguous()
+            fctx.save_for_backward(x, y)
+            fctx.pctx = pctx
+            return maxsat_lagrangian_fwd(pctx, x, y)
+
+        @staticmethod
+        def backward(fctx, dL):
+            x, y = fctx.saved_tensors
+            dx, dy = maxsat_lagrangian_bwd(fctx.pctx, x, y, dL.contiguous().float())
+            return dx, dy, None
+
+    return _MaxSATLagrangian
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def apply(self, x, y, pctx):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _autograd_class()
+        return _LazyAutograd._cls.apply(x, y, pctx)
+
+
+MaxSATLagrangian = _LazyAutograd()

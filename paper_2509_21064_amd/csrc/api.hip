@@ -1,0 +1,1324 @@
+// Host side of libpdbo: the extern "C" entry points declared in pdbo.h.
+//
+// Validation happens before any HIP call, so contract violations return
+// PDBO_EINVAL on any machine.  Canonicalisation follows Prop. 2.2: on binary
+// points x_i^2 = x_i, so the multilinear extension of x^T Q x + c^T x is
+// 1/2 x^T A x + c'^T x with A = offdiag(Q + Q^T) and c' = c + diag(Q).  A is
+// stored as Ahat = A / kappa with kappa = 2 when every entry of A is even (always
+// the case for a symmetric integer Q) and 1 otherwise, so the exact objective
+// is F = (kappa/2) x^T Ahat x + c'^T x and the gradient of f/s is
+// (kappa/s) Ahat x + c'/s.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace pdbo;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr int kTraceCap = 4096;
+constexpr int64_t kI64Max = LLONG_MAX;
+
+int roundup(int v, int a) { return (v + a - 1) / a * a; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Allocation counter for fault injection (PDBO_FAIL_ALLOC_AT=k fails the k-th
+// device allocation of the process with PDBO_ENOMEM).
+std::mutex g_alloc_mu;
+long g_alloc_count = 0;
+
+bool inject_alloc_failure() {
+  static long fail_at = [] {
+    const char* e = std::getenv("PDBO_FAIL_ALLOC_AT");
+    return e ? std::atol(e) : 0L;
+  }();
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  ++g_alloc_count;
+  return fail_at > 0 && g_alloc_count == fail_at;
+}
+
+}  // namespace
+
+struct TimedLaunch {
+  hipEvent_t a, b;
+  int cls;
+};
+
+struct pdbo_ctx {
+  int kind = 0;  // 0 dense (one or many instances), 1 CSR, 2 MaxSAT
+  hipStream_t stream = nullptr;
+  std::string err;
+  pdbo_params par{};
+  int B = 0, prec = 0, cfg = 0, eval_every = 1;
+  int64_t t_host = 0;
+  int parity = 0;
+  bool stamped = false;
+  std::vector<void*> allocs;
+  std::vector<int> n_of;  // n per instance
+  // dense
+  std::vector<InstDev> insts_h;
+  InstDev* insts_d = nullptr;
+  std::vector<TileDev> tiles_h;
+  TileDev* tiles_d = nullptr;
+  std::vector<int> tile_off, tile_cnt;
+  int grouped = 1;
+  InstDev* scratch_inst_d = nullptr;
+  float* gx_scratch = nullptr;     // fp32 x for grad()
+  uint8_t* gs_scratch = nullptr;   // shadow for grad()
+  float* g_scratch = nullptr;      // gradient out
+  int8_t* xr_scratch = nullptr;
+  int64_t *sp_scratch = nullptr, *cp_scratch = nullptr, *f_scratch = nullptr;
+  // graph
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream used only to record the graph
+  int graph_parity0 = -1;
+  // CSR / MaxSAT persistent
+  CsrDev csr{};
+  bool compact = false;
+  SatDev sat{};
+  Incumbent* inc_d = nullptr;
+  uint8_t* best_x_d = nullptr;
+  uint64_t* ts0_d = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  double ms[PDBO_K_COUNT] = {0, 0, 0, 0};
+  int64_t cnt[PDBO_K_COUNT] = {0, 0, 0, 0};
+};
+
+namespace {
+
+pdbo_status fail(pdbo_ctx* c, pdbo_status s, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  g_last_error = msg;
+  return s;
+}
+
+pdbo_status hipfail(pdbo_ctx* c, const char* what, hipError_t e) {
+  std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return fail(c, e == hipErrorOutOfMemory ? PDBO_ENOMEM : PDBO_EDEVICE, m);
+}
+
+#define HIPCHK(ctx, call)                              \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hipfail(ctx, #call, e_); \
+  } while (0)
+
+#define STCHK(call)                     \
+  do {                                  \
+    pdbo_status s_ = (call);            \
+    if (s_ != PDBO_OK) return s_;       \
+  } while (0)
+
+template <typename T>
+pdbo_status dalloc(pdbo_ctx* c, T** p, size_t count) {
+  *p = nullptr;
+  if (inject_alloc_failure()) return fail(c, PDBO_ENOMEM, "injected allocation failure");
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) return hipfail(c, "hipMalloc", e);
+  c->allocs.push_back(q);
+  e = hipMemsetAsync(q, 0, bytes, c->stream);
+  if (e != hipSuccess) return hipfail(c, "hipMemsetAsync", e);
+  *p = (T*)q;
+  return PDBO_OK;
+}
+
+void free_all(pdbo_ctx* c) {
+  if (!c) return;
+  if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+  for (auto& t : c->pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  c->pending.clear();
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+}
+
+// Temporary device buffer freed at scope exit (init-time uploads).
+struct TempDev {
+  void* p = nullptr;
+  ~TempDev() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+pdbo_status temp_upload(pdbo_ctx* c, TempDev& t, const void* host, size_t bytes) {
+  if (inject_alloc_failure()) return fail(c, PDBO_ENOMEM, "injected allocation failure");
+  hipError_t e = hipMalloc(&t.p, std::max<size_t>(bytes, 16));
+  if (e != hipSuccess) return hipfail(c, "hipMalloc", e);
+  if (bytes) {
+    e = hipMemcpyAsync(t.p, host, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hipfail(c, "hipMemcpyAsync", e);
+  }
+  return PDBO_OK;
+}
+
+// ---------------------------------------------------------------- validation
+
+pdbo_status check_params(const pdbo_params* p, int n, bool x0_required = true) {
+  if (!p) return fail(nullptr, PDBO_EINVAL, "params is NULL");
+  if (p->B < 1 || p->B > (1 << 20)) return fail(nullptr, PDBO_EINVAL, "B must be in [1, 2^20]");
+  if (!finite_pos(p->alpha) || !finite_pos(p->beta))
+    return fail(nullptr, PDBO_EINVAL, "alpha and beta must be finite and > 0");
+  if (!finite_pos(p->y0)) return fail(nullptr, PDBO_EINVAL, "y0 must be finite and > 0");
+  if (!finite_pos(p->scale)) return fail(nullptr, PDBO_EINVAL, "scale must be finite and > 0");
+  if (!(std::isfinite(p->delta) && p->delta > 0.0 && p->delta < 0.5))
+    return fail(nullptr, PDBO_EINVAL, "delta must be in (0, 1/2)");
+  if (p->g_kind != PDBO_G_QUAD && p->g_kind != PDBO_G_ENTROPY)
+    return fail(nullptr, PDBO_EINVAL, "unknown g_kind");
+  if (p->precision < PDBO_FP32 || p->precision > PDBO_FP8)
+    return fail(nullptr, PDBO_EINVAL, "unknown precision");
+  if (p->eval_every < 1) return fail(nullptr, PDBO_EINVAL, "eval_every must be >= 1");
+  if (p->graph_chunk < 0 || (p->graph_chunk & 1))
+    return fail(nullptr, PDBO_EINVAL, "graph_chunk must be 0 or a positive even number");
+  if (p->tile < 0 || p->tile > dense_num_cfgs())
+    return fail(nullptr, PDBO_EINVAL, "unknown tile configuration");
+  if (x0_required) {
+    if (!p->x0) return fail(nullptr, PDBO_EINVAL, "x0 is required");
+    const size_t tot = (size_t)p->B * (size_t)n;
+    for (size_t i = 0; i < tot; ++i) {
+      const double v = p->x0[i];
+      if (!(v >= 0.0 && v <= 1.0)) return fail(nullptr, PDBO_EINVAL, "x0 must lie in [0,1]");
+    }
+  }
+  return PDBO_OK;
+}
+
+pdbo_status check_qubo(const pdbo_qubo* q) {
+  if (!q) return fail(nullptr, PDBO_EINVAL, "problem is NULL");
+  if (q->n < 1 || q->n > 65536) return fail(nullptr, PDBO_EINVAL, "n must be in [1, 65536]");
+  const int n = q->n;
+  if (q->format == PDBO_DENSE) {
+    if (!q->q) return fail(nullptr, PDBO_EINVAL, "dense Q is NULL");
+    const size_t tot = (size_t)n * n;
+    for (size_t i = 0; i < tot; ++i)
+      if (q->q[i] >= (1 << 30) || q->q[i] <= -(1 << 30))
+        return fail(nullptr, PDBO_ERANGE, "|Q_ij| must be below 2^30");
+  } else if (q->format == PDBO_CSR) {
+    if (!q->row_ptr || (q->nnz > 0 && (!q->col_idx || !q->q)))
+      return fail(nullptr, PDBO_EINVAL, "CSR arrays are NULL");
+    if (q->nnz < 0 || q->nnz > (int64_t)INT_MAX) return fail(nullptr, PDBO_EINVAL, "bad nnz");
+    if (q->row_ptr[0] != 0 || (int64_t)q->row_ptr[n] != q->nnz)
+      return fail(nullptr, PDBO_EINVAL, "row_ptr must start at 0 and end at nnz");
+    for (int i = 0; i < n; ++i) {
+      if (q->row_ptr[i + 1] < q->row_ptr[i])
+        return fail(nullptr, PDBO_EINVAL, "row_ptr must be non-decreasing");
+      for (int p = q->row_ptr[i]; p < q->row_ptr[i + 1]; ++p) {
+        const int j = q->col_idx[p];
+        if (j < 0 || j >= n) return fail(nullptr, PDBO_EINVAL, "column index out of range");
+        if (p > q->row_ptr[i] && j <= q->col_idx[p - 1])
+          return fail(nullptr, PDBO_EINVAL, "columns of a row must be strictly increasing");
+        if (q->q[p] >= (1 << 30) || q->q[p] <= -(1 << 30))
+          return fail(nullptr, PDBO_ERANGE, "|Q_ij| must be below 2^30");
+      }
+    }
+  } else {
+    return fail(nullptr, PDBO_EINVAL, "unknown format");
+  }
+  if (q->c)
+    for (int i = 0; i < n; ++i)
+      if (q->c[i] >= (int64_t(1) << 40) || q->c[i] <= -(int64_t(1) << 40))
+        return fail(nullptr, PDBO_ERANGE, "|c_i| must be below 2^40");
+  return PDBO_OK;
+}
+
+// ---------------------------------------------------------------- canonical form
+
+struct DenseCanon {
+  int n = 0, kappa = 1;
+  std::vector<int32_t> Ahat;   // n*n
+  std::vector<int64_t> cp;     // n
+  int32_t amax = 0;
+  std::vector<float> rowmax;   // max_j |Ahat_ij|
+};
+
+pdbo_status canon_dense(const pdbo_qubo* q, DenseCanon& C) {
+  const int n = q->n;
+  C.n = n;
+  C.cp.assign(n, 0);
+  if (q->c)
+    for (int i = 0; i < n; ++i) C.cp[i] = q->c[i];
+  std::vector<int64_t> A;
+  try {
+    A.assign((size_t)n * n, 0);
+  } catch (...) {
+    return fail(nullptr, PDBO_ENOMEM, "host allocation failed");
+  }
+  if (q->format == PDBO_DENSE) {
+    constexpr int T = 64;
+    for (int i0 = 0; i0 < n; i0 += T)
+      for (int j0 = 0; j0 < n; j0 += T)
+        for (int i = i0; i < std::min(n, i0 + T); ++i)
+          for (int j = j0; j < std::min(n, j0 + T); ++j) {
+            const int64_t v = q->q[(size_t)i * n + j];
+            if (i == j)
+              C.cp[i] += v;
+            else {
+              A[(size_t)i * n + j] += v;
+              A[(size_t)j * n + i] += v;
+            }
+          }
+  } else {
+    for (int i = 0; i < n; ++i)
+      for (int p = q->row_ptr[i]; p < q->row_ptr[i + 1]; ++p) {
+        const int j = q->col_idx[p];
+        const int64_t v = q->q[p];
+        if (i == j)
+          C.cp[i] += v;
+        else {
+          A[(size_t)i * n + j] += v;
+          A[(size_t)j * n + i] += v;
+        }
+      }
+  }
+  bool even = true;
+  for (size_t k = 0; k < A.size() && even; ++k) even = (A[k] & 1) == 0;
+  C.kappa = even ? 2 : 1;
+  try {
+    C.Ahat.resize((size_t)n * n);
+  } catch (...) {
+    return fail(nullptr, PDBO_ENOMEM, "host allocation failed");
+  }
+  C.rowmax.assign(n, 0.f);
+  for (int i = 0; i < n; ++i) {
+    int64_t rs = 0;
+    int32_t rm = 0;
+    for (int j = 0; j < n; ++j) {
+      const int64_t v = A[(size_t)i * n + j] / C.kappa;
+      C.Ahat[(size_t)i * n + j] = (int32_t)v;
+      const int32_t av = (int32_t)(v < 0 ? -v : v);
+      rs += av;
+      rm = std::max(rm, av);
+    }
+    if (rs >= (int64_t(1) << 31)) return fail(nullptr, PDBO_ERANGE, "a row of |Ahat| sums to 2^31 or more");
+    C.rowmax[i] = (float)rm;
+    C.amax = std::max(C.amax, rm);
+  }
+  return PDBO_OK;
+}
+
+struct CsrCanon {
+  int n = 0, kappa = 1;
+  std::vector<int32_t> rp, col, val;
+  std::vector<int64_t> cp;
+  int32_t amax = 0;
+};
+
+pdbo_status canon_csr(const pdbo_qubo* q, CsrCanon& C) {
+  const int n = q->n;
+  C.n = n;
+  C.cp.assign(n, 0);
+  if (q->c)
+    for (int i = 0; i < n; ++i) C.cp[i] = q->c[i];
+  struct E {
+    int32_t i, j;
+    int64_t v;
+  };
+  std::vector<E> e;
+  e.reserve((size_t)q->nnz * 2);
+  for (int i = 0; i < n; ++i)
+    for (int p = q->row_ptr[i]; p < q->row_ptr[i + 1]; ++p) {
+      const int j = q->col_idx[p];
+      const int64_t v = q->q[p];
+      if (i == j) {
+        C.cp[i] += v;
+      } else {
+        e.push_back({i, j, v});
+        e.push_back({j, i, v});
+      }
+    }
+  std::sort(e.begin(), e.end(), [](const E& a, const E& b) { return a.i != b.i ? a.i < b.i : a.j < b.j; });
+  std::vector<E> m;
+  for (const E& x : e) {
+    if (!m.empty() && m.back().i == x.i && m.back().j == x.j)
+      m.back().v += x.v;
+    else
+      m.push_back(x);
+  }
+  bool even = true;
+  for (const E& x : m) even = even && ((x.v & 1) == 0);
+  C.kappa = even ? 2 : 1;
+  C.rp.assign(n + 1, 0);
+  std::vector<int64_t> rs(n, 0);
+  for (const E& x : m) {
+    const int64_t v = x.v / C.kappa;
+    if (v == 0) continue;
+    C.rp[x.i + 1]++;
+    C.col.push_back(x.j);
+    C.val.push_back((int32_t)v);
+    const int64_t av = v < 0 ? -v : v;
+    rs[x.i] += av;
+    C.amax = std::max<int32_t>(C.amax, (int32_t)av);
+  }
+  for (int i = 0; i < n; ++i) {
+    C.rp[i + 1] += C.rp[i];
+    if (rs[i] >= (int64_t(1) << 31)) return fail(nullptr, PDBO_ERANGE, "a row of |Ahat| sums to 2^31 or more");
+  }
+  return PDBO_OK;
+}
+
+GdaP make_gp(const pdbo_params* p) {
+  GdaP g;
+  g.alpha = (float)p->alpha;
+  g.beta = (float)p->beta;
+  g.delta = (float)p->delta;
+  g.gkind = p->g_kind;
+  return g;
+}
+
+int element_bytes(int prec) { return prec == PDBO_FP32 ? 4 : prec == PDBO_BF16 ? 2 : 1; }
+
+int default_cfg(int n, int B) {
+  // 0: 128x128, 1: 64x64
+  if (n <= 512 || B <= 64) return 1;
+  return 0;
+}
+
+// ---------------------------------------------------------------- timing
+
+void t_begin(pdbo_ctx* c, TimedLaunch& tl, int cls) {
+  tl.cls = -1;
+  if (!c->timing) return;
+  if (hipEventCreate(&tl.a) != hipSuccess) return;
+  if (hipEventCreate(&tl.b) != hipSuccess) {
+    (void)hipEventDestroy(tl.a);
+    return;
+  }
+  tl.cls = cls;
+  (void)hipEventRecord(tl.a, c->stream);
+}
+
+void t_end(pdbo_ctx* c, TimedLaunch& tl) {
+  if (tl.cls < 0) return;
+  (void)hipEventRecord(tl.b, c->stream);
+  c->pending.push_back(tl);
+}
+
+void t_collect(pdbo_ctx* c) {
+  for (auto& t : c->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      c->ms[t.cls] += ms;
+      c->cnt[t.cls] += 1;
+    }
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  c->pending.clear();
+}
+
+// ---------------------------------------------------------------- dense setup
+
+pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_params* p,
+                                 InstDev& I) {
+  const int n = C.n, B = p->B, prec = c->prec;
+  const int ld = roundup(n, kLdAlign);
+  const int EB = element_bytes(prec);
+  const TileCfgInfo& cf = dense_cfg(c->cfg);
+  std::memset(&I, 0, sizeof(I));
+  I.n = n;
+  I.ld = ld;
+  I.B = B;
+  I.mblocks = (n + cf.BM - 1) / cf.BM;
+  I.kappa = C.kappa;
+  I.kos = (float)((double)C.kappa / p->scale);
+  I.gp = make_gp(p);
+  I.trace_cap = kTraceCap;
+  if (C.amax > 127)
+    return fail(c, PDBO_EUNSUPPORTED,
+                "dense exact evaluation needs |Ahat_ij| <= 127 (int8 MFMA path)");
+
+  uint8_t* A = nullptr;
+  int8_t* A8 = nullptr;
+  float* rs = nullptr;
+  STCHK(dalloc(c, &A, (size_t)n * ld * EB));
+  STCHK(dalloc(c, &A8, (size_t)n * ld));
+  std::vector<float> hs(ld, 1.f);  // alive until the stream is synchronised below
+  if (prec == PDBO_FP8) {
+    for (int i = 0; i < n; ++i) hs[i] = C.rowmax[i] > 0.f ? C.rowmax[i] / 448.f : 1.f;
+    STCHK(dalloc(c, &rs, ld));
+    HIPCHK(c, hipMemcpyAsync(rs, hs.data(), ld * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  }
+  {
+    TempDev t;
+    STCHK(temp_upload(c, t, C.Ahat.data(), (size_t)n * n * sizeof(int32_t)));
+    HIPCHK(c, launch_quantize_A((const int32_t*)t.p, n, ld, prec, A, A8, rs, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  I.A = A;
+  I.A8 = A8;
+  I.rscale = rs;
+
+  std::vector<float> hcps(ld, 0.f);
+  std::vector<int64_t> hcp(ld, 0);
+  for (int i = 0; i < n; ++i) {
+    hcp[i] = C.cp[i];
+    hcps[i] = (float)((double)C.cp[i] / p->scale);
+  }
+  float* cps = nullptr;
+  int64_t* cpd = nullptr;
+  STCHK(dalloc(c, &cps, ld));
+  STCHK(dalloc(c, &cpd, ld));
+  HIPCHK(c, hipMemcpyAsync(cps, hcps.data(), ld * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(cpd, hcp.data(), ld * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  I.cps = cps;
+  I.cp = cpd;
+
+  const size_t sz = (size_t)B * ld;
+  STCHK(dalloc(c, &I.X[0], sz));
+  STCHK(dalloc(c, &I.X[1], sz));
+  STCHK(dalloc(c, &I.Y, sz));
+  if (prec == PDBO_FP32) {
+    I.Xs[0] = (uint8_t*)I.X[0];
+    I.Xs[1] = (uint8_t*)I.X[1];
+  } else {
+    STCHK(dalloc(c, &I.Xs[0], sz * EB));
+    STCHK(dalloc(c, &I.Xs[1], sz * EB));
+  }
+  STCHK(dalloc(c, &I.Xr, sz));
+  STCHK(dalloc(c, &I.Spart, (size_t)I.mblocks * B));
+  STCHK(dalloc(c, &I.Cpart, (size_t)I.mblocks * B));
+  STCHK(dalloc(c, &I.Fall, (size_t)B));
+  STCHK(dalloc(c, &I.inc, 1));
+  STCHK(dalloc(c, &I.best_x, (size_t)ld));
+  STCHK(dalloc(c, &I.trace, kTraceCap));
+  STCHK(dalloc(c, &I.trace_len, 1));
+  STCHK(dalloc(c, &I.t_dev, 1));
+  I.ts0 = c->ts0_d;
+  Incumbent init{kI64Max, -1, -1, 0};
+  HIPCHK(c, hipMemcpyAsync(I.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+  {
+    TempDev t;
+    STCHK(temp_upload(c, t, p->x0, (size_t)B * n * sizeof(double)));
+    HIPCHK(c, launch_init_state((const double*)t.p, B, n, ld, (float)p->y0, I.X[0], I.Y,
+                                prec == PDBO_FP32 ? nullptr : I.Xs[0], prec, I.Xr, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return PDBO_OK;
+}
+
+// Tile table: row groups (instance, m-block) are assigned round-robin to the
+// 8 XCDs (workgroup w of a launch runs on XCD w % 8) so that the column tiles
+// sharing one block of Ahat rows run on the same XCD, back to back, and reuse
+// that block from the XCD's L2.
+void build_tiles(pdbo_ctx* c) {
+  const TileCfgInfo& cf = dense_cfg(c->cfg);
+  c->tiles_h.clear();
+  c->tile_off.clear();
+  c->tile_cnt.clear();
+  for (size_t k = 0; k < c->insts_h.size(); ++k) {
+    const InstDev& I = c->insts_h[k];
+    const int nb = (I.B + cf.BN - 1) / cf.BN;
+    std::vector<std::vector<TileDev>> q(8);
+    for (int m = 0; m < I.mblocks; ++m)
+      for (int j = 0; j < nb; ++j) q[m % 8].push_back(TileDev{(int)k, m * cf.BM, j * cf.BN, m});
+    c->tile_off.push_back((int)c->tiles_h.size());
+    size_t longest = 0;
+    for (auto& v : q) longest = std::max(longest, v.size());
+    std::vector<TileDev> rest;
+    for (size_t r = 0; r < longest; ++r) {
+      bool full = true;
+      for (auto& v : q) full = full && r < v.size();
+      for (auto& v : q) {
+        if (r >= v.size()) continue;
+        if (full)
+          c->tiles_h.push_back(v[r]);
+        else
+          rest.push_back(v[r]);
+      }
+    }
+    c->tiles_h.insert(c->tiles_h.end(), rest.begin(), rest.end());
+    c->tile_cnt.push_back((int)c->tiles_h.size() - c->tile_off.back());
+  }
+}
+
+pdbo_status upload_dense_tables(pdbo_ctx* c) {
+  build_tiles(c);
+  STCHK(dalloc(c, &c->insts_d, c->insts_h.size()));
+  STCHK(dalloc(c, &c->tiles_d, c->tiles_h.size()));
+  HIPCHK(c, hipMemcpyAsync(c->insts_d, c->insts_h.data(), c->insts_h.size() * sizeof(InstDev),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->tiles_d, c->tiles_h.data(), c->tiles_h.size() * sizeof(TileDev),
+                           hipMemcpyHostToDevice, c->stream));
+  // set the dynamic LDS limit of every kernel this context launches, outside
+  // of any stream capture
+  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, nullptr, 0, nullptr, 0, 0, c->stream));
+  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_GRAD, nullptr, 0, nullptr, 0, 0, c->stream));
+  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, nullptr, 0, nullptr, 0, 0, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDBO_OK;
+}
+
+pdbo_status dense_one_step(pdbo_ctx* c) {
+  const bool do_eval = ((c->t_host + 1) % c->eval_every) == 0;
+  const int ninst = (int)c->insts_h.size();
+  TimedLaunch tl;
+  if (c->grouped) {
+    t_begin(c, tl, PDBO_K_STEP);
+    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->tiles_d, (int)c->tiles_h.size(),
+                                c->insts_d, c->parity, 0, c->stream));
+    t_end(c, tl);
+    if (do_eval) {
+      t_begin(c, tl, PDBO_K_EVAL);
+      HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, c->tiles_d, (int)c->tiles_h.size(),
+                                  c->insts_d, c->parity, 0, c->stream));
+      t_end(c, tl);
+    }
+    t_begin(c, tl, PDBO_K_ARGMIN);
+    HIPCHK(c, launch_argmin(c->insts_d, 0, ninst, do_eval ? 1 : 0, c->stream));
+    t_end(c, tl);
+  } else {
+    for (int k = 0; k < ninst; ++k) {
+      t_begin(c, tl, PDBO_K_STEP);
+      HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->tiles_d + c->tile_off[k],
+                                  c->tile_cnt[k], c->insts_d, c->parity, 0, c->stream));
+      t_end(c, tl);
+    }
+    if (do_eval)
+      for (int k = 0; k < ninst; ++k) {
+        t_begin(c, tl, PDBO_K_EVAL);
+        HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, c->tiles_d + c->tile_off[k],
+                                    c->tile_cnt[k], c->insts_d, c->parity, 0, c->stream));
+        t_end(c, tl);
+      }
+    for (int k = 0; k < ninst; ++k) {
+      t_begin(c, tl, PDBO_K_ARGMIN);
+      HIPCHK(c, launch_argmin(c->insts_d, k, 1, do_eval ? 1 : 0, c->stream));
+      t_end(c, tl);
+    }
+  }
+  c->parity ^= 1;
+  c->t_host += 1;
+  return PDBO_OK;
+}
+
+pdbo_status dense_steps(pdbo_ctx* c, int nsteps) {
+  const int K = c->par.graph_chunk;
+  const bool use_graph = K > 0 && c->eval_every == 1 && !c->timing;
+  int left = nsteps;
+  while (left > 0) {
+    if (use_graph && left >= K) {
+      if (!c->gexec) {
+        // The caller's stream may be the legacy default stream, which cannot
+        // be captured: record the K iterations on a private stream (nothing
+        // executes there) and launch the graph on the caller's stream.
+        if (!c->cap_stream)
+          HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const int64_t t_save = c->t_host;
+        const int par_save = c->parity;
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+          c->stream = user;
+          return hipfail(c, "hipStreamBeginCapture", e);
+        }
+        pdbo_status st = PDBO_OK;
+        for (int s = 0; s < K && st == PDBO_OK; ++s) st = dense_one_step(c);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->stream, &g);
+        c->stream = user;
+        c->t_host = t_save;
+        c->parity = par_save;
+        if (st != PDBO_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return st;
+        }
+        if (e != hipSuccess) return hipfail(c, "hipStreamEndCapture", e);
+        c->graph = g;
+        HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+        c->graph_parity0 = par_save;
+      }
+      if (c->parity != c->graph_parity0) {
+        STCHK(dense_one_step(c));
+        --left;
+        continue;
+      }
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      c->t_host += K;
+      left -= K;
+    } else {
+      STCHK(dense_one_step(c));
+      --left;
+    }
+  }
+  return PDBO_OK;
+}
+
+double clock_rate_hz() {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1e8;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return 1e8;
+  return (double)khz * 1e3;
+}
+
+pdbo_status fill_result(pdbo_ctx* c, const Incumbent* inc_d, const uint8_t* best_x_d, int n,
+                        pdbo_result* r) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  Incumbent inc;
+  uint64_t ts0 = 0;
+  HIPCHK(c, hipMemcpy(&inc, inc_d, sizeof(inc), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(&ts0, c->ts0_d, sizeof(ts0), hipMemcpyDeviceToHost));
+  r->steps_done = c->t_host;
+  if (inc.F == kI64Max) {
+    r->best_obj = 0;
+    r->best_restart = -1;
+    r->best_iter = -1;
+    r->time_to_best_s = 0.0;
+    return PDBO_OK;
+  }
+  r->best_obj = inc.F;
+  r->best_restart = (int32_t)inc.b;
+  r->best_iter = inc.t;
+  r->time_to_best_s = (inc.ts >= ts0 && ts0) ? (double)(inc.ts - ts0) / clock_rate_hz() : 0.0;
+  if (r->best_x) HIPCHK(c, hipMemcpy(r->best_x, best_x_d, (size_t)n, hipMemcpyDeviceToHost));
+  return PDBO_OK;
+}
+
+pdbo_status begin_ctx(pdbo_ctx* c, void* stream, const pdbo_params* p) {
+  c->stream = (hipStream_t)stream;
+  c->par = *p;
+  c->par.x0 = nullptr;
+  c->B = p->B;
+  c->prec = p->precision;
+  c->eval_every = p->eval_every;
+  STCHK(dalloc(c, &c->ts0_d, 1));
+  return PDBO_OK;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+
+extern "C" {
+
+const char* pdbo_status_str(pdbo_status s) {
+  switch (s) {
+    case PDBO_OK: return "ok";
+    case PDBO_EINVAL: return "invalid argument";
+    case PDBO_ENOMEM: return "out of memory";
+    case PDBO_EDEVICE: return "device error";
+    case PDBO_ERANGE: return "exactness guard failed";
+    case PDBO_ESTATE: return "invalid state";
+    case PDBO_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* pdbo_last_error(const pdbo_ctx* ctx) { return ctx ? ctx->err.c_str() : g_last_error.c_str(); }
+const char* pdbo_last_global_error(void) { return g_last_error.c_str(); }
+
+const char* pdbo_tile_name(const pdbo_ctx* ctx) {
+  if (!ctx || ctx->kind != 0) return "";
+  return dense_cfg(ctx->cfg).name;
+}
+
+void pdbo_destroy(pdbo_ctx* ctx) {
+  if (!ctx) return;
+  free_all(ctx);
+  delete ctx;
+}
+
+static pdbo_status dense_init(int k, const pdbo_qubo* probs, const pdbo_params* pars, int grouped,
+                              void* stream, pdbo_ctx** out) {
+  if (!out) return fail(nullptr, PDBO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (k < 1) return fail(nullptr, PDBO_EINVAL, "k must be >= 1");
+  if (!probs || !pars) return fail(nullptr, PDBO_EINVAL, "problem or params is NULL");
+  for (int i = 0; i < k; ++i) {
+    STCHK(check_qubo(&probs[i]));
+    STCHK(check_params(&pars[i], probs[i].n));
+    if (pars[i].B != pars[0].B || pars[i].precision != pars[0].precision ||
+        pars[i].g_kind != pars[0].g_kind || pars[i].eval_every != pars[0].eval_every)
+      return fail(nullptr, PDBO_EINVAL, "B, precision, g_kind and eval_every must agree");
+  }
+  pdbo_ctx* c = new pdbo_ctx();
+  c->kind = 0;
+  c->grouped = grouped ? 1 : 0;
+  pdbo_status st = begin_ctx(c, stream, &pars[0]);
+  if (st == PDBO_OK) {
+    if (pars[0].tile > 0) {
+      c->cfg = pars[0].tile - 1;
+    } else {
+      int nmax = 0;
+      for (int i = 0; i < k; ++i) nmax = std::max(nmax, probs[i].n);
+      c->cfg = default_cfg(nmax, pars[0].B);
+    }
+    c->insts_h.resize(k);
+    for (int i = 0; i < k && st == PDBO_OK; ++i) {
+      DenseCanon C;
+      st = canon_dense(&probs[i], C);
+      if (st == PDBO_OK) st = setup_dense_instance(c, C, &pars[i], c->insts_h[i]);
+      c->n_of.push_back(probs[i].n);
+    }
+  }
+  if (st == PDBO_OK) st = upload_dense_tables(c);
+  if (st != PDBO_OK) {
+    const std::string msg = c->err.empty() ? g_last_error : c->err;
+    pdbo_destroy(c);
+    g_last_error = msg;
+    return st;
+  }
+  *out = c;
+  return PDBO_OK;
+}
+
+static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stream, pdbo_ctx** out) {
+  if (p->eval_every != 1) return fail(nullptr, PDBO_EUNSUPPORTED, "the CSR path evaluates every iteration");
+  CsrCanon C;
+  STCHK(canon_csr(q, C));
+  const int n = q->n;
+  const bool compact = n <= 65536 && C.amax <= 127;
+  if (!csr_fits(n, (int64_t)C.col.size(), compact, nullptr))
+    return fail(nullptr, PDBO_EUNSUPPORTED, "instance too large for the restart-resident CSR kernel");
+  pdbo_ctx* c = new pdbo_ctx();
+  c->kind = 1;
+  c->compact = compact;
+  c->n_of.push_back(n);
+  pdbo_status st = begin_ctx(c, stream, p);
+  auto run = [&]() -> pdbo_status {
+    const int B = p->B, ld = roundup(n, kLdAlign);
+    const int64_t nnz = (int64_t)C.col.size();
+    CsrDev& d = c->csr;
+    std::memset(&d, 0, sizeof(d));
+    d.n = n;
+    d.ld = ld;
+    d.B = B;
+    d.kappa = C.kappa;
+    d.nnz = nnz;
+    d.kos = (float)((double)C.kappa / p->scale);
+    d.gp = make_gp(p);
+    int32_t* rp = nullptr;
+    STCHK(dalloc(c, &rp, n + 1));
+    HIPCHK(c, hipMemcpyAsync(rp, C.rp.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream));
+    d.row_ptr = rp;
+    // host staging lives until the stream is synchronised at the end of init
+    std::vector<uint16_t> cc;
+    std::vector<int8_t> vv;
+    if (compact) {
+      cc.assign(C.col.begin(), C.col.end());
+      vv.assign(C.val.begin(), C.val.end());
+      uint16_t* col = nullptr;
+      int8_t* val = nullptr;
+      STCHK(dalloc(c, &col, nnz));
+      STCHK(dalloc(c, &val, nnz));
+      HIPCHK(c, hipMemcpyAsync(col, cc.data(), nnz * 2, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(val, vv.data(), nnz, hipMemcpyHostToDevice, c->stream));
+      d.col = col;
+      d.val = val;
+    } else {
+      int32_t* col = nullptr;
+      int32_t* val = nullptr;
+      STCHK(dalloc(c, &col, nnz));
+      STCHK(dalloc(c, &val, nnz));
+      HIPCHK(c, hipMemcpyAsync(col, C.col.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(val, C.val.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
+      d.col = col;
+      d.val = val;
+    }
+    std::vector<float> hcps(ld, 0.f);
+    std::vector<int64_t> hcp(ld, 0);
+    for (int i = 0; i < n; ++i) {
+      hcp[i] = C.cp[i];
+      hcps[i] = (float)((double)C.cp[i] / p->scale);
+    }
+    float* cps = nullptr;
+    int64_t* cp = nullptr;
+    STCHK(dalloc(c, &cps, ld));
+    STCHK(dalloc(c, &cp, ld));
+    HIPCHK(c, hipMemcpyAsync(cps, hcps.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cp, hcp.data(), ld * 8, hipMemcpyHostToDevice, c->stream));
+    d.cps = cps;
+    d.cp = cp;
+    STCHK(dalloc(c, &d.X, (size_t)B * ld));
+    STCHK(dalloc(c, &d.Y, (size_t)B * ld));
+    STCHK(dalloc(c, &d.rbestF, B));
+    STCHK(dalloc(c, &d.rbestT, B));
+    STCHK(dalloc(c, &d.rbestTs, B));
+    STCHK(dalloc(c, &d.best_xr, (size_t)B * n));
+    STCHK(dalloc(c, &d.Flast, B));
+    STCHK(dalloc(c, &c->inc_d, 1));
+    STCHK(dalloc(c, &c->best_x_d, n));
+    HIPCHK(c, launch_fill_i64(d.rbestF, kI64Max, B, c->stream));
+    HIPCHK(c, launch_fill_i64(d.rbestT, kI64Max, B, c->stream));
+    Incumbent init{kI64Max, -1, -1, 0};
+    HIPCHK(c, hipMemcpyAsync(c->inc_d, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    TempDev t;
+    STCHK(temp_upload(c, t, p->x0, (size_t)B * n * sizeof(double)));
+    HIPCHK(c, launch_init_state((const double*)t.p, B, n, ld, (float)p->y0, d.X, d.Y, nullptr,
+                                P_F32, nullptr, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDBO_OK;
+  };
+  if (st == PDBO_OK) st = run();
+  if (st != PDBO_OK) {
+    const std::string msg = c->err.empty() ? g_last_error : c->err;
+    pdbo_destroy(c);
+    g_last_error = msg;
+    return st;
+  }
+  *out = c;
+  return PDBO_OK;
+}
+
+pdbo_status qubo_gda_init(const pdbo_qubo* prob, const pdbo_params* par, void* stream,
+                          pdbo_ctx** out) {
+  if (!out) return fail(nullptr, PDBO_EINVAL, "out is NULL");
+  *out = nullptr;
+  STCHK(check_qubo(prob));
+  STCHK(check_params(par, prob->n));
+  if (prob->format == PDBO_CSR) return csr_init(prob, par, stream, out);
+  return dense_init(1, prob, par, 1, stream, out);
+}
+
+pdbo_status qubo_gda_batch_init(int32_t k, const pdbo_qubo* probs, const pdbo_params* par,
+                                int32_t grouped, void* stream, pdbo_ctx** out) {
+  return dense_init(k, probs, par, grouped, stream, out);
+}
+
+pdbo_status qubo_gda_step(pdbo_ctx* c, int32_t nsteps) {
+  if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
+  if (nsteps < 0) return fail(c, PDBO_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return PDBO_OK;
+  if (!c->stamped) {
+    HIPCHK(c, launch_stamp(c->ts0_d, c->stream));
+    c->stamped = true;
+  }
+  if (c->kind == 0) return dense_steps(c, nsteps);
+  TimedLaunch tl;
+  t_begin(c, tl, PDBO_K_PERSISTENT);
+  if (c->kind == 1)
+    HIPCHK(c, launch_csr_persistent(c->csr, c->compact, c->t_host, nsteps, c->stream));
+  else
+    HIPCHK(c, launch_sat_persistent(c->sat, c->t_host, nsteps, c->stream));
+  t_end(c, tl);
+  c->t_host += nsteps;
+  return PDBO_OK;
+}
+
+pdbo_status qubo_gda_result(pdbo_ctx* c, pdbo_result* r) {
+  if (!c || !r) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (c->kind == 0) {
+    if (c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "use qubo_gda_batch_result");
+    return fill_result(c, c->insts_h[0].inc, c->insts_h[0].best_x, c->insts_h[0].n, r);
+  }
+  const int B = c->B;
+  const int n = c->n_of[0];
+  if (c->kind == 1)
+    HIPCHK(c, launch_restart_best(c->csr.rbestF, c->csr.rbestT, c->csr.rbestTs, c->csr.best_xr, B,
+                                  n, c->inc_d, c->best_x_d, c->stream));
+  else
+    HIPCHK(c, launch_restart_best(c->sat.rbestF, c->sat.rbestT, c->sat.rbestTs, c->sat.best_xr, B,
+                                  n, c->inc_d, c->best_x_d, c->stream));
+  return fill_result(c, c->inc_d, c->best_x_d, n, r);
+}
+
+pdbo_status qubo_gda_batch_result(pdbo_ctx* c, int32_t inst, pdbo_result* r) {
+  if (!c || !r) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (c->kind != 0 || inst < 0 || inst >= (int)c->insts_h.size())
+    return fail(c, PDBO_EINVAL, "instance index out of range");
+  return fill_result(c, c->insts_h[inst].inc, c->insts_h[inst].best_x, c->insts_h[inst].n, r);
+}
+
+static void state_ptrs(pdbo_ctx* c, float** X, float** Y, int* ld, int* n) {
+  if (c->kind == 0) {
+    InstDev& I = c->insts_h[0];
+    *X = I.X[c->parity];
+    *Y = I.Y;
+    *ld = I.ld;
+    *n = I.n;
+  } else if (c->kind == 1) {
+    *X = c->csr.X;
+    *Y = c->csr.Y;
+    *ld = c->csr.ld;
+    *n = c->csr.n;
+  } else {
+    *X = c->sat.X;
+    *Y = c->sat.Y;
+    *ld = c->sat.ld;
+    *n = c->sat.n;
+  }
+}
+
+pdbo_status qubo_gda_get_state(pdbo_ctx* c, float* x, float* y, int64_t* t) {
+  if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
+  if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  float *X, *Y;
+  int ld, n;
+  state_ptrs(c, &X, &Y, &ld, &n);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (x)
+    HIPCHK(c, hipMemcpy2D(x, n * sizeof(float), X, ld * sizeof(float), n * sizeof(float), c->B,
+                          hipMemcpyDeviceToHost));
+  if (y)
+    HIPCHK(c, hipMemcpy2D(y, n * sizeof(float), Y, ld * sizeof(float), n * sizeof(float), c->B,
+                          hipMemcpyDeviceToHost));
+  if (t) *t = c->t_host;
+  return PDBO_OK;
+}
+
+pdbo_status qubo_gda_set_state(pdbo_ctx* c, const float* x, const float* y, int64_t t) {
+  if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
+  if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (t < 0) return fail(c, PDBO_EINVAL, "t must be >= 0");
+  float *X, *Y;
+  int ld, n;
+  state_ptrs(c, &X, &Y, &ld, &n);
+  const size_t tot = (size_t)c->B * n;
+  if (x)
+    for (size_t i = 0; i < tot; ++i)
+      if (!(x[i] >= 0.f && x[i] <= 1.f)) return fail(c, PDBO_EINVAL, "x must lie in [0,1]");
+  if (y)
+    for (size_t i = 0; i < tot; ++i)
+      if (!std::isfinite(y[i])) return fail(c, PDBO_EINVAL, "y must be finite");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  TempDev tx, ty;
+  if (x) STCHK(temp_upload(c, tx, x, tot * sizeof(float)));
+  if (y) STCHK(temp_upload(c, ty, y, tot * sizeof(float)));
+  uint8_t* Xs = nullptr;
+  if (c->kind == 0 && c->prec != PDBO_FP32) Xs = c->insts_h[0].Xs[c->parity];
+  HIPCHK(c, launch_set_state((const float*)tx.p, (const float*)ty.p, c->B, n, ld, X, Y, Xs, c->prec,
+                             c->stream));
+  c->t_host = t;
+  if (c->kind == 0) HIPCHK(c, hipMemcpyAsync(c->insts_h[0].t_dev, &t, sizeof(t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDBO_OK;
+}
+
+pdbo_status qubo_gda_objectives(pdbo_ctx* c, int64_t* F) {
+  if (!c || !F) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  const int64_t* src = c->kind == 0 ? c->insts_h[0].Fall : c->kind == 1 ? c->csr.Flast : c->sat.Flast;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(F, src, c->B * sizeof(int64_t), hipMemcpyDeviceToHost));
+  return PDBO_OK;
+}
+
+static pdbo_status ensure_scratch(pdbo_ctx* c) {
+  if (c->g_scratch) return PDBO_OK;
+  int ld = 0;
+  if (c->kind == 0)
+    ld = c->insts_h[0].ld;
+  else if (c->kind == 1)
+    ld = c->csr.ld;
+  else
+    ld = c->sat.ld;
+  const size_t sz = (size_t)c->B * ld;
+  STCHK(dalloc(c, &c->g_scratch, sz));
+  STCHK(dalloc(c, &c->gx_scratch, sz));
+  STCHK(dalloc(c, &c->xr_scratch, sz));
+  STCHK(dalloc(c, &c->f_scratch, c->B));
+  if (c->kind == 0) {
+    STCHK(dalloc(c, &c->gs_scratch, sz * element_bytes(c->prec)));
+    STCHK(dalloc(c, &c->sp_scratch, (size_t)c->insts_h[0].mblocks * c->B));
+    STCHK(dalloc(c, &c->cp_scratch, (size_t)c->insts_h[0].mblocks * c->B));
+    STCHK(dalloc(c, &c->scratch_inst_d, 1));
+  }
+  return PDBO_OK;
+}
+
+pdbo_status qubo_gda_grad(pdbo_ctx* c, const float* x, float* G) {
+  if (!c || !x || !G) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  STCHK(ensure_scratch(c));
+  int n = c->n_of[0];
+  const size_t tot = (size_t)c->B * n;
+  for (size_t i = 0; i < tot; ++i)
+    if (!(x[i] >= 0.f && x[i] <= 1.f)) return fail(c, PDBO_EINVAL, "x must lie in [0,1]");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  TempDev tx;
+  STCHK(temp_upload(c, tx, x, tot * sizeof(float)));
+  int ld;
+  if (c->kind == 0) {
+    InstDev I = c->insts_h[0];
+    ld = I.ld;
+    uint8_t* Xs = c->prec == PDBO_FP32 ? (uint8_t*)c->gx_scratch : c->gs_scratch;
+    HIPCHK(c, launch_set_state((const float*)tx.p, nullptr, c->B, n, ld, c->gx_scratch, nullptr,
+                               c->prec == PDBO_FP32 ? nullptr : Xs, c->prec, c->stream));
+    I.Xs[0] = I.Xs[1] = Xs;
+    I.G = c->g_scratch;
+    HIPCHK(c, hipMemcpyAsync(c->scratch_inst_d, &I, sizeof(I), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_GRAD, c->tiles_d, (int)c->tiles_h.size(),
+                                c->scratch_inst_d, 0, 0, c->stream));
+  } else if (c->kind == 1) {
+    ld = c->csr.ld;
+    HIPCHK(c, launch_set_state((const float*)tx.p, nullptr, c->B, n, ld, c->gx_scratch, nullptr,
+                               nullptr, P_F32, c->stream));
+    HIPCHK(c, launch_csr_grad(c->csr, c->compact, c->gx_scratch, c->g_scratch, c->B, c->stream));
+  } else {
+    ld = c->sat.ld;
+    HIPCHK(c, launch_set_state((const float*)tx.p, nullptr, c->B, n, ld, c->gx_scratch, nullptr,
+                               nullptr, P_F32, c->stream));
+    HIPCHK(c, launch_sat_grad(c->sat, c->gx_scratch, ld, c->g_scratch, c->B, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy2D(G, n * sizeof(float), c->g_scratch, ld * sizeof(float), n * sizeof(float),
+                        c->B, hipMemcpyDeviceToHost));
+  return PDBO_OK;
+}
+
+pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F) {
+  if (!c || !xr || !F) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (nb < 1 || nb > c->B) return fail(c, PDBO_EINVAL, "nb must be in [1, B]");
+  const int n = c->n_of[0];
+  for (size_t i = 0; i < (size_t)nb * n; ++i)
+    if (xr[i] > 1) return fail(c, PDBO_EINVAL, "xr must be 0/1 bytes");
+  STCHK(ensure_scratch(c));
+  const int ld = c->kind == 0 ? c->insts_h[0].ld : c->kind == 1 ? c->csr.ld : c->sat.ld;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemsetAsync(c->xr_scratch, 0, (size_t)c->B * ld, c->stream));
+  HIPCHK(c, hipMemcpy2DAsync(c->xr_scratch, ld, xr, n, n, nb, hipMemcpyHostToDevice, c->stream));
+  if (c->kind == 0) {
+    InstDev I = c->insts_h[0];
+    I.Xr = c->xr_scratch;
+    I.Spart = c->sp_scratch;
+    I.Cpart = c->cp_scratch;
+    I.Fall = c->f_scratch;
+    I.B = nb;
+    HIPCHK(c, hipMemcpyAsync(c->scratch_inst_d, &I, sizeof(I), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, c->tiles_d, (int)c->tiles_h.size(),
+                                c->scratch_inst_d, 0, 0, c->stream));
+    HIPCHK(c, launch_argmin(c->scratch_inst_d, 0, 1, 2, c->stream));
+  } else if (c->kind == 1) {
+    HIPCHK(c, launch_csr_eval(c->csr, c->compact, c->xr_scratch, nb, c->f_scratch, c->stream));
+  } else {
+    HIPCHK(c, launch_sat_eval(c->sat, c->xr_scratch, nb, c->f_scratch, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(F, c->f_scratch, nb * sizeof(int64_t), hipMemcpyDeviceToHost));
+  return PDBO_OK;
+}
+
+pdbo_status qubo_gda_solve(const pdbo_qubo* prob, const pdbo_params* par, int32_t T, void* stream,
+                           pdbo_result* result) {
+  if (T < 0 || !result) return fail(nullptr, PDBO_EINVAL, "T must be >= 0 and result non-NULL");
+  pdbo_ctx* c = nullptr;
+  STCHK(qubo_gda_init(prob, par, stream, &c));
+  pdbo_status st = qubo_gda_step(c, T);
+  if (st == PDBO_OK) st = qubo_gda_result(c, result);
+  if (st != PDBO_OK) g_last_error = c->err;
+  pdbo_destroy(c);
+  return st;
+}
+
+pdbo_status qubo_gda_batch_solve(int32_t k, const pdbo_qubo* probs, const pdbo_params* par,
+                                 int32_t T, int32_t grouped, void* stream, pdbo_result* results) {
+  if (T < 0 || !results) return fail(nullptr, PDBO_EINVAL, "T must be >= 0 and results non-NULL");
+  pdbo_ctx* c = nullptr;
+  STCHK(qubo_gda_batch_init(k, probs, par, grouped, stream, &c));
+  pdbo_status st = qubo_gda_step(c, T);
+  for (int i = 0; i < k && st == PDBO_OK; ++i) st = qubo_gda_batch_result(c, i, &results[i]);
+  if (st != PDBO_OK) g_last_error = c->err;
+  pdbo_destroy(c);
+  return st;
+}
+
+// ---------------------------------------------------------------- MaxSAT
+
+static pdbo_status check_maxsat(const pdbo_maxsat* s) {
+  if (!s) return fail(nullptr, PDBO_EINVAL, "problem is NULL");
+  if (s->n < 1 || s->n > (1 << 24)) return fail(nullptr, PDBO_EINVAL, "n must be in [1, 2^24]");
+  if (s->m < 1) return fail(nullptr, PDBO_EINVAL, "m must be >= 1");
+  if (s->k < 1 || s->k > 16) return fail(nullptr, PDBO_EINVAL, "k must be in [1, 16]");
+  if (!s->lits) return fail(nullptr, PDBO_EINVAL, "lits is NULL");
+  for (int j = 0; j < s->m; ++j) {
+    for (int l = 0; l < s->k; ++l) {
+      const int32_t v = s->lits[(size_t)j * s->k + l];
+      if (v == 0 || v > s->n || v < -s->n)
+        return fail(nullptr, PDBO_EINVAL, "literal out of range (DIMACS 1..n with sign)");
+      for (int l2 = 0; l2 < l; ++l2) {
+        const int32_t u = s->lits[(size_t)j * s->k + l2];
+        if ((u < 0 ? -u : u) == (v < 0 ? -v : v))
+          return fail(nullptr, PDBO_EINVAL, "a clause repeats a variable");
+      }
+    }
+    if (s->w && (s->w[j] < 0 || s->w[j] >= (1 << 24)))
+      return fail(nullptr, PDBO_EINVAL, "clause weights must be in [0, 2^24)");
+  }
+  return PDBO_OK;
+}
+
+pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void* stream,
+                            pdbo_ctx** out) {
+  if (!out) return fail(nullptr, PDBO_EINVAL, "out is NULL");
+  *out = nullptr;
+  STCHK(check_maxsat(prob));
+  STCHK(check_params(p, prob->n));
+  if (p->eval_every != 1) return fail(nullptr, PDBO_EUNSUPPORTED, "the MaxSAT path evaluates every iteration");
+  const int n = prob->n, m = prob->m, k = prob->k;
+  if (!sat_fits(n, nullptr))
+    return fail(nullptr, PDBO_EUNSUPPORTED, "n too large for the restart-resident MaxSAT kernel");
+  // literal codes and the variable-major occurrence lists
+  std::vector<int32_t> codes((size_t)m * k), wv(m);
+  std::vector<int32_t> ptr(n + 1, 0);
+  for (int j = 0; j < m; ++j) {
+    wv[j] = prob->w ? prob->w[j] : 1;
+    for (int l = 0; l < k; ++l) {
+      const int32_t v = prob->lits[(size_t)j * k + l];
+      const int32_t var = (v < 0 ? -v : v) - 1;
+      codes[(size_t)j * k + l] = (int32_t)((uint32_t)var | (v < 0 ? 0x80000000u : 0u));
+      ptr[var + 1]++;
+    }
+  }
+  for (int i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  std::vector<int32_t> inc((size_t)ptr[n] * k);
+  std::vector<int32_t> fillp(ptr.begin(), ptr.end() - 1);
+  for (int j = 0; j < m; ++j)
+    for (int l = 0; l < k; ++l) {
+      const int32_t code = codes[(size_t)j * k + l];
+      const int var = code & 0x7fffffff;
+      const int e = fillp[var]++;
+      int o = 0;
+      for (int l2 = 0; l2 < k; ++l2)
+        if (l2 != l) inc[(size_t)e * k + o++] = codes[(size_t)j * k + l2];
+      const int32_t meta = wv[j] | ((code < 0 ? 1 : 0) << 30) | ((l == 0 ? 1 : 0) << 29);
+      inc[(size_t)e * k + (k - 1)] = meta;
+    }
+
+  pdbo_ctx* c = new pdbo_ctx();
+  c->kind = 2;
+  c->n_of.push_back(n);
+  pdbo_status st = begin_ctx(c, stream, p);
+  auto run = [&]() -> pdbo_status {
+    const int B = p->B, ld = roundup(n, kLdAlign);
+    SatDev& d = c->sat;
+    std::memset(&d, 0, sizeof(d));
+    d.n = n;
+    d.m = m;
+    d.k = k;
+    d.ld = ld;
+    d.B = B;
+    d.ios = (float)(1.0 / p->scale);
+    d.gp = make_gp(p);
+    int32_t *dp = nullptr, *di = nullptr, *dl = nullptr, *dw = nullptr;
+    STCHK(dalloc(c, &dp, n + 1));
+    STCHK(dalloc(c, &di, inc.size()));
+    STCHK(dalloc(c, &dl, codes.size()));
+    STCHK(dalloc(c, &dw, m));
+    HIPCHK(c, hipMemcpyAsync(dp, ptr.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(di, inc.data(), inc.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dl, codes.data(), codes.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dw, wv.data(), m * 4, hipMemcpyHostToDevice, c->stream));
+    d.inc_ptr = dp;
+    d.inc = di;
+    d.lits = dl;
+    d.w = dw;
+    STCHK(dalloc(c, &d.X, (size_t)B * ld));
+    STCHK(dalloc(c, &d.Y, (size_t)B * ld));
+    STCHK(dalloc(c, &d.rbestF, B));
+    STCHK(dalloc(c, &d.rbestT, B));
+    STCHK(dalloc(c, &d.rbestTs, B));
+    STCHK(dalloc(c, &d.best_xr, (size_t)B * n));
+    STCHK(dalloc(c, &d.Flast, B));
+    STCHK(dalloc(c, &c->inc_d, 1));
+    STCHK(dalloc(c, &c->best_x_d, n));
+    HIPCHK(c, launch_fill_i64(d.rbestF, kI64Max, B, c->stream));
+    HIPCHK(c, launch_fill_i64(d.rbestT, kI64Max, B, c->stream));
+    Incumbent init{kI64Max, -1, -1, 0};
+    HIPCHK(c, hipMemcpyAsync(c->inc_d, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    TempDev t;
+    STCHK(temp_upload(c, t, p->x0, (size_t)B * n * sizeof(double)));
+    HIPCHK(c, launch_init_state((const double*)t.p, B, n, ld, (float)p->y0, d.X, d.Y, nullptr,
+                                P_F32, nullptr, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDBO_OK;
+  };
+  if (st == PDBO_OK) st = run();
+  if (st != PDBO_OK) {
+    const std::string msg = c->err.empty() ? g_last_error : c->err;
+    pdbo_destroy(c);
+    g_last_error = msg;
+    return st;
+  }
+  *out = c;
+  return PDBO_OK;
+}
+
+pdbo_status maxsat_gda_step(pdbo_ctx* c, int32_t nsteps) {
+  if (!c || c->kind != 2) return fail(c, PDBO_ESTATE, "not a MaxSAT context");
+  return qubo_gda_step(c, nsteps);
+}
+
+pdbo_status maxsat_gda_result(pdbo_ctx* c, pdbo_result* r) {
+  if (!c || c->kind != 2) return fail(c, PDBO_ESTATE, "not a MaxSAT context");
+  return qubo_gda_result(c, r);
+}
+
+pdbo_status maxsat_gda_solve(const pdbo_maxsat* prob, const pdbo_params* par, int32_t T,
+                             void* stream, pdbo_result* result) {
+  if (T < 0 || !result) return fail(nullptr, PDBO_EINVAL, "T must be >= 0 and result non-NULL");
+  pdbo_ctx* c = nullptr;
+  STCHK(maxsat_gda_init(prob, par, stream, &c));
+  pdbo_status st = qubo_gda_step(c, T);
+  if (st == PDBO_OK) st = qubo_gda_result(c, result);
+  if (st != PDBO_OK) g_last_error = c->err;
+  pdbo_destroy(c);
+  return st;
+}
+
+pdbo_status maxsat_lagrangian_fwd(pdbo_ctx* c, const float* x, const float* y, int32_t nb,
+                                  float* L, void* stream) {
+  if (!c || c->kind != 2) return fail(c, PDBO_ESTATE, "not a MaxSAT context");
+  if (!x || !y || !L || nb < 1) return fail(c, PDBO_EINVAL, "bad arguments");
+  HIPCHK(c, launch_sat_fwd(c->sat, x, y, nb, L, (hipStream_t)stream));
+  return PDBO_OK;
+}
+
+pdbo_status maxsat_lagrangian_bwd(pdbo_ctx* c, const float* x, const float* y, const float* dL,
+                                  int32_t nb, float* dx, float* dy, void* stream) {
+  if (!c || c->kind != 2) return fail(c, PDBO_ESTATE, "not a MaxSAT context");
+  if (!x || !y || !dL || !dx || !dy || nb < 1) return fail(c, PDBO_EINVAL, "bad arguments");
+  HIPCHK(c, launch_sat_bwd(c->sat, x, y, dL, nb, dx, dy, (hipStream_t)stream));
+  return PDBO_OK;
+}
+
+// ---------------------------------------------------------------- timing
+
+pdbo_status pdbo_timing(pdbo_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  t_collect(c);
+  for (int k = 0; k < PDBO_K_COUNT; ++k) {
+    c->ms[k] = 0.0;
+    c->cnt[k] = 0;
+  }
+  c->timing = enable != 0;
+  return PDBO_OK;
+}
+
+pdbo_status pdbo_kernel_time(pdbo_ctx* c, int32_t which, double* total_ms, int64_t* launches) {
+  if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
+  if (which < 0 || which >= PDBO_K_COUNT || !total_ms || !launches)
+    return fail(c, PDBO_EINVAL, "bad arguments");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  t_collect(c);
+  *total_ms = c->ms[which];
+  *launches = c->cnt[which];
+  return PDBO_OK;
+}
+
+}  // extern "C"

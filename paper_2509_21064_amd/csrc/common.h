@@ -1,0 +1,196 @@
+// Internal declarations shared by the HIP translation units of libpdbo.
+//
+// Layout in HBM (all per-restart arrays are restart-major):
+//   X[2], Y      float32 [B][ld]   ping-pong primal iterate, dual iterate
+//   Xs[2]        GEMM shadow of X in the operand type (bf16 / e4m3) [B][ld]
+//   Xr           int8 {0,1} [B][ld] rounded iterate [x > 1/2]
+//   A            canonical Ahat = offdiag(Q + Q^T)/kappa in the operand type,
+//                n rows x ld columns (columns n..ld-1 are zero)
+//   A8           the same matrix as exact int8 (evaluation operand)
+// ld is n rounded up to a multiple of 128 elements, so every row of every
+// operand is a whole number of 128-byte K chunks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pdbo.h"
+
+namespace pdbo {
+
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2, P_I8 = 3 };
+enum Epi { EPI_STEP = 0, EPI_GRAD = 1, EPI_EVAL = 2 };
+
+constexpr int kLdAlign = 128;        // elements
+constexpr float kEntropyEps = 9.5367431640625e-07f;  // 2^-20
+
+struct Incumbent {
+  int64_t F;        // INT64_MAX when empty
+  int64_t t;        // iteration (1-based)
+  int64_t b;        // restart
+  uint64_t ts;      // device wall clock at the improvement
+};
+
+struct TraceRec {
+  int64_t t;
+  int64_t F;
+  int64_t b;
+  uint64_t ts;
+};
+
+// Alg. 1 step-size parameters, kernel-argument sized.
+struct GdaP {
+  float alpha, beta, delta;
+  int gkind;        // 0 quadratic, 1 entropy
+};
+
+// One dense instance as seen by the kernels.
+struct InstDev {
+  const uint8_t* A;       // Ahat in the GEMM operand type
+  const int8_t* A8;       // Ahat as int8 (evaluation)
+  const float* rscale;    // e4m3 row scale (FP8 form), else nullptr
+  const float* cps;       // c'/s, padded to ld with zeros
+  const int64_t* cp;      // c', padded to ld with zeros
+  float* X[2];
+  float* Y;
+  uint8_t* Xs[2];         // shadows; for FP32 these alias X
+  int8_t* Xr;
+  float* G;               // gradient output of the GRAD epilogue
+  int64_t* Spart;         // [mblocks][B] partial x_r^T Ahat x_r
+  int64_t* Cpart;         // [mblocks][B] partial c'^T x_r
+  int64_t* Fall;          // [B] objectives of the last evaluation
+  Incumbent* inc;
+  uint8_t* best_x;        // [n]
+  TraceRec* trace;
+  int32_t* trace_len;
+  int64_t* t_dev;         // completed iterations
+  uint64_t* ts0;          // clock at the first step
+  int n, ld, B, mblocks;
+  int kappa, trace_cap;
+  float kos;              // kappa / s
+  GdaP gp;
+};
+
+struct TileDev {
+  int inst, m0, n0, mblk;
+};
+
+// ---- device helpers -------------------------------------------------------
+
+__device__ __forceinline__ float g_value(float x, int gkind) {
+  if (gkind == 0) return x * x - x;
+  float a = x > 0.f ? x * logf(x) : 0.f;
+  float b = x < 1.f ? (1.f - x) * logf(1.f - x) : 0.f;
+  return a + b;
+}
+
+__device__ __forceinline__ float g_deriv(float x, int gkind) {
+  if (gkind == 0) return 2.f * x - 1.f;
+  float xc = fminf(fmaxf(x, kEntropyEps), 1.f - kEntropyEps);
+  return logf(xc) - logf(1.f - xc);
+}
+
+// One coordinate of Alg. 1: perturbation test, projected primal step and dual
+// ascent with g evaluated at the old x (simultaneous update, Eq. 5).
+__device__ __forceinline__ void gda_update(float x, float y, float G, const GdaP& p,
+                                           float& xn, float& yn) {
+  float dL = fmaf(y, g_deriv(x, p.gkind), G);
+  bool pert = (fabsf(x - 0.5f) <= p.delta) && (fabsf(dL) <= 2.f * p.delta) && (y <= 0.f);
+  float xs = fminf(fmaxf(fmaf(-p.alpha, dL, x), 0.f), 1.f);
+  float xp = x <= 0.5f ? 0.5f - p.delta : 0.5f + p.delta;
+  xn = pert ? xp : xs;
+  yn = fmaf(p.beta, g_value(x, p.gkind), y);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_memrealtime(); }
+
+// ---- launchers (dense.hip) --------------------------------------------------
+
+struct TileCfgInfo {
+  const char* name;
+  int BM, BN, threads;
+};
+int dense_num_cfgs();
+const TileCfgInfo& dense_cfg(int id);
+
+hipError_t launch_dense_gemm(int cfg, int prec, int epi, const TileDev* tiles, int ntiles,
+                             const InstDev* insts, int parity, int grid, hipStream_t s);
+hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, hipStream_t s);
+hipError_t launch_stamp(uint64_t* ts0, hipStream_t s);
+hipError_t launch_init_state(const double* x0, int B, int n, int ld, float y0, float* X,
+                             float* Y, uint8_t* Xs, int xs_prec, int8_t* Xr, hipStream_t s);
+hipError_t launch_set_state(const float* x, const float* y, int B, int n, int ld, float* X,
+                            float* Y, uint8_t* Xs, int xs_prec, hipStream_t s);
+hipError_t launch_quantize_A(const int32_t* Ahat, int n, int ld, int prec, uint8_t* A,
+                             int8_t* A8, const float* rscale, hipStream_t s);
+hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t cnt, hipStream_t s);
+
+// ---- launchers (sparse.hip) -------------------------------------------------
+
+struct CsrDev {
+  const int32_t* row_ptr;
+  const void* col;        // uint16 or int32
+  const void* val;        // int8 or int32
+  const float* cps;
+  const int64_t* cp;
+  float* X;               // [B][ld]
+  float* Y;
+  int64_t* rbestF;        // [B]
+  int64_t* rbestT;
+  uint64_t* rbestTs;
+  uint8_t* best_xr;       // [B][n]
+  int64_t* Flast;         // [B]
+  int64_t nnz;
+  int n, ld, B, kappa;
+  float kos;
+  GdaP gp;
+};
+bool csr_fits(int n, int64_t nnz, bool compact, size_t* lds_bytes);
+hipError_t launch_csr_persistent(const CsrDev& d, bool compact, int64_t t0, int nsteps,
+                                 hipStream_t s);
+hipError_t launch_csr_grad(const CsrDev& d, bool compact, const float* X, float* G, int nb,
+                           hipStream_t s);
+hipError_t launch_csr_eval(const CsrDev& d, bool compact, const int8_t* xr, int nb, int64_t* F,
+                           hipStream_t s);
+
+// Reduction of per-restart bests to the incumbent (persistent paths).
+hipError_t launch_restart_best(const int64_t* rbestF, const int64_t* rbestT,
+                               const uint64_t* rbestTs, const uint8_t* best_xr, int B, int n,
+                               Incumbent* inc, uint8_t* best_x, hipStream_t s);
+
+// ---- launchers (maxsat.hip) -------------------------------------------------
+
+struct SatDev {
+  const int32_t* inc_ptr;   // [n+1] per-variable incidence ranges
+  const int32_t* inc;       // entries of k int32: (k-1) other literal codes, then meta
+  const int32_t* lits;      // [m][k] literal codes (var | neg<<31)
+  const int32_t* w;         // [m]
+  float* X;                 // [B][ld]
+  float* Y;
+  int64_t* rbestF;
+  int64_t* rbestT;
+  uint64_t* rbestTs;
+  uint8_t* best_xr;
+  int64_t* Flast;
+  int n, m, k, ld, B;
+  float ios;                // 1/s
+  GdaP gp;
+};
+bool sat_fits(int n, size_t* lds_bytes);
+hipError_t launch_sat_persistent(const SatDev& d, int64_t t0, int nsteps, hipStream_t s);
+hipError_t launch_sat_grad(const SatDev& d, const float* X, int ldx, float* G, int nb,
+                           hipStream_t s);
+hipError_t launch_sat_eval(const SatDev& d, const int8_t* xr, int nb, int64_t* F,
+                           hipStream_t s);
+hipError_t launch_sat_fwd(const SatDev& d, const float* x, const float* y, int nb, float* L,
+                          hipStream_t s);
+hipError_t launch_sat_bwd(const SatDev& d, const float* x, const float* y, const float* dL,
+                          int nb, float* dx, float* dy, hipStream_t s);
+
+}  // namespace pdbo

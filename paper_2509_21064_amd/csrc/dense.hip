@@ -1,0 +1,556 @@
+// Dense QUBO path: one MFMA GEMM kernel family for gfx950.
+//
+//   EPI_STEP : G = (kappa/s) * Ahat . X + c'/s, then Alg. 1 for every (i, b) in
+//              the tile, in registers (perturbation, projection, dual ascent),
+//              writing X^{t+1}, Y^{t+1}, the operand shadow of X^{t+1} and the
+//              rounded iterate [x^{t+1} > 1/2].
+//   EPI_GRAD : G only (tests and autotuning).
+//   EPI_EVAL : E = Ahat . Xr in int8 x int8 -> int32, reduced on the fly to
+//              per-tile partials of x_r^T Ahat x_r and c'^T x_r (int64).
+//
+// Operands are both K-contiguous: row i of Ahat (Ahat is symmetric) and row b
+// of the restart-major shadow.  Every K step consumes one 128-byte chunk of
+// each row, whatever the element type, so a lane always reads 32 bytes per
+// 16-row fragment: row (lane % 16), bytes [32*(lane/16), +32) of the chunk.
+// The same lane->k mapping is used for both operands, which is all the MFMA
+// dot product needs.  Output layout of the 16x16 MFMA: lane holds rows
+// 4*(lane/16)+r, r = 0..3, of column lane % 16.
+#include <climits>
+
+#include "common.h"
+
+namespace pdbo {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int P> struct PT;
+template <> struct PT<P_F32> { static constexpr int EB = 4; using Acc = f32x4; };
+template <> struct PT<P_BF16> { static constexpr int EB = 2; using Acc = f32x4; };
+template <> struct PT<P_FP8> { static constexpr int EB = 1; using Acc = f32x4; };
+template <> struct PT<P_I8> { static constexpr int EB = 1; using Acc = i32x4; };
+
+// One 128-byte K chunk of a 16x16 output fragment.
+template <int P>
+__device__ __forceinline__ void mfma_chunk(typename PT<P>::Acc& c, const u32x4 (&a)[2],
+                                           const u32x4 (&b)[2]);
+
+template <>
+__device__ __forceinline__ void mfma_chunk<P_F32>(f32x4& c, const u32x4 (&a)[2],
+                                                  const u32x4 (&b)[2]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[h][s]),
+                                               __uint_as_float(b[h][s]), c, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ void mfma_chunk<P_BF16>(f32x4& c, const u32x4 (&a)[2],
+                                                   const u32x4 (&b)[2]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[h]),
+                                                __builtin_bit_cast(bf16x8, b[h]), c, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ void mfma_chunk<P_FP8>(f32x4& c, const u32x4 (&a)[2],
+                                                  const u32x4 (&b)[2]) {
+  i32x8 av = {(int)a[0][0], (int)a[0][1], (int)a[0][2], (int)a[0][3],
+              (int)a[1][0], (int)a[1][1], (int)a[1][2], (int)a[1][3]};
+  i32x8 bv = {(int)b[0][0], (int)b[0][1], (int)b[0][2], (int)b[0][3],
+              (int)b[1][0], (int)b[1][1], (int)b[1][2], (int)b[1][3]};
+  // format 0 = e4m3 for both operands; E8M0 scales of 2^0
+  c = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 0, 0, 0, 0x7f7f7f7f, 0,
+                                                       0x7f7f7f7f);
+}
+
+template <>
+__device__ __forceinline__ void mfma_chunk<P_I8>(i32x4& c, const u32x4 (&a)[2],
+                                                 const u32x4 (&b)[2]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    c = __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i32x4, a[h]),
+                                              __builtin_bit_cast(i32x4, b[h]), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  return (uint32_t)w;
+}
+
+constexpr int kRow = 144;  // LDS bytes per operand row: one 128-byte chunk + 16 pad
+
+template <int BM, int BN>
+constexpr int gemm_lds_bytes() {
+  return 2 * (BM + BN) * kRow;
+}
+
+template <int BM, int BN, int WM, int WN, int P, int EPI>
+__global__ void __launch_bounds__(64 * WM * WN)
+    dense_gemm(const TileDev* __restrict__ tiles, int ntiles, const InstDev* __restrict__ insts,
+               int parity) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int WTM = BM / WM, WTN = BN / WN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int STAGE = (BM + BN) * kRow;
+  constexpr int APC = BM * 8 / NT, BPC = BN * 8 / NT;
+  constexpr int EB = PT<P>::EB;
+  static_assert((BM * 8) % NT == 0 && (BN * 8) % NT == 0, "tile / thread mismatch");
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be whole fragments");
+  using Acc = typename PT<P>::Acc;
+
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  __shared__ int64_t red[(EPI == EPI_EVAL) ? 2 * WM * BN : 1];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wm = wid % WM, wn = wid / WM;
+
+  for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    const TileDev td = tiles[w];
+    const InstDev& I = insts[td.inst];
+    const int n = I.n, ld = I.ld, B = I.B;
+    const size_t rbytes = (size_t)ld * EB;
+    const int nk = (int)(rbytes / 128);
+    const uint8_t* Ag = (EPI == EPI_EVAL) ? (const uint8_t*)I.A8 : I.A;
+    const uint8_t* Bg = (EPI == EPI_EVAL) ? (const uint8_t*)I.Xr : I.Xs[parity];
+
+    const uint8_t* pa[APC];
+    const uint8_t* pb[BPC];
+    int la[APC], lb[BPC];
+#pragma unroll
+    for (int j = 0; j < APC; ++j) {
+      const int p = tid + j * NT, r = p >> 3, c = p & 7;
+      const int row = min(td.m0 + r, n - 1);
+      pa[j] = Ag + (size_t)row * rbytes + c * 16;
+      la[j] = r * kRow + c * 16;
+    }
+#pragma unroll
+    for (int j = 0; j < BPC; ++j) {
+      const int p = tid + j * NT, r = p >> 3, c = p & 7;
+      const int row = min(td.n0 + r, B - 1);
+      pb[j] = Bg + (size_t)row * rbytes + c * 16;
+      lb[j] = (BM + r) * kRow + c * 16;
+    }
+
+    Acc acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+    u32x4 ra[APC], rb[BPC];
+#pragma unroll
+    for (int j = 0; j < APC; ++j) ra[j] = *(const u32x4*)(pa[j]);
+#pragma unroll
+    for (int j = 0; j < BPC; ++j) rb[j] = *(const u32x4*)(pb[j]);
+#pragma unroll
+    for (int j = 0; j < APC; ++j) *(u32x4*)(smem + la[j]) = ra[j];
+#pragma unroll
+    for (int j = 0; j < BPC; ++j) *(u32x4*)(smem + lb[j]) = rb[j];
+    __syncthreads();
+
+    const int frow = (lane & 15) * kRow + (lane >> 4) * 32;
+    for (int kc = 0; kc < nk; ++kc) {
+      const int cur = kc & 1;
+      const bool more = kc + 1 < nk;
+      if (more) {
+        const size_t off = (size_t)(kc + 1) * 128;
+#pragma unroll
+        for (int j = 0; j < APC; ++j) ra[j] = *(const u32x4*)(pa[j] + off);
+#pragma unroll
+        for (int j = 0; j < BPC; ++j) rb[j] = *(const u32x4*)(pb[j] + off);
+      }
+      const uint8_t* sA = smem + cur * STAGE + (wm * WTM) * kRow + frow;
+      const uint8_t* sB = smem + cur * STAGE + (BM + wn * WTN) * kRow + frow;
+      u32x4 fa[FM][2], fb[FN][2];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        fa[i][0] = *(const u32x4*)(sA + i * 16 * kRow);
+        fa[i][1] = *(const u32x4*)(sA + i * 16 * kRow + 16);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        fb[j][0] = *(const u32x4*)(sB + j * 16 * kRow);
+        fb[j][1] = *(const u32x4*)(sB + j * 16 * kRow + 16);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) mfma_chunk<P>(acc[i][j], fa[i], fb[j]);
+      if (more) {
+        uint8_t* nxt = smem + (cur ^ 1) * STAGE;
+#pragma unroll
+        for (int j = 0; j < APC; ++j) *(u32x4*)(nxt + la[j]) = ra[j];
+#pragma unroll
+        for (int j = 0; j < BPC; ++j) *(u32x4*)(nxt + lb[j]) = rb[j];
+      }
+      __syncthreads();
+    }
+
+    // ---------------------------------------------------------------- epilogue
+    const int ibase = td.m0 + wm * WTM + 4 * (lane >> 4);
+    const int bbase = td.n0 + wn * WTN + (lane & 15);
+    if constexpr (EPI == EPI_STEP || EPI == EPI_GRAD) {
+      const float kos = I.kos;
+      const GdaP gp = I.gp;
+      float* Xc = I.X[parity];
+      float* Xn = I.X[parity ^ 1];
+      float* Yp = I.Y;
+      uint8_t* Xsn = I.Xs[parity ^ 1];
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) {
+        const int i = ibase + fm * 16;
+        if (i >= n) continue;
+        const f32x4 cs = *(const f32x4*)(I.cps + i);
+        f32x4 sc = {kos, kos, kos, kos};
+        if constexpr (P == P_FP8) sc = sc * *(const f32x4*)(I.rscale + i);
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+          const int b = bbase + fn * 16;
+          if (b >= B) continue;
+          const size_t off = (size_t)b * ld + i;
+          f32x4 G;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) G[r] = fmaf(acc[fm][fn][r], sc[r], cs[r]);
+          if constexpr (EPI == EPI_GRAD) {
+            *(f32x4*)(I.G + off) = G;
+          } else {
+            const f32x4 xv = *(const f32x4*)(Xc + off);
+            const f32x4 yv = *(const f32x4*)(Yp + off);
+            f32x4 xo, yo;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              float a, c;
+              gda_update(xv[r], yv[r], G[r], gp, a, c);
+              xo[r] = a;
+              yo[r] = c;
+            }
+            *(f32x4*)(Xn + off) = xo;
+            *(f32x4*)(Yp + off) = yo;
+            const uint32_t xr = (uint32_t)(xo[0] > 0.5f) | ((uint32_t)(xo[1] > 0.5f) << 8) |
+                                ((uint32_t)(xo[2] > 0.5f) << 16) |
+                                ((uint32_t)(xo[3] > 0.5f) << 24);
+            *(uint32_t*)(I.Xr + off) = xr;
+            if constexpr (P == P_BF16) {
+              uint2 v;
+              v.x = (uint32_t)f32_to_bf16_rne(xo[0]) | ((uint32_t)f32_to_bf16_rne(xo[1]) << 16);
+              v.y = (uint32_t)f32_to_bf16_rne(xo[2]) | ((uint32_t)f32_to_bf16_rne(xo[3]) << 16);
+              *(uint2*)(Xsn + off * 2) = v;
+            } else if constexpr (P == P_FP8) {
+              *(uint32_t*)(Xsn + off) = pack_fp8x4(xo[0], xo[1], xo[2], xo[3]);
+            }
+          }
+        }
+      }
+    } else {
+      int64_t sS[FN], sC[FN];
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn) sS[fn] = sC[fn] = 0;
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) {
+        const int i = ibase + fm * 16;
+        if (i >= n) continue;
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+          const int b = bbase + fn * 16;
+          if (b >= B) continue;
+          const uint32_t xr = *(const uint32_t*)(I.Xr + (size_t)b * ld + i);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (((xr >> (8 * r)) & 1u) && (i + r < n)) {
+              sS[fn] += acc[fm][fn][r];
+              sC[fn] += I.cp[i + r];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn) {
+        sS[fn] += __shfl_xor(sS[fn], 16);
+        sS[fn] += __shfl_xor(sS[fn], 32);
+        sC[fn] += __shfl_xor(sC[fn], 16);
+        sC[fn] += __shfl_xor(sC[fn], 32);
+        if (lane < 16) {
+          const int col = wn * WTN + fn * 16 + lane;
+          red[(wm * BN + col) * 2 + 0] = sS[fn];
+          red[(wm * BN + col) * 2 + 1] = sC[fn];
+        }
+      }
+      __syncthreads();
+      for (int col = tid; col < BN; col += NT) {
+        const int b = td.n0 + col;
+        if (b < B) {
+          int64_t S = 0, C = 0;
+#pragma unroll
+          for (int q = 0; q < WM; ++q) {
+            S += red[(q * BN + col) * 2 + 0];
+            C += red[(q * BN + col) * 2 + 1];
+          }
+          I.Spart[(size_t)td.mblk * B + b] = S;
+          I.Cpart[(size_t)td.mblk * B + b] = C;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- tile table
+
+#define PDBO_TILE_CFGS(X)      \
+  X(0, 128, 128, 2, 2)         \
+  X(1, 64, 64, 2, 2)           \
+  X(2, 256, 128, 4, 2)         \
+  X(3, 128, 256, 2, 4)
+
+static const TileCfgInfo kCfgs[] = {
+#define X(id, bm, bn, wm, wn) {#bm "x" #bn "_w" #wm "x" #wn, bm, bn, 64 * wm * wn},
+    PDBO_TILE_CFGS(X)
+#undef X
+};
+
+int dense_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
+const TileCfgInfo& dense_cfg(int id) { return kCfgs[id]; }
+
+template <int BM, int BN, int WM, int WN, int P, int EPI>
+static hipError_t launch_one(const TileDev* tiles, int ntiles, const InstDev* insts, int parity,
+                             int grid, hipStream_t s) {
+  constexpr int lds = gemm_lds_bytes<BM, BN>();
+  auto kern = dense_gemm<BM, BN, WM, WN, P, EPI>;
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  if (grid <= 0 || grid > ntiles) grid = ntiles;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds, s, tiles, ntiles, insts, parity);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int WM, int WN>
+static hipError_t launch_cfg(int prec, int epi, const TileDev* tiles, int ntiles,
+                             const InstDev* insts, int parity, int grid, hipStream_t s) {
+  if (epi == EPI_EVAL)
+    return launch_one<BM, BN, WM, WN, P_I8, EPI_EVAL>(tiles, ntiles, insts, parity, grid, s);
+  switch (prec * 2 + epi) {
+    case P_F32 * 2 + EPI_STEP:
+      return launch_one<BM, BN, WM, WN, P_F32, EPI_STEP>(tiles, ntiles, insts, parity, grid, s);
+    case P_F32 * 2 + EPI_GRAD:
+      return launch_one<BM, BN, WM, WN, P_F32, EPI_GRAD>(tiles, ntiles, insts, parity, grid, s);
+    case P_BF16 * 2 + EPI_STEP:
+      return launch_one<BM, BN, WM, WN, P_BF16, EPI_STEP>(tiles, ntiles, insts, parity, grid, s);
+    case P_BF16 * 2 + EPI_GRAD:
+      return launch_one<BM, BN, WM, WN, P_BF16, EPI_GRAD>(tiles, ntiles, insts, parity, grid, s);
+    case P_FP8 * 2 + EPI_STEP:
+      return launch_one<BM, BN, WM, WN, P_FP8, EPI_STEP>(tiles, ntiles, insts, parity, grid, s);
+    case P_FP8 * 2 + EPI_GRAD:
+      return launch_one<BM, BN, WM, WN, P_FP8, EPI_GRAD>(tiles, ntiles, insts, parity, grid, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_dense_gemm(int cfg, int prec, int epi, const TileDev* tiles, int ntiles,
+                             const InstDev* insts, int parity, int grid, hipStream_t s) {
+  switch (cfg) {
+#define X(id, bm, bn, wm, wn) \
+  case id:                    \
+    return launch_cfg<bm, bn, wm, wn>(prec, epi, tiles, ntiles, insts, parity, grid, s);
+    PDBO_TILE_CFGS(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------- best of B
+
+// One workgroup per instance: F_b = (kappa * S_b) / 2 + C_b from the tile
+// partials (fixed summation order), first argmin over b, strict-improvement
+// update of the incumbent, copy of the winning rounded column.
+// mode 0: no evaluation this iteration (only the iteration counter advances);
+// mode 1: evaluation and incumbent update; mode 2: objectives only.
+__global__ void __launch_bounds__(256)
+    argmin_kernel(const InstDev* __restrict__ insts, int inst0, int mode) {
+  const int do_eval = mode != 0;
+  const InstDev& I = insts[inst0 + blockIdx.x];
+  __shared__ int64_t sF[256];
+  __shared__ int sb[256];
+  __shared__ int improved;
+  const int tid = threadIdx.x;
+  const int64_t t = *I.t_dev + 1;
+  if (do_eval) {
+    int64_t bestF = LLONG_MAX;
+    int bestb = INT_MAX;
+    for (int b = tid; b < I.B; b += 256) {
+      int64_t S = 0, C = 0;
+      for (int mb = 0; mb < I.mblocks; ++mb) {
+        S += I.Spart[(size_t)mb * I.B + b];
+        C += I.Cpart[(size_t)mb * I.B + b];
+      }
+      const int64_t F = (I.kappa == 2 ? S : S / 2) + C;
+      I.Fall[b] = F;
+      if (F < bestF) {
+        bestF = F;
+        bestb = b;
+      }
+    }
+    sF[tid] = bestF;
+    sb[tid] = bestb;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) {
+        const int64_t f2 = sF[tid + h];
+        const int b2 = sb[tid + h];
+        if (f2 < sF[tid] || (f2 == sF[tid] && b2 < sb[tid])) {
+          sF[tid] = f2;
+          sb[tid] = b2;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      improved = 0;
+      if (mode == 1 && sF[0] < I.inc->F) {
+        const uint64_t ts = wall_clock();
+        I.inc->F = sF[0];
+        I.inc->t = t;
+        I.inc->b = sb[0];
+        I.inc->ts = ts;
+        const int k = *I.trace_len;
+        if (k < I.trace_cap) {
+          I.trace[k] = TraceRec{t, sF[0], (int64_t)sb[0], ts};
+          *I.trace_len = k + 1;
+        }
+        improved = 1;
+      }
+    }
+    __syncthreads();
+    if (improved) {
+      const int8_t* src = I.Xr + (size_t)sb[0] * I.ld;
+      for (int i = tid; i < I.n; i += 256) I.best_x[i] = (uint8_t)src[i];
+    }
+  }
+  if (tid == 0 && mode != 2) *I.t_dev = t;
+}
+
+hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(argmin_kernel, dim3(ninst), dim3(256), 0, s, insts, inst0, mode);
+  return hipGetLastError();
+}
+
+__global__ void stamp_kernel(uint64_t* ts0) {
+  if (*ts0 == 0) *ts0 = wall_clock();
+}
+
+hipError_t launch_stamp(uint64_t* ts0, hipStream_t s) {
+  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(1), 0, s, ts0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- state
+
+__device__ __forceinline__ void store_shadow(uint8_t* Xs, size_t off, float v, int prec) {
+  if (!Xs) return;
+  if (prec == P_BF16) {
+    ((uint16_t*)Xs)[off] = f32_to_bf16_rne(v);
+  } else if (prec == P_FP8) {
+    Xs[off] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xff);
+  }
+}
+
+__global__ void init_state_kernel(const double* __restrict__ x0, int B, int n, int ld, float y0,
+                                  float* X, float* Y, uint8_t* Xs, int prec, int8_t* Xr) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)B * n) return;
+  const int b = (int)(idx / n), i = (int)(idx % n);
+  const size_t off = (size_t)b * ld + i;
+  const float x = (float)x0[idx];
+  X[off] = x;
+  Y[off] = y0;
+  store_shadow(Xs, off, x, prec);
+  if (Xr) Xr[off] = (int8_t)(x > 0.5f);
+}
+
+hipError_t launch_init_state(const double* x0, int B, int n, int ld, float y0, float* X,
+                             float* Y, uint8_t* Xs, int xs_prec, int8_t* Xr, hipStream_t s) {
+  const size_t tot = (size_t)B * n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(init_state_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x0,
+                     B, n, ld, y0, X, Y, Xs, xs_prec, Xr);
+  return hipGetLastError();
+}
+
+__global__ void set_state_kernel(const float* __restrict__ x, const float* __restrict__ y, int B,
+                                 int n, int ld, float* X, float* Y, uint8_t* Xs, int prec) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)B * n) return;
+  const int b = (int)(idx / n), i = (int)(idx % n);
+  const size_t off = (size_t)b * ld + i;
+  if (x) {
+    X[off] = x[idx];
+    store_shadow(Xs, off, x[idx], prec);
+  }
+  if (y) Y[off] = y[idx];
+}
+
+hipError_t launch_set_state(const float* x, const float* y, int B, int n, int ld, float* X,
+                            float* Y, uint8_t* Xs, int xs_prec, hipStream_t s) {
+  const size_t tot = (size_t)B * n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(set_state_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, y,
+                     B, n, ld, X, Y, Xs, xs_prec);
+  return hipGetLastError();
+}
+
+// Ahat (int32, n x n) -> operand copy (n x ld, zero padded) and the int8 copy.
+__global__ void quantize_A_kernel(const int32_t* __restrict__ Ah, int n, int ld, int prec,
+                                  uint8_t* A, int8_t* A8, const float* __restrict__ rscale) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * ld) return;
+  const int i = (int)(idx / ld), k = (int)(idx % ld);
+  const int32_t v = k < n ? Ah[(size_t)i * n + k] : 0;
+  if (A8) A8[idx] = (int8_t)v;
+  if (!A) return;
+  if (prec == P_F32) {
+    ((float*)A)[idx] = (float)v;
+  } else if (prec == P_BF16) {
+    ((uint16_t*)A)[idx] = f32_to_bf16_rne((float)v);
+  } else if (prec == P_FP8) {
+    const float q = (float)v / rscale[i];
+    A[idx] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(q, 0.f, 0, false) & 0xff);
+  }
+}
+
+hipError_t launch_quantize_A(const int32_t* Ahat, int n, int ld, int prec, uint8_t* A,
+                             int8_t* A8, const float* rscale, hipStream_t s) {
+  const size_t tot = (size_t)n * ld;
+  hipLaunchKernelGGL(quantize_A_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Ahat,
+                     n, ld, prec, A, A8, rscale);
+  return hipGetLastError();
+}
+
+__global__ void fill_i64_kernel(int64_t* p, int64_t v, size_t cnt) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < cnt) p[idx] = v;
+}
+
+hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t cnt, hipStream_t s) {
+  if (cnt == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i64_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, p, v,
+                     cnt);
+  return hipGetLastError();
+}
+
+}  // namespace pdbo

@@ -1,0 +1,299 @@
+// Weighted Max-k-SAT path (Sec. 5.1, Max-k-SAT; weighted clauses).
+//
+// f(x) = sum_j w_j prod_{l in C_j} p(x_l), p = x for a negated literal and
+// 1 - x otherwise; its partial derivative in x_i sums, over the occurrences of
+// variable i, w_j * (+1 if that literal is negated, else -1) times the product
+// of p over the other literals of the clause.  The adjoint is computed
+// variable-major: every variable owns the list of its occurrences, each entry
+// carrying the codes of the clause's other literals and a meta word, so the
+// gradient is a deterministic gather with no atomics.  The meta word holds the
+// weight (bits 0-23), "this literal is negated" (bit 30) and "this is the first
+// literal of its clause" (bit 29); the exact weighted unsatisfied count of
+// round(x) is fused into the same pass by counting each clause at its first
+// literal.  Literal codes are (variable index) | (negated << 31).
+#include <climits>
+
+#include "common.h"
+
+namespace pdbo {
+
+__host__ __device__ static inline size_t align16s(size_t v) { return (v + 15) & ~size_t(15); }
+
+constexpr size_t kSatLdsBudget = 150 * 1024;
+
+bool sat_fits(int n, size_t* lds_bytes) {
+  const size_t need = align16s((size_t)n * 4);
+  if (lds_bytes) *lds_bytes = need;
+  return n <= 32768 && need <= kSatLdsBudget;
+}
+
+// Sum over the occurrences of variable i of the adjoint terms; also the
+// weighted count of clauses first-listed at i whose literals are all false.
+__device__ __forceinline__ float sat_adjoint(const SatDev& D, const float* __restrict__ xsrc,
+                                             int i, float xi, bool want_eval, int64_t& unsat) {
+  const int k = D.k;
+  float g = 0.f;
+  const bool own_true = xi > 0.5f;
+  const int pe = D.inc_ptr[i + 1];
+  for (int e = D.inc_ptr[i]; e < pe; ++e) {
+    const int32_t* E = D.inc + (size_t)e * k;
+    float prod = 1.f;
+    bool others_false = true;
+    for (int o = 0; o < k - 1; ++o) {
+      const int32_t code = E[o];
+      const float xv = xsrc[code & 0x7fffffff];
+      const bool neg = code < 0;
+      prod *= neg ? xv : 1.f - xv;
+      others_false = others_false && ((xv > 0.5f) == neg);
+    }
+    const int32_t meta = E[k - 1];
+    const float w = (float)(meta & 0xffffff);
+    const bool own_neg = (meta >> 30) & 1;
+    g = fmaf(own_neg ? w : -w, prod, g);
+    if (want_eval && ((meta >> 29) & 1) && others_false && (own_true == own_neg))
+      unsat += (meta & 0xffffff);
+  }
+  return g;
+}
+
+template <int NT, int RMAX>
+__global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int nsteps) {
+  constexpr int NW = NT / 64;
+  extern __shared__ __attribute__((aligned(16))) float xs[];
+  __shared__ int64_t red[2][NW];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int b = blockIdx.x, n = D.n;
+  float xr[RMAX], yr[RMAX], xn[RMAX];
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    const int i = tid + j * NT;
+    xr[j] = 0.f;
+    yr[j] = 0.f;
+    if (i < n) {
+      xr[j] = D.X[(size_t)b * D.ld + i];
+      yr[j] = D.Y[(size_t)b * D.ld + i];
+      xs[i] = xr[j];
+    }
+  }
+  int64_t bF = D.rbestF[b], bT = D.rbestT[b];
+  uint64_t bTs = D.rbestTs[b];
+  int64_t Flast = D.Flast[b];
+  const GdaP gp = D.gp;
+  const float ios = D.ios;
+  __syncthreads();
+  for (int s = 0; s <= nsteps; ++s) {
+    const bool upd = s < nsteps;
+    const bool ev = s > 0;
+    int64_t S = 0;
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+      const int i = tid + j * NT;
+      if (i < n) {
+        const float g = sat_adjoint(D, xs, i, xr[j], ev, S);
+        if (upd) {
+          float a, c;
+          gda_update(xr[j], yr[j], g * ios, gp, a, c);
+          xn[j] = a;
+          yr[j] = c;
+        }
+      }
+    }
+    if (ev) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
+      if (lane == 0) red[s & 1][wid] = S;
+    }
+    __syncthreads();
+    if (ev) {
+      int64_t F = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) F += red[s & 1][w];
+      Flast = F;
+      if (F < bF) {
+        bF = F;
+        bT = t0 + s;
+        if (tid == 0) bTs = wall_clock();
+        uint8_t* dst = D.best_xr + (size_t)b * n;
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) {
+          const int i = tid + j * NT;
+          if (i < n) dst[i] = (uint8_t)(xr[j] > 0.5f);
+        }
+      }
+    }
+    if (upd) {
+#pragma unroll
+      for (int j = 0; j < RMAX; ++j) {
+        const int i = tid + j * NT;
+        if (i < n) {
+          xs[i] = xn[j];
+          xr[j] = xn[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    const int i = tid + j * NT;
+    if (i < n) {
+      D.X[(size_t)b * D.ld + i] = xr[j];
+      D.Y[(size_t)b * D.ld + i] = yr[j];
+    }
+  }
+  if (tid == 0) {
+    D.rbestF[b] = bF;
+    D.rbestT[b] = bT;
+    D.rbestTs[b] = bTs;
+    D.Flast[b] = Flast;
+  }
+}
+
+template <int NT, int RMAX>
+static hipError_t launch_sat_k(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
+  auto kern = sat_persistent<NT, RMAX>;
+  const size_t lds = align16s((size_t)d.n * 4);
+  hipError_t e =
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(d.B), dim3(NT), lds, s, d, t0, nsteps);
+  return hipGetLastError();
+}
+
+hipError_t launch_sat_persistent(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
+  if (nsteps <= 0) return hipSuccess;
+  const int r = (d.n + 511) / 512;
+  if (r <= 8) return launch_sat_k<512, 8>(d, t0, nsteps, s);
+  if (r <= 16) return launch_sat_k<512, 16>(d, t0, nsteps, s);
+  if (r <= 32) return launch_sat_k<512, 32>(d, t0, nsteps, s);
+  if (r <= 48) return launch_sat_k<512, 48>(d, t0, nsteps, s);
+  if (r <= 64) return launch_sat_k<512, 64>(d, t0, nsteps, s);
+  return hipErrorInvalidValue;
+}
+
+// ---- adjoint at given points: gradient (mode 0) or Lagrangian backward (mode 1)
+
+template <int MODE>
+__global__ void __launch_bounds__(512)
+    sat_adjoint_kernel(SatDev D, const float* __restrict__ X, int ldx, const float* __restrict__ Yv,
+                       const float* __restrict__ dL, float* __restrict__ dx,
+                       float* __restrict__ dy, int ldo, int use_lds) {
+  extern __shared__ __attribute__((aligned(16))) float xs[];
+  const int b = blockIdx.x, tid = threadIdx.x, n = D.n;
+  const float* xb = X + (size_t)b * ldx;
+  const float* src = xb;
+  if (use_lds) {
+    for (int i = tid; i < n; i += 512) xs[i] = xb[i];
+    __syncthreads();
+    src = xs;
+  }
+  const float scale = MODE == 1 ? dL[b] : 1.f;
+  for (int i = tid; i < n; i += 512) {
+    int64_t unused = 0;
+    const float xi = src[i];
+    const float g = sat_adjoint(D, src, i, xi, false, unused) * D.ios;
+    if (MODE == 0) {
+      dx[(size_t)b * ldo + i] = g;
+    } else {
+      const float yi = Yv[(size_t)b * ldx + i];
+      dx[(size_t)b * ldo + i] = scale * fmaf(yi, g_deriv(xi, D.gp.gkind), g);
+      dy[(size_t)b * ldo + i] = scale * g_value(xi, D.gp.gkind);
+    }
+  }
+}
+
+static hipError_t launch_adjoint(int mode, const SatDev& d, const float* X, int ldx,
+                                 const float* Y, const float* dL, float* dx, float* dy, int ldo,
+                                 int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  size_t lds = 0;
+  const int use_lds = sat_fits(d.n, &lds) ? 1 : 0;
+  if (!use_lds) lds = 0;
+  hipError_t e;
+  if (mode == 0) {
+    e = hipFuncSetAttribute((const void*)sat_adjoint_kernel<0>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sat_adjoint_kernel<0>, dim3(nb), dim3(512), lds, s, d, X, ldx, Y, dL, dx,
+                       dy, ldo, use_lds);
+  } else {
+    e = hipFuncSetAttribute((const void*)sat_adjoint_kernel<1>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sat_adjoint_kernel<1>, dim3(nb), dim3(512), lds, s, d, X, ldx, Y, dL, dx,
+                       dy, ldo, use_lds);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sat_grad(const SatDev& d, const float* X, int ldx, float* G, int nb,
+                           hipStream_t s) {
+  return launch_adjoint(0, d, X, ldx, nullptr, nullptr, G, nullptr, ldx, nb, s);
+}
+
+hipError_t launch_sat_bwd(const SatDev& d, const float* x, const float* y, const float* dL,
+                          int nb, float* dx, float* dy, hipStream_t s) {
+  return launch_adjoint(1, d, x, d.n, y, dL, dx, dy, d.n, nb, s);
+}
+
+// ---- clause-major passes: Lagrangian value and exact unsatisfied weight ----
+
+__global__ void __launch_bounds__(256)
+    sat_fwd_kernel(SatDev D, const float* __restrict__ x, const float* __restrict__ y,
+                   float* __restrict__ L) {
+  __shared__ double red[4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const float* xb = x + (size_t)b * D.n;
+  const float* yb = y + (size_t)b * D.n;
+  double acc = 0.0;
+  for (int j = tid; j < D.m; j += 256) {
+    float prod = 1.f;
+    for (int l = 0; l < D.k; ++l) {
+      const int32_t code = D.lits[(size_t)j * D.k + l];
+      const float xv = xb[code & 0x7fffffff];
+      prod *= code < 0 ? xv : 1.f - xv;
+    }
+    acc += (double)D.w[j] * (double)prod * (double)D.ios;
+  }
+  for (int i = tid; i < D.n; i += 256) acc += (double)yb[i] * (double)g_value(xb[i], D.gp.gkind);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) L[b] = (float)(red[0] + red[1] + red[2] + red[3]);
+}
+
+hipError_t launch_sat_fwd(const SatDev& d, const float* x, const float* y, int nb, float* L,
+                          hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sat_fwd_kernel, dim3(nb), dim3(256), 0, s, d, x, y, L);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+    sat_eval_kernel(SatDev D, const int8_t* __restrict__ xr, int64_t* __restrict__ F) {
+  __shared__ int64_t red[4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int8_t* xb = xr + (size_t)b * D.ld;
+  int64_t acc = 0;
+  for (int j = tid; j < D.m; j += 256) {
+    bool sat = false;
+    for (int l = 0; l < D.k; ++l) {
+      const int32_t code = D.lits[(size_t)j * D.k + l];
+      sat = sat || ((xb[code & 0x7fffffff] != 0) != (code < 0));
+    }
+    if (!sat) acc += D.w[j];
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) F[b] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_sat_eval(const SatDev& d, const int8_t* xr, int nb, int64_t* F,
+                           hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sat_eval_kernel, dim3(nb), dim3(256), 0, s, d, xr, F);
+  return hipGetLastError();
+}
+
+}  // namespace pdbo

@@ -1,0 +1,348 @@
+// Sparse QUBO path: a persistent, restart-resident kernel for CSR couplings.
+//
+// Restarts are independent (Sec. 5.2, Model Settings), so one workgroup owns
+// one restart for the whole launch: x of that restart lives in LDS (every row's
+// neighbours are gathered from there), y and the thread's own x in registers,
+// and when it fits the canonical CSR matrix Ahat = offdiag(Q + Q^T)/kappa is
+// staged in LDS too.  Each iteration needs two barriers and no grid-wide
+// synchronisation.  The exact objective of round(x^t) is fused into the same
+// gathers: while row i accumulates sum_k Ahat_ik x_k for the gradient it also
+// accumulates sum_k Ahat_ik [x_k > 1/2] in int32, so F(round(x^t)) =
+// (kappa/2) x_r^T Ahat x_r + c'^T x_r costs no extra pass.  The best value of
+// each restart over time (and the vector that attained it) is kept per restart
+// and reduced to the incumbent by restart_best_kernel.
+#include <climits>
+
+#include "common.h"
+
+namespace pdbo {
+
+__host__ __device__ static inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+
+static size_t csr_lds_need(int n, int64_t nnz, bool compact, bool with_csr) {
+  size_t b = align16((size_t)n * 4);
+  if (with_csr) {
+    b += align16((size_t)(n + 1) * 4);
+    b += align16((size_t)nnz * (compact ? 2 : 4));
+    b += align16((size_t)nnz * (compact ? 1 : 4));
+  }
+  return b;
+}
+
+constexpr size_t kLdsBudget = 150 * 1024;
+
+// The persistent kernel needs x of one restart in LDS and at most 32768 rows
+// (1024 threads x 32 rows in registers); the CSR arrays are staged in LDS when
+// they fit as well and are read through the L2 otherwise.
+bool csr_fits(int n, int64_t nnz, bool compact, size_t* lds_bytes) {
+  const bool with_csr = csr_lds_need(n, nnz, compact, true) <= kLdsBudget;
+  const size_t need = csr_lds_need(n, nnz, compact, with_csr);
+  if (lds_bytes) *lds_bytes = need;
+  return n <= 32768 && need <= kLdsBudget;
+}
+
+template <typename ColT, typename ValT, bool CSR_LDS, int NT, int RMAX>
+__global__ void __launch_bounds__(NT)
+    csr_persistent(CsrDev D, int64_t t0, int nsteps) {
+  constexpr int NW = NT / 64;
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  __shared__ int64_t red[2][NW][2];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int b = blockIdx.x;
+  const int n = D.n;
+  float* xs = (float*)lds;
+  const int32_t* rp = D.row_ptr;
+  const ColT* col = (const ColT*)D.col;
+  const ValT* val = (const ValT*)D.val;
+  if constexpr (CSR_LDS) {
+    int32_t* rpl = (int32_t*)(lds + align16((size_t)n * 4));
+    const int nnz = (int)D.nnz;
+    ColT* coll = (ColT*)((uint8_t*)rpl + align16((size_t)(n + 1) * 4));
+    ValT* vall = (ValT*)((uint8_t*)coll + align16((size_t)nnz * sizeof(ColT)));
+    for (int p = tid; p <= n; p += NT) rpl[p] = D.row_ptr[p];
+    for (int p = tid; p < nnz; p += NT) {
+      coll[p] = col[p];
+      vall[p] = val[p];
+    }
+    rp = rpl;
+    col = coll;
+    val = vall;
+  }
+  const float* Xg = D.X + (size_t)b * D.ld;
+  float xr[RMAX], yr[RMAX], xn[RMAX];
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    const int i = tid + j * NT;
+    xr[j] = 0.f;
+    yr[j] = 0.f;
+    if (i < n) {
+      xr[j] = Xg[i];
+      yr[j] = D.Y[(size_t)b * D.ld + i];
+      xs[i] = xr[j];
+    }
+  }
+  int64_t bF = D.rbestF[b], bT = D.rbestT[b];
+  uint64_t bTs = D.rbestTs[b];
+  int64_t Flast = D.Flast[b];
+  const float kos = D.kos;
+  const GdaP gp = D.gp;
+  __syncthreads();
+
+  for (int s = 0; s <= nsteps; ++s) {
+    const bool upd = s < nsteps;
+    const bool ev = s > 0;
+    int64_t S = 0, C = 0;
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+      const int i = tid + j * NT;
+      if (i < n) {
+        float acc = 0.f;
+        int accr = 0;
+        const int pe = rp[i + 1];
+        for (int p = rp[i]; p < pe; ++p) {
+          const float xk = xs[col[p]];
+          const int v = (int)val[p];
+          acc = fmaf((float)v, xk, acc);
+          accr += xk > 0.5f ? v : 0;
+        }
+        if (ev && xr[j] > 0.5f) {
+          S += accr;
+          C += D.cp[i];
+        }
+        if (upd) {
+          float a, c;
+          gda_update(xr[j], yr[j], fmaf(acc, kos, D.cps[i]), gp, a, c);
+          xn[j] = a;
+          yr[j] = c;
+        }
+      }
+    }
+    if (ev) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        S += __shfl_xor(S, o);
+        C += __shfl_xor(C, o);
+      }
+      if (lane == 0) {
+        red[s & 1][wid][0] = S;
+        red[s & 1][wid][1] = C;
+      }
+    }
+    __syncthreads();
+    if (ev) {
+      int64_t St = 0, Ct = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        St += red[s & 1][w][0];
+        Ct += red[s & 1][w][1];
+      }
+      const int64_t F = (D.kappa == 2 ? St : St / 2) + Ct;
+      Flast = F;
+      if (F < bF) {
+        bF = F;
+        bT = t0 + s;
+        if (tid == 0) bTs = wall_clock();
+        uint8_t* dst = D.best_xr + (size_t)b * n;
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) {
+          const int i = tid + j * NT;
+          if (i < n) dst[i] = (uint8_t)(xr[j] > 0.5f);
+        }
+      }
+    }
+    if (upd) {
+#pragma unroll
+      for (int j = 0; j < RMAX; ++j) {
+        const int i = tid + j * NT;
+        if (i < n) {
+          xs[i] = xn[j];
+          xr[j] = xn[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    const int i = tid + j * NT;
+    if (i < n) {
+      D.X[(size_t)b * D.ld + i] = xr[j];
+      D.Y[(size_t)b * D.ld + i] = yr[j];
+    }
+  }
+  if (tid == 0) {
+    D.rbestF[b] = bF;
+    D.rbestT[b] = bT;
+    D.rbestTs[b] = bTs;
+    D.Flast[b] = Flast;
+  }
+}
+
+template <typename ColT, typename ValT, bool CSR_LDS, int NT, int RMAX>
+static hipError_t launch_csr_k(const CsrDev& d, int64_t nnz, int64_t t0, int nsteps,
+                               hipStream_t s) {
+  auto kern = csr_persistent<ColT, ValT, CSR_LDS, NT, RMAX>;
+  size_t lds = align16((size_t)d.n * 4);
+  if (CSR_LDS)
+    lds += align16((size_t)(d.n + 1) * 4) + align16((size_t)nnz * sizeof(ColT)) +
+           align16((size_t)nnz * sizeof(ValT));
+  hipError_t e =
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(d.B), dim3(NT), lds, s, d, t0, nsteps);
+  return hipGetLastError();
+}
+
+template <typename ColT, typename ValT, bool CSR_LDS>
+static hipError_t launch_csr_r(const CsrDev& d, int64_t nnz, int64_t t0, int nsteps,
+                               hipStream_t s) {
+  const int r = (d.n + 255) / 256;
+  if (r <= 8) return launch_csr_k<ColT, ValT, CSR_LDS, 256, 8>(d, nnz, t0, nsteps, s);
+  if (r <= 16) return launch_csr_k<ColT, ValT, CSR_LDS, 256, 16>(d, nnz, t0, nsteps, s);
+  if (r <= 32) return launch_csr_k<ColT, ValT, CSR_LDS, 256, 32>(d, nnz, t0, nsteps, s);
+  if (r <= 64) return launch_csr_k<ColT, ValT, CSR_LDS, 256, 64>(d, nnz, t0, nsteps, s);
+  if (r <= 128) return launch_csr_k<ColT, ValT, CSR_LDS, 1024, 32>(d, nnz, t0, nsteps, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_csr_persistent(const CsrDev& d, bool compact, int64_t t0, int nsteps,
+                                 hipStream_t s) {
+  if (nsteps <= 0) return hipSuccess;
+  const int64_t nnz = d.nnz;
+  const size_t need = csr_lds_need(d.n, nnz, compact, true);
+  if (need <= kLdsBudget) {
+    if (compact) return launch_csr_r<uint16_t, int8_t, true>(d, nnz, t0, nsteps, s);
+    return launch_csr_r<int32_t, int32_t, true>(d, nnz, t0, nsteps, s);
+  }
+  if (compact) return launch_csr_r<uint16_t, int8_t, false>(d, nnz, t0, nsteps, s);
+  return launch_csr_r<int32_t, int32_t, false>(d, nnz, t0, nsteps, s);
+}
+
+// ---- gradient and exact evaluation at given points (tests, qubo_gda_grad/eval)
+
+template <typename ColT, typename ValT>
+__global__ void csr_grad_kernel(CsrDev D, const float* __restrict__ X, float* __restrict__ G,
+                                int nb) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nb * D.n) return;
+  const int b = (int)(idx / D.n), i = (int)(idx % D.n);
+  const float* xb = X + (size_t)b * D.ld;
+  const ColT* col = (const ColT*)D.col;
+  const ValT* val = (const ValT*)D.val;
+  float acc = 0.f;
+  for (int p = D.row_ptr[i]; p < D.row_ptr[i + 1]; ++p) acc = fmaf((float)val[p], xb[col[p]], acc);
+  G[(size_t)b * D.ld + i] = fmaf(acc, D.kos, D.cps[i]);
+}
+
+template <typename ColT, typename ValT>
+__global__ void __launch_bounds__(256)
+    csr_eval_kernel(CsrDev D, const int8_t* __restrict__ xr, int64_t* __restrict__ F) {
+  __shared__ int64_t red[4][2];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int8_t* x = xr + (size_t)b * D.ld;
+  const ColT* col = (const ColT*)D.col;
+  const ValT* val = (const ValT*)D.val;
+  int64_t S = 0, C = 0;
+  for (int i = tid; i < D.n; i += 256) {
+    if (!x[i]) continue;
+    int64_t a = 0;
+    for (int p = D.row_ptr[i]; p < D.row_ptr[i + 1]; ++p) a += x[col[p]] ? (int64_t)val[p] : 0;
+    S += a;
+    C += D.cp[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    S += __shfl_xor(S, o);
+    C += __shfl_xor(C, o);
+  }
+  if ((tid & 63) == 0) {
+    red[tid >> 6][0] = S;
+    red[tid >> 6][1] = C;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int64_t St = 0, Ct = 0;
+    for (int w = 0; w < 4; ++w) {
+      St += red[w][0];
+      Ct += red[w][1];
+    }
+    F[b] = (D.kappa == 2 ? St : St / 2) + Ct;
+  }
+}
+
+hipError_t launch_csr_grad(const CsrDev& d, bool compact, const float* X, float* G, int nb,
+                           hipStream_t s) {
+  const size_t tot = (size_t)nb * d.n;
+  if (tot == 0) return hipSuccess;
+  const dim3 grid((unsigned)((tot + 255) / 256));
+  if (compact)
+    hipLaunchKernelGGL((csr_grad_kernel<uint16_t, int8_t>), grid, dim3(256), 0, s, d, X, G, nb);
+  else
+    hipLaunchKernelGGL((csr_grad_kernel<int32_t, int32_t>), grid, dim3(256), 0, s, d, X, G, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_eval(const CsrDev& d, bool compact, const int8_t* xr, int nb, int64_t* F,
+                           hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  if (compact)
+    hipLaunchKernelGGL((csr_eval_kernel<uint16_t, int8_t>), dim3(nb), dim3(256), 0, s, d, xr, F);
+  else
+    hipLaunchKernelGGL((csr_eval_kernel<int32_t, int32_t>), dim3(nb), dim3(256), 0, s, d, xr, F);
+  return hipGetLastError();
+}
+
+// ---- per-restart bests -> incumbent ----------------------------------------
+
+__global__ void __launch_bounds__(256)
+    restart_best_kernel(const int64_t* __restrict__ rbestF, const int64_t* __restrict__ rbestT,
+                        const uint64_t* __restrict__ rbestTs, const uint8_t* __restrict__ best_xr,
+                        int B, int n, Incumbent* inc, uint8_t* best_x) {
+  __shared__ int64_t sF[256], sT[256];
+  __shared__ int sb[256];
+  const int tid = threadIdx.x;
+  int64_t F = LLONG_MAX, T = LLONG_MAX;
+  int bb = INT_MAX;
+  for (int b = tid; b < B; b += 256) {
+    const int64_t f = rbestF[b], t = rbestT[b];
+    if (f < F || (f == F && t < T)) {
+      F = f;
+      T = t;
+      bb = b;
+    }
+  }
+  sF[tid] = F;
+  sT[tid] = T;
+  sb[tid] = bb;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      const int64_t f = sF[tid + h], t = sT[tid + h];
+      const int b = sb[tid + h];
+      if (f < sF[tid] || (f == sF[tid] && (t < sT[tid] || (t == sT[tid] && b < sb[tid])))) {
+        sF[tid] = f;
+        sT[tid] = t;
+        sb[tid] = b;
+      }
+    }
+    __syncthreads();
+  }
+  const int b = sb[0];
+  if (sF[0] == LLONG_MAX || b == INT_MAX) return;
+  if (tid == 0) {
+    inc->F = sF[0];
+    inc->t = sT[0];
+    inc->b = b;
+    inc->ts = rbestTs[b];
+  }
+  for (int i = tid; i < n; i += 256) best_x[i] = best_xr[(size_t)b * n + i];
+}
+
+hipError_t launch_restart_best(const int64_t* rbestF, const int64_t* rbestT,
+                               const uint64_t* rbestTs, const uint8_t* best_xr, int B, int n,
+                               Incumbent* inc, uint8_t* best_x, hipStream_t s) {
+  hipLaunchKernelGGL(restart_best_kernel, dim3(1), dim3(256), 0, s, rbestF, rbestT, rbestTs,
+                     best_xr, B, n, inc, best_x);
+  return hipGetLastError();
+}
+
+}  // namespace pdbo

@@ -1,0 +1,43 @@
+"""Helpers shared by the GPU parity tests (test infrastructure)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gda
+from oracle.binarity import by_name
+
+
+def require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2509_21064_amd as P
+    P.load()  # a missing library is an error on a GPU machine, not a skip
+    return P
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def normwise(G, G64):
+    return float(np.max(np.abs(G - G64)) / max(np.max(np.abs(G64)), 1e-30))
+
+
+def lockstep_compare(X, Y, G64, Xg, Yg, p, gtol_abs):
+    """Compares one GPU iteration (Xg, Yg) from float32 inputs (X, Y) with the
+    oracle's iteration from the same inputs.  Coordinates whose branch of Alg. 1
+    could flip within the gradient tolerance are excluded and counted."""
+    g = by_name(p.get("g", "quad"))
+    d = p["delta"]
+    Xn, Yn, dL = gda.alg1_update(X, Y, G64, p["alpha"], p["beta"], d, g)
+    # |x - 1/2| <= delta and y <= 0 are decided exactly in float32 and float64
+    # on the same float32 inputs; only |dL| <= 2 delta depends on the gradient
+    eps = 4e-7
+    live = (np.abs(X - 0.5) <= d) & (Y <= 0)
+    amb = live & (np.abs(np.abs(dL) - 2 * d) <= gtol_abs + eps)
+    ok = ~amb
+    dx = float(np.max(np.abs(Xg - Xn)[ok])) if ok.any() else 0.0
+    dy = float(np.max(np.abs(Yg - Yn)))
+    return dx, dy, int(amb.sum()), Xn, Yn

@@ -1,0 +1,116 @@
+"""CSR persistent path on the GPU against the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import lockstep_compare, normwise, require_gpu, say
+from oracle import gda
+from oracle import qubo as oq
+
+pytestmark = pytest.mark.gpu
+
+
+def _wide_weights(n=900, M=4000, seed=0):
+    """A CSR QUBO with weights beyond int8 and an asymmetric part plus diagonal,
+    which takes the int32 (non-compact) storage."""
+    g = np.random.default_rng(seed)
+    base = W.maxcut_c2(rep=seed, n=n, M=M)
+    vals = g.integers(-900, 901, size=base.vals.shape[0]).astype(np.int32)
+    rows = np.repeat(np.arange(n), np.diff(base.row_ptr))
+    # add diagonal entries to some rows
+    Qd = np.zeros((n, n), np.int64)
+    Qd[rows, base.col_idx] = vals
+    di = g.choice(n, n // 5, replace=False)
+    Qd[di, di] = g.integers(-50, 51, size=di.size)
+    import scipy.sparse as sp
+    S = sp.csr_matrix(Qd)
+    S.sort_indices()
+    return W.Qubo(n=n, row_ptr=S.indptr.astype(np.int32), col_idx=S.indices.astype(np.int32),
+                  vals=S.data.astype(np.int32), c=g.integers(-100, 101, n).astype(np.int64))
+
+
+CASES = {
+    "maxcut_n2000": (lambda: W.maxcut_c2(0), 256, 1.0),
+    "maxcut_n301_ragged": (lambda: W.maxcut_c2(1, n=301, M=900), 37, 1.0),
+    "wide_n900": (lambda: _wide_weights(), 20, None),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_gradient_and_lockstep(name):
+    P = require_gpu()
+    mk, B, s = CASES[name]
+    q = mk()
+    s = W.qubo_scale(q) if s is None else s
+    say(f"[csr lockstep] case={name} n={q.n} B={B}")
+    g = np.random.default_rng(2)
+    X = g.random((B, q.n)).astype(np.float32)
+    X[:, ::9] = 0.5
+    Y = g.uniform(-2.0, 6.0, (B, q.n)).astype(np.float32)
+    p = W.gda_params("maxcut", B=B, T=1, scale=s)
+    ctx = P.qubo_gda_init(q, p, X.astype(np.float64))
+    G64 = oq.grad_f(*oq.canonicalize(q), X.astype(np.float64), s)
+    G = ctx.grad(X)
+    assert normwise(G, G64) <= 1e-5
+    ctx.set_state(X, Y, 0)
+    ctx.step(1)
+    Xg, Yg, t = ctx.get_state()
+    gabs = 1e-5 * float(np.max(np.abs(G64))) + 1e-6
+    dx, dy, namb, _, _ = lockstep_compare(X.astype(np.float64), Y.astype(np.float64), G64, Xg, Yg, p, gabs)
+    say(f"   max|dX|={dx:.3e} max|dY|={dy:.3e} excluded={namb}/{X.size}")
+    assert dx <= p["alpha"] * gabs + 2e-6 and dy <= 2e-6 * 7
+    assert namb <= 0.2 * X.size
+    # the objective of round(x^1) is fused into the persistent kernel: bit-exact
+    assert np.array_equal(ctx.objectives(), oq.objective(q, Xg > 0.5))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_eval_exact(name):
+    P = require_gpu()
+    mk, B, s = CASES[name]
+    q = mk()
+    ctx = P.qubo_gda_init(q, W.gda_params("maxcut", B=B, T=1, scale=1.0), W.x0_uniform(2, 3, B, q.n))
+    g = np.random.default_rng(4)
+    xr = (g.random((B, q.n)) < 0.5).astype(np.uint8)
+    assert np.array_equal(ctx.eval(xr), oq.objective(q, xr))
+
+
+def test_full_c2_run_invariants_and_split_launches():
+    P = require_gpu()
+    q = W.maxcut_c2(0)
+    B, T = 256, 5000
+    x0 = W.x0_uniform(2, 0, B, q.n)
+    p = W.gda_params("maxcut", B=B, T=T)
+    say("[csr run] C2 n=2000 B=256 T=5000")
+    ctx = P.qubo_gda_init(q, p, x0)
+    ctx.step(T)
+    X, Y, t = ctx.get_state()
+    r = ctx.result()
+    assert t == T and np.all((X >= 0) & (X <= 1)) and np.all(Y <= p["y0"])
+    assert r["best_obj"] == oq.objective(q, r["best_x"][None])[0]
+    # the same run split into uneven launches is bit-identical
+    ctx2 = P.qubo_gda_init(q, p, x0)
+    for k in (1, 999, 2000, 2000):
+        ctx2.step(k)
+    X2, Y2, _ = ctx2.get_state()
+    r2 = ctx2.result()
+    assert np.array_equal(X, X2) and np.array_equal(Y, Y2)
+    assert (r2["best_obj"], r2["best_iter"], r2["best_restart"]) == (r["best_obj"], r["best_iter"], r["best_restart"])
+    # quality against the oracle on a bounded sample of restarts and iterations
+    ref = gda.run(oq.QuboProblem(q, 1.0), x0[:32], p, T=1000)
+    say(f"   GPU best cut {-r['best_obj']} (t={r['best_iter']}); oracle 32 restarts x 1000 it: {-ref.inc.F}")
+    assert r["best_obj"] <= ref.inc.F
+
+
+def test_oracle_trajectory_short_horizon():
+    """Over a few iterations the float32 trajectory tracks the float64 one."""
+    P = require_gpu()
+    q = W.maxcut_c2(1, n=301, M=900)
+    B = 8
+    x0 = W.x0_uniform(2, 1, B, q.n)
+    p = W.gda_params("maxcut", B=B, T=5)
+    ctx = P.qubo_gda_init(q, p, x0)
+    ctx.step(5)
+    X, Y, _ = ctx.get_state()
+    ref = gda.run(oq.QuboProblem(q, 1.0), x0, p, T=5)
+    assert np.max(np.abs(X - ref.X)) < 1e-4 and np.max(np.abs(Y - ref.Y)) < 1e-5
