@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the PDBO hot path on one MI355X.
+
+Workload: dense QUBO, n = 10,000, Q symmetric with integer entries U{-100..100}
+(diagonal included), c ~ U{-100..100}, B = 1,024 restarts, Alg. 1 with g = x^2 - x,
+y_bar = 6, alpha = beta = 0.025, delta = 2^-7 and the convex-start scale s.  A
+"step" is one iteration of the whole hot path over all restarts: the fused
+gradient GEMM + Alg. 1 epilogue, the exact int8 evaluation of every rounded
+restart and the best-of-B / incumbent update.
+
+Prints one JSON line: restart-iterations/s of the mixed-precision (BF16) form
+as `value`, the plain FP32 form beside it, the best objective found by 1 s of
+device time for each form, the roofline of the dominant kernel (HIP-event
+times of its launches in the timed region) and the CPU oracle baseline.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "restart-iters/s + best objective at 1 s, mixed-prec vs FP32 plain, n=10k"
+UNIT = "restart-iterations/s"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3, "i8": 5000.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def dense_source_hash():
+    p = os.path.join(ROOT, "paper_2509_21064_amd", "csrc", "dense.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(form, n, B):
+    """HBM bytes per launch of the step kernel, from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"dense_{form}_step_n{n}_B{B}_traffic.txt")
+    if not os.path.exists(p):
+        return None
+    kv = {}
+    for line in open(p):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("dense.hip sha256[:16]") != dense_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_form(P, q, s, x0, form, args):
+    import numpy as np
+    import torch
+
+    import workloads as W
+
+    B, n = args.B, q.n
+    p = W.gda_params("qubo", B=B, T=args.T, scale=s, precision=form, tile=args.tile,
+                     graph_chunk=args.graph_chunk)
+    t0 = time.time()
+    ctx = P.qubo_gda_init(q, p, x0)
+    log(f"{form}: init {time.time() - t0:.1f}s (tile {ctx.tile_name})")
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ctx.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - ts
+    k_step = ctx.kernel_time(P.PDBO_K_STEP)
+    k_eval = ctx.kernel_time(P.PDBO_K_EVAL)
+    k_arg = ctx.kernel_time(P.PDBO_K_ARGMIN)
+    ctx.timing(False)
+    ctx.destroy()
+    out = dict(value=B * args.steps / el, ms_per_step=1e3 * el / args.steps,
+               step_kernel_ms=k_step[0] / max(k_step[1], 1),
+               eval_kernel_ms=k_eval[0] / max(k_eval[1], 1),
+               argmin_kernel_ms=k_arg[0] / max(k_arg[1], 1), launches=k_step[1])
+    log(f"{form}: {out['value']:.4g} restart-it/s, {out['ms_per_step']:.3f} ms/step "
+        f"(step {out['step_kernel_ms']:.3f} ms, eval {out['eval_kernel_ms']:.3f} ms, "
+        f"argmin {out['argmin_kernel_ms']:.3f} ms)")
+    if not args.no_quality:
+        ctx = P.qubo_gda_init(q, p, x0)
+        ctx.step(args.T)
+        r = ctx.result()
+        tr = ctx.trace()
+        ctx.destroy()
+        at1 = [int(F) for F, sec in zip(tr["F"], tr["sec"]) if sec <= 1.0]
+        out.update(best_at_1s=(at1[-1] if at1 else None), best_at_T=int(r["best_obj"]),
+                   T=args.T, time_to_best_s=float(r["time_to_best_s"]),
+                   iter_of_best=int(r["best_iter"]),
+                   seconds_for_T=float(tr["sec"][-1]) if len(tr["sec"]) else None)
+        log(f"{form}: best@1s {out['best_at_1s']}  best@T={args.T} {out['best_at_T']} "
+            f"(t={r['best_iter']}, {r['time_to_best_s']:.3f}s)")
+    return out
+
+
+def cpu_baseline(q, s, x0, args):
+    import numpy as np
+
+    import workloads as W
+    from oracle import gda
+    from oracle import qubo as oq
+
+    Bs = args.cpu_restarts
+    prob = oq.QuboProblem(q, s)
+    # size the sample to about cpu_seconds of host work: one calibration iteration first
+    p1 = W.gda_params("qubo", B=Bs, T=1, scale=s)
+    t0 = time.perf_counter()
+    gda.run(prob, x0[:Bs], p1, T=1)
+    t1 = time.perf_counter() - t0
+    Ts = int(min(args.T, max(1, round(args.cpu_seconds / max(t1, 1e-3)))))
+    p = W.gda_params("qubo", B=Bs, T=Ts, scale=s)
+    t0 = time.perf_counter()
+    gda.run(prob, x0[:Bs], p, T=Ts)
+    el = time.perf_counter() - t0
+    cores = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        th = [i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"]
+        if th:
+            cores = max(th)
+    except Exception:
+        pass
+    v = Bs * Ts / el
+    log(f"cpu oracle: {v:.4g} restart-it/s over {Bs} restarts x {Ts} iterations ({el:.1f}s, {cores} threads)")
+    return dict(value=v, unit=UNIT, cores=cores, kind="oracle",
+                sample=f"FP64 oracle (numpy/BLAS), first {Bs} of the {args.B} restarts, {Ts} "
+                       f"iterations incl. exact int64 evaluation, same instance and x0; {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=10000)
+    ap.add_argument("--B", type=int, default=1024)
+    ap.add_argument("--T", type=int, default=2000, help="iterations of the quality run")
+    ap.add_argument("--forms", default="bf16,fp32,fp8")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--graph-chunk", type=int, default=0)
+    ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-restarts", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); restarts shard trivially "
+              "across GPUs but no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2509_21064_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    P.load()
+    t0 = time.time()
+    q = W.qubo_c3(0, n=args.n)
+    s = W.qubo_scale(q)
+    x0 = W.x0_uniform(3, 0, args.B, q.n)
+    log(f"instance n={q.n} B={args.B} s={s:.2f} generated in {time.time() - t0:.1f}s")
+
+    forms = [f for f in args.forms.split(",") if f]
+    res = {f: run_form(P, q, s, x0, f, args) for f in forms}
+    head = "bf16" if "bf16" in res else forms[0]
+    h = res[head]
+    flops = 2.0 * q.n * q.n * args.B
+    achieved = flops / (h["step_kernel_ms"] * 1e-3) / 1e12
+    traffic = read_traffic(head, q.n, args.B)
+    roof = dict(bound="mfma", kernel=f"dense_gemm<{head}, STEP>", achieved=achieved,
+                peak=PEAK_TFLOPS[head], unit="TFLOP/s", frac=achieved / PEAK_TFLOPS[head],
+                traffic=traffic, flop_per_launch=flops,
+                avg_launch_ms=h["step_kernel_ms"], launches=h["launches"])
+    ev = dict(kernel="dense_gemm<i8, EVAL>", achieved=flops / (h["eval_kernel_ms"] * 1e-3) / 1e12,
+              peak=PEAK_TFLOPS["i8"], unit="TOP/s")
+    ev["frac"] = ev["achieved"] / ev["peak"]
+    line = dict(metric=METRIC, value=h["value"], unit=UNIT, n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=h["ms_per_step"], higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype=head, data="synthetic",
+                config=dict(workload=f"dense QUBO n={q.n}, Q sym U{{-100..100}}, c U{{-100..100}}, "
+                                     f"B={args.B}, quality run T={args.T}",
+                            n=q.n, B=args.B, T=args.T, scale=s, precision=head,
+                            g="x^2-x", y0=6.0, alpha=0.025, beta=0.025, delta=2 ** -7),
+                forms=res, roofline=roof, eval_roofline=ev)
+    if "fp32" in res and head != "fp32":
+        f32 = res["fp32"]
+        line["speedup_vs_fp32"] = h["value"] / f32["value"]
+        if not args.no_quality and f32.get("best_at_1s") is not None and h.get("best_at_1s") is not None:
+            line["rel_gap_best_at_1s_vs_fp32"] = (h["best_at_1s"] - f32["best_at_1s"]) / abs(f32["best_at_1s"])
+            line["rel_gap_best_at_T_vs_fp32"] = (h["best_at_T"] - f32["best_at_T"]) / abs(f32["best_at_T"])
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(q, s, x0, args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

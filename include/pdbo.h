@@ -226,6 +226,15 @@ PDBO_API pdbo_status maxsat_lagrangian_bwd(pdbo_ctx* ctx, const float* x, const 
 
 /* ---- instrumentation ------------------------------------------------------ */
 
+/* Incumbent improvements of a dense context, in order: iteration t, objective
+ * F, restart b and device-clock seconds since the start of the first step, for
+ * at most `cap` records (host arrays, any may be NULL); *len receives the
+ * number of records kept (the device keeps the first 4096).  Persistent
+ * (CSR, MaxSAT) contexts keep per-restart bests instead and report len = 0.
+ * Synchronises. */
+PDBO_API pdbo_status qubo_gda_trace(pdbo_ctx* ctx, int32_t cap, int64_t* t, int64_t* F, int32_t* b,
+                                    double* sec, int32_t* len);
+
 enum { PDBO_K_STEP = 0, PDBO_K_EVAL = 1, PDBO_K_ARGMIN = 2, PDBO_K_PERSISTENT = 3,
        PDBO_K_COUNT = 4 };
 

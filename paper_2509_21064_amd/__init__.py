@@ -26,7 +26,7 @@ from ._abi import (PDBO_BF16, PDBO_CSR, PDBO_DENSE, PDBO_FP8, PDBO_FP32, PDBO_G_
 __all__ = [
     "load", "PdboError", "Context", "qubo_gda_init", "qubo_gda_step", "qubo_gda_result",
     "qubo_gda_get_state", "qubo_gda_set_state", "qubo_gda_objectives", "qubo_gda_grad",
-    "qubo_gda_eval", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
+    "qubo_gda_eval", "qubo_gda_trace", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
     "qubo_gda_batch_solve", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
     "maxsat_gda_solve", "maxsat_lagrangian_fwd", "maxsat_lagrangian_bwd", "MaxSATLagrangian",
     "PDBO_FP32", "PDBO_BF16", "PDBO_FP8", "PDBO_K_STEP", "PDBO_K_EVAL", "PDBO_K_ARGMIN",
@@ -149,6 +149,9 @@ class Context:
     def eval(self, xr):
         return qubo_gda_eval(self, xr)
 
+    def trace(self, cap=4096):
+        return qubo_gda_trace(self, cap)
+
     def timing(self, enable=True):
         check(load().pdbo_timing(self.h, int(bool(enable))), self.h)
 
@@ -218,6 +221,18 @@ def qubo_gda_eval(ctx: Context, xr) -> np.ndarray:
     F = np.zeros(xa.shape[0], dtype=np.int64)
     check(load().qubo_gda_eval(ctx.h, _ptr(xa), int(xa.shape[0]), _ptr(F)), ctx.h)
     return F
+
+
+def qubo_gda_trace(ctx: Context, cap: int = 4096) -> dict:
+    t = np.zeros(cap, dtype=np.int64)
+    F = np.zeros(cap, dtype=np.int64)
+    b = np.zeros(cap, dtype=np.int32)
+    sec = np.zeros(cap, dtype=np.float64)
+    ln = ctypes.c_int32()
+    check(load().qubo_gda_trace(ctx.h, int(cap), _ptr(t), _ptr(F), _ptr(b), _ptr(sec),
+                                ctypes.byref(ln)), ctx.h)
+    k = ln.value
+    return dict(t=t[:k], F=F[:k], b=b[:k], sec=sec[:k])
 
 
 def qubo_gda_solve(q, params: dict, x0, T: int, stream=None) -> dict:

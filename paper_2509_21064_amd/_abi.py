@@ -68,6 +68,8 @@ SIGNATURES = {
     "maxsat_lagrangian_fwd": (_st, [_ctx, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "maxsat_lagrangian_bwd": (_st, [_ctx, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
                                     c_void_p, c_void_p]),
+    "qubo_gda_trace": (_st, [_ctx, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                             POINTER(c_int32)]),
     "pdbo_timing": (_st, [_ctx, c_int32]),
     "pdbo_kernel_time": (_st, [_ctx, c_int32, POINTER(c_double), POINTER(c_int64)]),
     "pdbo_tile_name": (c_char_p, [_ctx]),

@@ -388,10 +388,37 @@ GdaP make_gp(const pdbo_params* p) {
 
 int element_bytes(int prec) { return prec == PDBO_FP32 ? 4 : prec == PDBO_BF16 ? 2 : 1; }
 
-int default_cfg(int n, int B) {
-  // 0: 128x128, 1: 64x64
-  if (n <= 512 || B <= 64) return 1;
-  return 0;
+// Estimated cost of a tile configuration for a set of instances: the launch
+// runs in ceil(tiles / (256 CUs x workgroups per CU)) rounds, each costing the
+// per-CU output area, inflated when the wave tile needs more LDS bytes per MFMA
+// than the LDS can deliver at the MFMA rate (wave tiles below 64x64).
+double cfg_cost(int cfg, const std::vector<int>& ns, int B) {
+  const TileCfgInfo& cf = dense_cfg(cfg);
+  const int lds = 2 * (cf.BM + cf.BN) * 144;
+  const int occ = std::max(1, std::min(4, (160 * 1024) / lds));
+  double tiles = 0;
+  for (int n : ns) tiles += (double)((n + cf.BM - 1) / cf.BM) * ((B + cf.BN - 1) / cf.BN);
+  const double rounds = std::ceil(tiles / (256.0 * occ));
+  const double fm = cf.BM / cf.WM / 16.0, fn = cf.BN / cf.WN / 16.0;
+  const double lds_per_mfma = (fm + fn) / (fm * fn);
+  const double ineff = std::max(1.0, lds_per_mfma / 0.5);
+  return rounds * occ * cf.BM * cf.BN * ineff;
+}
+
+int default_cfg(const std::vector<int>& ns, int B) {
+  // small tiles first so that they win ties on small problems
+  static const int order[] = {1, 0, 2, 3, 4, 5};
+  int best = 1;
+  double bc = 1e300;
+  for (int id : order) {
+    if (id >= dense_num_cfgs()) continue;
+    const double cst = cfg_cost(id, ns, B);
+    if (cst < bc) {
+      bc = cst;
+      best = id;
+    }
+  }
+  return best;
 }
 
 // ---------------------------------------------------------------- timing
@@ -496,8 +523,8 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
     STCHK(dalloc(c, &I.Xs[1], sz * EB));
   }
   STCHK(dalloc(c, &I.Xr, sz));
-  STCHK(dalloc(c, &I.Spart, (size_t)I.mblocks * B));
-  STCHK(dalloc(c, &I.Cpart, (size_t)I.mblocks * B));
+  STCHK(dalloc(c, &I.Sacc, (size_t)B));
+  STCHK(dalloc(c, &I.Cacc, (size_t)B));
   STCHK(dalloc(c, &I.Fall, (size_t)B));
   STCHK(dalloc(c, &I.inc, 1));
   STCHK(dalloc(c, &I.best_x, (size_t)ld));
@@ -520,15 +547,28 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
 // Tile table: row groups (instance, m-block) are assigned round-robin to the
 // 8 XCDs (workgroup w of a launch runs on XCD w % 8) so that the column tiles
 // sharing one block of Ahat rows run on the same XCD, back to back, and reuse
-// that block from the XCD's L2.
+// that block from the XCD's L2.  PDBO_TILE_ORDER=1 selects plain row-group
+// order instead (for measurement).
 void build_tiles(pdbo_ctx* c) {
   const TileCfgInfo& cf = dense_cfg(c->cfg);
   c->tiles_h.clear();
   c->tile_off.clear();
   c->tile_cnt.clear();
+  static const int order = [] {
+    const char* e = std::getenv("PDBO_TILE_ORDER");
+    return e ? std::atoi(e) : 0;
+  }();
   for (size_t k = 0; k < c->insts_h.size(); ++k) {
-    const InstDev& I = c->insts_h[k];
+    InstDev& I = c->insts_h[k];
+    I.mblocks = (I.n + cf.BM - 1) / cf.BM;
     const int nb = (I.B + cf.BN - 1) / cf.BN;
+    if (order == 1) {
+      c->tile_off.push_back((int)c->tiles_h.size());
+      for (int m = 0; m < I.mblocks; ++m)
+        for (int j = 0; j < nb; ++j) c->tiles_h.push_back(TileDev{(int)k, m * cf.BM, j * cf.BN, m});
+      c->tile_cnt.push_back((int)c->tiles_h.size() - c->tile_off.back());
+      continue;
+    }
     std::vector<std::vector<TileDev>> q(8);
     for (int m = 0; m < I.mblocks; ++m)
       for (int j = 0; j < nb; ++j) q[m % 8].push_back(TileDev{(int)k, m * cf.BM, j * cf.BN, m});
@@ -566,6 +606,147 @@ pdbo_status upload_dense_tables(pdbo_ctx* c) {
   HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_GRAD, nullptr, 0, nullptr, 0, 0, c->stream));
   HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, nullptr, 0, nullptr, 0, 0, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDBO_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+//
+// Times the GRAD variant of the dense GEMM (the same main loop as the step)
+// for every tile configuration on the context's own operands and keeps the
+// fastest.  Every output element is accumulated along K in the same order
+// whatever the tile shape, so the choice never changes results.  Choices are
+// cached as a flat JSON object {"key": cfg, ...} in $PDBO_AUTOTUNE_CACHE
+// (default $HOME/.cache/pdbo_autotune.json), keyed by architecture, operand
+// type, B, instance count and the instance sizes.
+
+std::string autotune_key(const pdbo_ctx* c) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  long long nsum = 0;
+  int nmax = 0;
+  for (const InstDev& I : c->insts_h) {
+    nsum += I.n;
+    nmax = std::max(nmax, I.n);
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s/p%d/B%d/k%zu/nmax%d/nsum%lld", arch.c_str(), c->prec, c->B,
+                c->insts_h.size(), (nmax + 63) / 64 * 64, (nsum + 1023) / 1024 * 1024);
+  return buf;
+}
+
+std::string autotune_path() {
+  const char* e = std::getenv("PDBO_AUTOTUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = std::getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/pdbo_autotune.json";
+}
+
+std::mutex g_tune_mu;
+
+int autotune_lookup(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* f = std::fopen(autotune_path().c_str(), "r");
+  if (!f) return -1;
+  char line[512];
+  int found = -1;
+  while (std::fgets(line, sizeof(line), f)) {
+    char k[400];
+    int v;
+    if (std::sscanf(line, " \"%399[^\"]\" : %d", k, &v) == 2 && key == k) found = v;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void autotune_store(const std::string& key, int cfg) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const std::string path = autotune_path();
+  std::vector<std::pair<std::string, int>> ent;
+  if (FILE* f = std::fopen(path.c_str(), "r")) {
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+      char k[400];
+      int v;
+      if (std::sscanf(line, " \"%399[^\"]\" : %d", k, &v) == 2 && key != k) ent.emplace_back(k, v);
+    }
+    std::fclose(f);
+  }
+  ent.emplace_back(key, cfg);
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    const std::string dir = path.substr(0, slash);
+    (void)std::system(("mkdir -p '" + dir + "' 2>/dev/null").c_str());
+  }
+  if (FILE* f = std::fopen(path.c_str(), "w")) {
+    std::fprintf(f, "{\n");
+    for (size_t i = 0; i < ent.size(); ++i)
+      std::fprintf(f, "  \"%s\": %d%s\n", ent[i].first.c_str(), ent[i].second,
+                   i + 1 < ent.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+  }
+}
+
+pdbo_status upload_dense_tables(pdbo_ctx* c);
+
+pdbo_status autotune_dense(pdbo_ctx* c) {
+  const std::string key = autotune_key(c);
+  const int cached = autotune_lookup(key);
+  if (cached >= 0 && cached < dense_num_cfgs()) {
+    c->cfg = cached;
+    return PDBO_OK;
+  }
+  // gradient outputs for the timing launches, freed on return
+  std::vector<TempDev> gbuf(c->insts_h.size());
+  for (size_t k = 0; k < c->insts_h.size(); ++k) {
+    InstDev& I = c->insts_h[k];
+    HIPCHK(c, hipMalloc(&gbuf[k].p, (size_t)I.B * I.ld * sizeof(float)));
+    I.G = (float*)gbuf[k].p;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  int best = c->cfg;
+  float best_ms = 1e30f;
+  for (int id = 0; id < dense_num_cfgs(); ++id) {
+    c->cfg = id;
+    build_tiles(c);
+    TileDev* td = nullptr;
+    InstDev* idv = nullptr;
+    TempDev ttd, tid;
+    HIPCHK(c, hipMalloc(&ttd.p, c->tiles_h.size() * sizeof(TileDev)));
+    HIPCHK(c, hipMalloc(&tid.p, c->insts_h.size() * sizeof(InstDev)));
+    td = (TileDev*)ttd.p;
+    idv = (InstDev*)tid.p;
+    HIPCHK(c, hipMemcpyAsync(td, c->tiles_h.data(), c->tiles_h.size() * sizeof(TileDev),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(idv, c->insts_h.data(), c->insts_h.size() * sizeof(InstDev),
+                             hipMemcpyHostToDevice, c->stream));
+    const int nt = (int)c->tiles_h.size();
+    HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_GRAD, td, nt, idv, c->parity, 0, c->stream));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    constexpr int reps = 3;
+    for (int r = 0; r < reps; ++r)
+      HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_GRAD, td, nt, idv, c->parity, 0, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = id;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (InstDev& I : c->insts_h) I.G = nullptr;
+  c->cfg = best;
+  autotune_store(key, best);
   return PDBO_OK;
 }
 
@@ -762,9 +943,9 @@ static pdbo_status dense_init(int k, const pdbo_qubo* probs, const pdbo_params* 
     if (pars[0].tile > 0) {
       c->cfg = pars[0].tile - 1;
     } else {
-      int nmax = 0;
-      for (int i = 0; i < k; ++i) nmax = std::max(nmax, probs[i].n);
-      c->cfg = default_cfg(nmax, pars[0].B);
+      std::vector<int> ns;
+      for (int i = 0; i < k; ++i) ns.push_back(probs[i].n);
+      c->cfg = default_cfg(ns, pars[0].B);
     }
     c->insts_h.resize(k);
     for (int i = 0; i < k && st == PDBO_OK; ++i) {
@@ -773,6 +954,14 @@ static pdbo_status dense_init(int k, const pdbo_qubo* probs, const pdbo_params* 
       if (st == PDBO_OK) st = setup_dense_instance(c, C, &pars[i], c->insts_h[i]);
       c->n_of.push_back(probs[i].n);
     }
+  }
+  if (st == PDBO_OK && pars[0].tile == 0) {
+    // autotune large problems (or when asked); PDBO_AUTOTUNE=0 keeps the heuristic
+    const char* e = std::getenv("PDBO_AUTOTUNE");
+    double work = 0;
+    for (const InstDev& I : c->insts_h) work += (double)I.n * I.n * I.B;
+    const bool want = e ? std::atoi(e) != 0 : work >= (double)(1 << 30);
+    if (want) st = autotune_dense(c);
   }
   if (st == PDBO_OK) st = upload_dense_tables(c);
   if (st != PDBO_OK) {
@@ -1032,8 +1221,8 @@ static pdbo_status ensure_scratch(pdbo_ctx* c) {
   STCHK(dalloc(c, &c->f_scratch, c->B));
   if (c->kind == 0) {
     STCHK(dalloc(c, &c->gs_scratch, sz * element_bytes(c->prec)));
-    STCHK(dalloc(c, &c->sp_scratch, (size_t)c->insts_h[0].mblocks * c->B));
-    STCHK(dalloc(c, &c->cp_scratch, (size_t)c->insts_h[0].mblocks * c->B));
+    STCHK(dalloc(c, &c->sp_scratch, (size_t)c->B));
+    STCHK(dalloc(c, &c->cp_scratch, (size_t)c->B));
     STCHK(dalloc(c, &c->scratch_inst_d, 1));
   }
   return PDBO_OK;
@@ -1094,8 +1283,8 @@ pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F
   if (c->kind == 0) {
     InstDev I = c->insts_h[0];
     I.Xr = c->xr_scratch;
-    I.Spart = c->sp_scratch;
-    I.Cpart = c->cp_scratch;
+    I.Sacc = c->sp_scratch;
+    I.Cacc = c->cp_scratch;
     I.Fall = c->f_scratch;
     I.B = nb;
     HIPCHK(c, hipMemcpyAsync(c->scratch_inst_d, &I, sizeof(I), hipMemcpyHostToDevice, c->stream));
@@ -1293,6 +1482,32 @@ pdbo_status maxsat_lagrangian_bwd(pdbo_ctx* c, const float* x, const float* y, c
   if (!c || c->kind != 2) return fail(c, PDBO_ESTATE, "not a MaxSAT context");
   if (!x || !y || !dL || !dx || !dy || nb < 1) return fail(c, PDBO_EINVAL, "bad arguments");
   HIPCHK(c, launch_sat_bwd(c->sat, x, y, dL, nb, dx, dy, (hipStream_t)stream));
+  return PDBO_OK;
+}
+
+pdbo_status qubo_gda_trace(pdbo_ctx* c, int32_t cap, int64_t* t, int64_t* F, int32_t* b,
+                           double* sec, int32_t* len) {
+  if (!c || !len) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (cap < 0) return fail(c, PDBO_EINVAL, "cap must be >= 0");
+  *len = 0;
+  if (c->kind != 0 || c->insts_h.size() != 1) return PDBO_OK;
+  const InstDev& I = c->insts_h[0];
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int32_t k = 0;
+  uint64_t ts0 = 0;
+  HIPCHK(c, hipMemcpy(&k, I.trace_len, sizeof(k), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(&ts0, c->ts0_d, sizeof(ts0), hipMemcpyDeviceToHost));
+  k = std::min(k, cap);
+  std::vector<TraceRec> tr(k);
+  if (k > 0) HIPCHK(c, hipMemcpy(tr.data(), I.trace, k * sizeof(TraceRec), hipMemcpyDeviceToHost));
+  const double hz = clock_rate_hz();
+  for (int i = 0; i < k; ++i) {
+    if (t) t[i] = tr[i].t;
+    if (F) F[i] = tr[i].F;
+    if (b) b[i] = (int32_t)tr[i].b;
+    if (sec) sec[i] = (tr[i].ts >= ts0 && ts0) ? (double)(tr[i].ts - ts0) / hz : 0.0;
+  }
+  *len = k;
   return PDBO_OK;
 }
 

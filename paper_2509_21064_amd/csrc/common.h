@@ -56,8 +56,8 @@ struct InstDev {
   uint8_t* Xs[2];         // shadows; for FP32 these alias X
   int8_t* Xr;
   float* G;               // gradient output of the GRAD epilogue
-  int64_t* Spart;         // [mblocks][B] partial x_r^T Ahat x_r
-  int64_t* Cpart;         // [mblocks][B] partial c'^T x_r
+  int64_t* Sacc;          // [B] x_r^T Ahat x_r, accumulated by integer atomics
+  int64_t* Cacc;          // [B] c'^T x_r, accumulated by integer atomics
   int64_t* Fall;          // [B] objectives of the last evaluation
   Incumbent* inc;
   uint8_t* best_x;        // [n]
@@ -114,7 +114,7 @@ __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_mem
 
 struct TileCfgInfo {
   const char* name;
-  int BM, BN, threads;
+  int BM, BN, WM, WN, threads;  // block tile, waves along M and N
 };
 int dense_num_cfgs();
 const TileCfgInfo& dense_cfg(int id);

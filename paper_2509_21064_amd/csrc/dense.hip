@@ -6,7 +6,9 @@
 //              rounded iterate [x^{t+1} > 1/2].
 //   EPI_GRAD : G only (tests and autotuning).
 //   EPI_EVAL : E = Ahat . Xr in int8 x int8 -> int32, reduced on the fly to
-//              per-tile partials of x_r^T Ahat x_r and c'^T x_r (int64).
+//              x_r^T Ahat x_r and c'^T x_r per restart with int64 atomics
+//              (integer addition is exact in any order, so the totals are
+//              bit-reproducible).
 //
 // Operands are both K-contiguous: row i of Ahat (Ahat is symmetric) and row b
 // of the restart-major shadow.  Every K step consumes one 128-byte chunk of
@@ -25,6 +27,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <int P> struct PT;
@@ -85,6 +88,16 @@ __device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float 
   return (uint32_t)w;
 }
 
+// Pointers read from the instance table are generic; casting them to the
+// global address space makes the compiler emit global_load/global_store rather
+// than flat accesses, which would also count against the LDS wait counter and
+// serialise the operand prefetch with the fragment reads.
+#define PDBO_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ PDBO_GLOBAL T* gptr(T* p) {
+  return (PDBO_GLOBAL T*)p;
+}
+
 constexpr int kRow = 144;  // LDS bytes per operand row: one 128-byte chunk + 16 pad
 
 template <int BM, int BN>
@@ -107,7 +120,6 @@ __global__ void __launch_bounds__(64 * WM * WN)
   using Acc = typename PT<P>::Acc;
 
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  __shared__ int64_t red[(EPI == EPI_EVAL) ? 2 * WM * BN : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
@@ -148,9 +160,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
 
     u32x4 ra[APC], rb[BPC];
 #pragma unroll
-    for (int j = 0; j < APC; ++j) ra[j] = *(const u32x4*)(pa[j]);
+    for (int j = 0; j < APC; ++j) ra[j] = *gptr((const u32x4*)(pa[j]));
 #pragma unroll
-    for (int j = 0; j < BPC; ++j) rb[j] = *(const u32x4*)(pb[j]);
+    for (int j = 0; j < BPC; ++j) rb[j] = *gptr((const u32x4*)(pb[j]));
 #pragma unroll
     for (int j = 0; j < APC; ++j) *(u32x4*)(smem + la[j]) = ra[j];
 #pragma unroll
@@ -164,9 +176,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
       if (more) {
         const size_t off = (size_t)(kc + 1) * 128;
 #pragma unroll
-        for (int j = 0; j < APC; ++j) ra[j] = *(const u32x4*)(pa[j] + off);
+        for (int j = 0; j < APC; ++j) ra[j] = *gptr((const u32x4*)(pa[j] + off));
 #pragma unroll
-        for (int j = 0; j < BPC; ++j) rb[j] = *(const u32x4*)(pb[j] + off);
+        for (int j = 0; j < BPC; ++j) rb[j] = *gptr((const u32x4*)(pb[j] + off));
       }
       const uint8_t* sA = smem + cur * STAGE + (wm * WTM) * kRow + frow;
       const uint8_t* sB = smem + cur * STAGE + (BM + wn * WTN) * kRow + frow;
@@ -209,9 +221,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
       for (int fm = 0; fm < FM; ++fm) {
         const int i = ibase + fm * 16;
         if (i >= n) continue;
-        const f32x4 cs = *(const f32x4*)(I.cps + i);
+        const f32x4 cs = *gptr((const f32x4*)(I.cps + i));
         f32x4 sc = {kos, kos, kos, kos};
-        if constexpr (P == P_FP8) sc = sc * *(const f32x4*)(I.rscale + i);
+        if constexpr (P == P_FP8) sc = sc * *gptr((const f32x4*)(I.rscale + i));
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn) {
           const int b = bbase + fn * 16;
@@ -221,10 +233,10 @@ __global__ void __launch_bounds__(64 * WM * WN)
 #pragma unroll
           for (int r = 0; r < 4; ++r) G[r] = fmaf(acc[fm][fn][r], sc[r], cs[r]);
           if constexpr (EPI == EPI_GRAD) {
-            *(f32x4*)(I.G + off) = G;
+            *gptr((f32x4*)(I.G + off)) = G;
           } else {
-            const f32x4 xv = *(const f32x4*)(Xc + off);
-            const f32x4 yv = *(const f32x4*)(Yp + off);
+            const f32x4 xv = *gptr((const f32x4*)(Xc + off));
+            const f32x4 yv = *gptr((const f32x4*)(Yp + off));
             f32x4 xo, yo;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -233,19 +245,19 @@ __global__ void __launch_bounds__(64 * WM * WN)
               xo[r] = a;
               yo[r] = c;
             }
-            *(f32x4*)(Xn + off) = xo;
-            *(f32x4*)(Yp + off) = yo;
+            *gptr((f32x4*)(Xn + off)) = xo;
+            *gptr((f32x4*)(Yp + off)) = yo;
             const uint32_t xr = (uint32_t)(xo[0] > 0.5f) | ((uint32_t)(xo[1] > 0.5f) << 8) |
                                 ((uint32_t)(xo[2] > 0.5f) << 16) |
                                 ((uint32_t)(xo[3] > 0.5f) << 24);
-            *(uint32_t*)(I.Xr + off) = xr;
+            *gptr((uint32_t*)(I.Xr + off)) = xr;
             if constexpr (P == P_BF16) {
-              uint2 v;
+              u32x2 v;
               v.x = (uint32_t)f32_to_bf16_rne(xo[0]) | ((uint32_t)f32_to_bf16_rne(xo[1]) << 16);
               v.y = (uint32_t)f32_to_bf16_rne(xo[2]) | ((uint32_t)f32_to_bf16_rne(xo[3]) << 16);
-              *(uint2*)(Xsn + off * 2) = v;
+              *gptr((u32x2*)(Xsn + off * 2)) = v;
             } else if constexpr (P == P_FP8) {
-              *(uint32_t*)(Xsn + off) = pack_fp8x4(xo[0], xo[1], xo[2], xo[3]);
+              *gptr((uint32_t*)(Xsn + off)) = pack_fp8x4(xo[0], xo[1], xo[2], xo[3]);
             }
           }
         }
@@ -262,12 +274,12 @@ __global__ void __launch_bounds__(64 * WM * WN)
         for (int fn = 0; fn < FN; ++fn) {
           const int b = bbase + fn * 16;
           if (b >= B) continue;
-          const uint32_t xr = *(const uint32_t*)(I.Xr + (size_t)b * ld + i);
+          const uint32_t xr = *gptr((const uint32_t*)(I.Xr + (size_t)b * ld + i));
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             if (((xr >> (8 * r)) & 1u) && (i + r < n)) {
               sS[fn] += acc[fm][fn][r];
-              sC[fn] += I.cp[i + r];
+              sC[fn] += *gptr(I.cp + i + r);
             }
           }
         }
@@ -278,27 +290,12 @@ __global__ void __launch_bounds__(64 * WM * WN)
         sS[fn] += __shfl_xor(sS[fn], 32);
         sC[fn] += __shfl_xor(sC[fn], 16);
         sC[fn] += __shfl_xor(sC[fn], 32);
-        if (lane < 16) {
-          const int col = wn * WTN + fn * 16 + lane;
-          red[(wm * BN + col) * 2 + 0] = sS[fn];
-          red[(wm * BN + col) * 2 + 1] = sC[fn];
+        const int b = bbase + fn * 16;
+        if (lane < 16 && b < B) {
+          if (sS[fn]) atomicAdd((unsigned long long*)(I.Sacc + b), (unsigned long long)sS[fn]);
+          if (sC[fn]) atomicAdd((unsigned long long*)(I.Cacc + b), (unsigned long long)sC[fn]);
         }
       }
-      __syncthreads();
-      for (int col = tid; col < BN; col += NT) {
-        const int b = td.n0 + col;
-        if (b < B) {
-          int64_t S = 0, C = 0;
-#pragma unroll
-          for (int q = 0; q < WM; ++q) {
-            S += red[(q * BN + col) * 2 + 0];
-            C += red[(q * BN + col) * 2 + 1];
-          }
-          I.Spart[(size_t)td.mblk * B + b] = S;
-          I.Cpart[(size_t)td.mblk * B + b] = C;
-        }
-      }
-      __syncthreads();
     }
   }
 }
@@ -309,10 +306,12 @@ __global__ void __launch_bounds__(64 * WM * WN)
   X(0, 128, 128, 2, 2)         \
   X(1, 64, 64, 2, 2)           \
   X(2, 256, 128, 4, 2)         \
-  X(3, 128, 256, 2, 4)
+  X(3, 128, 256, 2, 4)         \
+  X(4, 160, 256, 2, 2)         \
+  X(5, 192, 256, 2, 2)
 
 static const TileCfgInfo kCfgs[] = {
-#define X(id, bm, bn, wm, wn) {#bm "x" #bn "_w" #wm "x" #wn, bm, bn, 64 * wm * wn},
+#define X(id, bm, bn, wm, wn) {#bm "x" #bn "_w" #wm "x" #wn, bm, bn, wm, wn, 64 * wm * wn},
     PDBO_TILE_CFGS(X)
 #undef X
 };
@@ -381,24 +380,24 @@ hipError_t launch_dense_gemm(int cfg, int prec, int epi, const TileDev* tiles, i
 // update of the incumbent, copy of the winning rounded column.
 // mode 0: no evaluation this iteration (only the iteration counter advances);
 // mode 1: evaluation and incumbent update; mode 2: objectives only.
-__global__ void __launch_bounds__(256)
+constexpr int kArgThreads = 1024;
+
+__global__ void __launch_bounds__(kArgThreads)
     argmin_kernel(const InstDev* __restrict__ insts, int inst0, int mode) {
   const int do_eval = mode != 0;
   const InstDev& I = insts[inst0 + blockIdx.x];
-  __shared__ int64_t sF[256];
-  __shared__ int sb[256];
+  __shared__ int64_t sF[kArgThreads];
+  __shared__ int sb[kArgThreads];
   __shared__ int improved;
   const int tid = threadIdx.x;
   const int64_t t = *I.t_dev + 1;
   if (do_eval) {
     int64_t bestF = LLONG_MAX;
     int bestb = INT_MAX;
-    for (int b = tid; b < I.B; b += 256) {
-      int64_t S = 0, C = 0;
-      for (int mb = 0; mb < I.mblocks; ++mb) {
-        S += I.Spart[(size_t)mb * I.B + b];
-        C += I.Cpart[(size_t)mb * I.B + b];
-      }
+    for (int b = tid; b < I.B; b += kArgThreads) {
+      const int64_t S = I.Sacc[b], C = I.Cacc[b];
+      I.Sacc[b] = 0;  // ready for the next evaluation
+      I.Cacc[b] = 0;
       const int64_t F = (I.kappa == 2 ? S : S / 2) + C;
       I.Fall[b] = F;
       if (F < bestF) {
@@ -409,7 +408,7 @@ __global__ void __launch_bounds__(256)
     sF[tid] = bestF;
     sb[tid] = bestb;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kArgThreads / 2; h > 0; h >>= 1) {
       if (tid < h) {
         const int64_t f2 = sF[tid + h];
         const int b2 = sb[tid + h];
@@ -439,14 +438,14 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
     if (improved) {
       const int8_t* src = I.Xr + (size_t)sb[0] * I.ld;
-      for (int i = tid; i < I.n; i += 256) I.best_x[i] = (uint8_t)src[i];
+      for (int i = tid; i < I.n; i += kArgThreads) I.best_x[i] = (uint8_t)src[i];
     }
   }
   if (tid == 0 && mode != 2) *I.t_dev = t;
 }
 
 hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(argmin_kernel, dim3(ninst), dim3(256), 0, s, insts, inst0, mode);
+  hipLaunchKernelGGL(argmin_kernel, dim3(ninst), dim3(kArgThreads), 0, s, insts, inst0, mode);
   return hipGetLastError();
 }
 

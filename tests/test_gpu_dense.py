@@ -54,7 +54,7 @@ def test_gradient_parity(name, prec):
     assert err <= GTOL[prec], err
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
 def test_gradient_parity_every_tile(tile):
     P = require_gpu()
     q = W.random_dense_qubo(517, -100, 100, W.rng_for(3, 1, 0, 517))
