@@ -55,7 +55,7 @@ typedef struct pdbo_ctx pdbo_ctx;
 
 enum { PDBO_DENSE = 0, PDBO_CSR = 1 };
 enum { PDBO_G_QUAD = 0, PDBO_G_ENTROPY = 1 };
-enum { PDBO_FP32 = 0, PDBO_BF16 = 1, PDBO_FP8 = 2 };
+enum { PDBO_FP32 = 0, PDBO_BF16 = 1, PDBO_FP8 = 2, PDBO_I8 = 3 };
 
 /*
  * QUBO instance (Eq. 1 with quadratic F): minimise F(x) = x^T Q x + c^T x over
@@ -103,9 +103,12 @@ typedef struct {
  *              objective is still reported unscaled.
  *   g_kind     PDBO_G_QUAD (x^2 - x) or PDBO_G_ENTROPY (x log x + (1-x) log(1-x),
  *              derivative taken at x clipped to [2^-20, 1 - 2^-20]).
- *   precision  operand type of the dense gradient product A.X (FP32 accumulate
- *              always): PDBO_FP32, PDBO_BF16 (A and a bf16 copy of X), PDBO_FP8
- *              (A as OCP e4m3 with one fp32 scale per row, X as e4m3).
+ *   precision  operand type of the dense gradient product A.X: PDBO_FP32,
+ *              PDBO_BF16 (A and a bf16 copy of X), PDBO_FP8 (A as OCP e4m3 with
+ *              one fp32 scale per row, X as e4m3), all with FP32 accumulation;
+ *              or PDBO_I8 (A exactly as int8, X quantised to q = round(254 x) -
+ *              127 so that x ~ (q + 127)/254 within 1/508, int32 accumulation;
+ *              needs |Ahat_ij| <= 127 and 127 sum_j |Ahat_ij| < 2^31).
  *              Ignored by the CSR and MaxSAT paths, whose integer weights are
  *              stored exactly.
  *   eval_every evaluate round(x^t) every eval_every iterations (>= 1); the

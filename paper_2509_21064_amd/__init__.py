@@ -9,7 +9,7 @@ Instances are duck-typed: a QUBO has ``n`` and either a dense int32 ``Q`` or CSR
 ``row_ptr``/``col_idx``/``vals``, plus ``c`` (int64 or None); a MaxSAT formula
 has ``n``, ``lits`` (m, k) DIMACS int32 and ``w`` (m,) int32.  Parameters are a
 dict with B, alpha, beta, y0, delta, scale, g ("quad"/"entropy"), and
-optionally precision ("fp32"/"bf16"/"fp8"), eval_every, tile, graph_chunk.
+optionally precision ("fp32"/"bf16"/"fp8"/"i8"), eval_every, tile, graph_chunk.
 Starting points x0 are float64 arrays of shape (B, n).
 """
 from __future__ import annotations
@@ -19,7 +19,7 @@ import ctypes
 import numpy as np
 
 from . import _abi
-from ._abi import (PDBO_BF16, PDBO_CSR, PDBO_DENSE, PDBO_FP8, PDBO_FP32, PDBO_G_ENTROPY,
+from ._abi import (PDBO_BF16, PDBO_CSR, PDBO_DENSE, PDBO_FP8, PDBO_FP32, PDBO_G_ENTROPY, PDBO_I8,
                    PDBO_G_QUAD, PDBO_K_ARGMIN, PDBO_K_EVAL, PDBO_K_PERSISTENT, PDBO_K_STEP,
                    PdboError, check, load)
 
@@ -29,11 +29,11 @@ __all__ = [
     "qubo_gda_eval", "qubo_gda_trace", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
     "qubo_gda_batch_solve", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
     "maxsat_gda_solve", "maxsat_lagrangian_fwd", "maxsat_lagrangian_bwd", "MaxSATLagrangian",
-    "PDBO_FP32", "PDBO_BF16", "PDBO_FP8", "PDBO_K_STEP", "PDBO_K_EVAL", "PDBO_K_ARGMIN",
+    "PDBO_FP32", "PDBO_BF16", "PDBO_FP8", "PDBO_I8", "PDBO_K_STEP", "PDBO_K_EVAL", "PDBO_K_ARGMIN",
     "PDBO_K_PERSISTENT",
 ]
 
-_PREC = {"fp32": PDBO_FP32, "bf16": PDBO_BF16, "fp8": PDBO_FP8}
+_PREC = {"fp32": PDBO_FP32, "bf16": PDBO_BF16, "fp8": PDBO_FP8, "i8": PDBO_I8}
 _G = {"quad": PDBO_G_QUAD, "entropy": PDBO_G_ENTROPY}
 
 

@@ -186,7 +186,7 @@ pdbo_status check_params(const pdbo_params* p, int n, bool x0_required = true) {
     return fail(nullptr, PDBO_EINVAL, "delta must be in (0, 1/2)");
   if (p->g_kind != PDBO_G_QUAD && p->g_kind != PDBO_G_ENTROPY)
     return fail(nullptr, PDBO_EINVAL, "unknown g_kind");
-  if (p->precision < PDBO_FP32 || p->precision > PDBO_FP8)
+  if (p->precision < PDBO_FP32 || p->precision > PDBO_I8)
     return fail(nullptr, PDBO_EINVAL, "unknown precision");
   if (p->eval_every < 1) return fail(nullptr, PDBO_EINVAL, "eval_every must be >= 1");
   if (p->graph_chunk < 0 || (p->graph_chunk & 1))
@@ -387,6 +387,7 @@ GdaP make_gp(const pdbo_params* p) {
 }
 
 int element_bytes(int prec) { return prec == PDBO_FP32 ? 4 : prec == PDBO_BF16 ? 2 : 1; }
+static_assert((int)PDBO_I8 == (int)P_I8, "ABI and kernel precision codes agree");
 
 // Estimated cost of a tile configuration for a set of instances: the launch
 // runs in ceil(tiles / (256 CUs x workgroups per CU)) rounds, each costing the
@@ -394,7 +395,7 @@ int element_bytes(int prec) { return prec == PDBO_FP32 ? 4 : prec == PDBO_BF16 ?
 // than the LDS can deliver at the MFMA rate (wave tiles below 64x64).
 double cfg_cost(int cfg, const std::vector<int>& ns, int B) {
   const TileCfgInfo& cf = dense_cfg(cfg);
-  const int lds = 2 * (cf.BM + cf.BN) * 144;
+  const int lds = cf.dma ? 3 * (cf.BM + cf.BN) * 128 : 2 * (cf.BM + cf.BN) * 144;
   const int occ = std::max(1, std::min(4, (160 * 1024) / lds));
   double tiles = 0;
   for (int n : ns) tiles += (double)((n + cf.BM - 1) / cf.BM) * ((B + cf.BN - 1) / cf.BN);
@@ -407,7 +408,7 @@ double cfg_cost(int cfg, const std::vector<int>& ns, int B) {
 
 int default_cfg(const std::vector<int>& ns, int B) {
   // small tiles first so that they win ties on small problems
-  static const int order[] = {1, 0, 2, 3, 4, 5};
+  static const int order[] = {1, 9, 0, 7, 2, 8, 3, 4, 6, 5};
   int best = 1;
   double bc = 1e300;
   for (int id : order) {
@@ -478,8 +479,31 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
   uint8_t* A = nullptr;
   int8_t* A8 = nullptr;
   float* rs = nullptr;
-  STCHK(dalloc(c, &A, (size_t)n * ld * EB));
   STCHK(dalloc(c, &A8, (size_t)n * ld));
+  if (prec == PDBO_I8) {
+    // the exact int8 matrix is the gradient operand as well
+    int64_t worst = 0;
+    std::vector<int32_t> hsum(ld, 0);
+    for (int i = 0; i < n; ++i) {
+      int64_t sa = 0, sg = 0;
+      for (int j = 0; j < n; ++j) {
+        const int32_t v = C.Ahat[(size_t)i * n + j];
+        sg += v;
+        sa += v < 0 ? -v : v;
+      }
+      hsum[i] = (int32_t)sg;
+      worst = std::max(worst, sa);
+    }
+    if (127 * worst >= (int64_t(1) << 31))
+      return fail(c, PDBO_EUNSUPPORTED, "INT8 form needs 127 * sum_j |Ahat_ij| < 2^31");
+    int32_t* dsum = nullptr;
+    STCHK(dalloc(c, &dsum, ld));
+    HIPCHK(c, hipMemcpyAsync(dsum, hsum.data(), ld * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    I.rsum = dsum;
+  } else {
+    STCHK(dalloc(c, &A, (size_t)n * ld * EB));
+  }
   std::vector<float> hs(ld, 1.f);  // alive until the stream is synchronised below
   if (prec == PDBO_FP8) {
     for (int i = 0; i < n; ++i) hs[i] = C.rowmax[i] > 0.f ? C.rowmax[i] / 448.f : 1.f;
@@ -492,6 +516,7 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
     HIPCHK(c, launch_quantize_A((const int32_t*)t.p, n, ld, prec, A, A8, rs, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
+  if (prec == PDBO_I8) A = (uint8_t*)A8;
   I.A = A;
   I.A8 = A8;
   I.rscale = rs;

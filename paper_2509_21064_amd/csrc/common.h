@@ -49,6 +49,7 @@ struct InstDev {
   const uint8_t* A;       // Ahat in the GEMM operand type
   const int8_t* A8;       // Ahat as int8 (evaluation)
   const float* rscale;    // e4m3 row scale (FP8 form), else nullptr
+  const int32_t* rsum;    // sum_j Ahat_ij (INT8 form: offset of the quantised x)
   const float* cps;       // c'/s, padded to ld with zeros
   const int64_t* cp;      // c', padded to ld with zeros
   float* X[2];
@@ -115,6 +116,7 @@ __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_mem
 struct TileCfgInfo {
   const char* name;
   int BM, BN, WM, WN, threads;  // block tile, waves along M and N
+  int dma;                       // 1: three-stage direct-to-LDS main loop
 };
 int dense_num_cfgs();
 const TileCfgInfo& dense_cfg(int id);

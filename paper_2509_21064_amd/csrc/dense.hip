@@ -82,6 +82,15 @@ __device__ __forceinline__ void mfma_chunk<P_I8>(i32x4& c, const u32x4 (&a)[2],
                                               __builtin_bit_cast(i32x4, b[h]), c, 0, 0, 0);
 }
 
+// x in [0,1] -> q = round(254 x) - 127 in [-127, 127] (x ~ (q + 127) / 254)
+__device__ __forceinline__ uint32_t quant8(float x) {
+  return (uint32_t)(uint8_t)(int8_t)((int)rintf(x * 254.f) - 127);
+}
+
+__device__ __forceinline__ uint32_t pack_q8x4(float a, float b, float c, float d) {
+  return quant8(a) | (quant8(b) << 8) | (quant8(c) << 16) | (quant8(d) << 24);
+}
+
 __device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float d) {
   int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
   w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
@@ -103,6 +112,119 @@ constexpr int kRow = 144;  // LDS bytes per operand row: one 128-byte chunk + 16
 template <int BM, int BN>
 constexpr int gemm_lds_bytes() {
   return 2 * (BM + BN) * kRow;
+}
+
+// Epilogue of one tile, shared by both main loops.  STEP/GRAD: lane holds
+// rows ibase+16*fm+r (r = 0..3) of restart column bbase+16*fn.
+template <int BM, int BN, int WM, int WN, int P, int EPI>
+__device__ __forceinline__ void gemm_epilogue(
+    typename PT<P>::Acc (&acc)[BM / WM / 16][BN / WN / 16], const TileDev& td, const InstDev& I,
+    int parity, int lane, int wm, int wn) {
+  constexpr int WTM = BM / WM, WTN = BN / WN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  const int n = I.n, ld = I.ld, B = I.B;
+  const int ibase = td.m0 + wm * WTM + 4 * (lane >> 4);
+  const int bbase = td.n0 + wn * WTN + (lane & 15);
+  if constexpr (EPI == EPI_STEP || EPI == EPI_GRAD) {
+    const float kos = I.kos;
+    const GdaP gp = I.gp;
+    float* Xc = I.X[parity];
+    float* Xn = I.X[parity ^ 1];
+    float* Yp = I.Y;
+    uint8_t* Xsn = I.Xs[parity ^ 1];
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+      const int i = ibase + fm * 16;
+      if (i >= n) continue;
+      const f32x4 cs = *gptr((const f32x4*)(I.cps + i));
+      f32x4 sc = {kos, kos, kos, kos};
+      if constexpr (P == P_FP8) sc = sc * *gptr((const f32x4*)(I.rscale + i));
+      i32x4 off8 = {0, 0, 0, 0};
+      if constexpr (P == P_I8) {
+        // A x ~ (A q + 127 A 1) / 254 for the quantised iterate q
+        sc = sc * (1.f / 254.f);
+        off8 = *gptr((const i32x4*)(I.rsum + i)) * 127;
+      }
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn) {
+        const int b = bbase + fn * 16;
+        if (b >= B) continue;
+        const size_t off = (size_t)b * ld + i;
+        f32x4 G;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if constexpr (P == P_I8)
+            G[r] = fmaf((float)(acc[fm][fn][r] + off8[r]), sc[r], cs[r]);
+          else
+            G[r] = fmaf(acc[fm][fn][r], sc[r], cs[r]);
+        }
+        if constexpr (EPI == EPI_GRAD) {
+          *gptr((f32x4*)(I.G + off)) = G;
+        } else {
+          const f32x4 xv = *gptr((const f32x4*)(Xc + off));
+          const f32x4 yv = *gptr((const f32x4*)(Yp + off));
+          f32x4 xo, yo;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float a, c;
+            gda_update(xv[r], yv[r], G[r], gp, a, c);
+            xo[r] = a;
+            yo[r] = c;
+          }
+          *gptr((f32x4*)(Xn + off)) = xo;
+          *gptr((f32x4*)(Yp + off)) = yo;
+          const uint32_t xr = (uint32_t)(xo[0] > 0.5f) | ((uint32_t)(xo[1] > 0.5f) << 8) |
+                              ((uint32_t)(xo[2] > 0.5f) << 16) |
+                              ((uint32_t)(xo[3] > 0.5f) << 24);
+          *gptr((uint32_t*)(I.Xr + off)) = xr;
+          if constexpr (P == P_BF16) {
+            u32x2 v;
+            v.x = (uint32_t)f32_to_bf16_rne(xo[0]) | ((uint32_t)f32_to_bf16_rne(xo[1]) << 16);
+            v.y = (uint32_t)f32_to_bf16_rne(xo[2]) | ((uint32_t)f32_to_bf16_rne(xo[3]) << 16);
+            *gptr((u32x2*)(Xsn + off * 2)) = v;
+          } else if constexpr (P == P_FP8) {
+            *gptr((uint32_t*)(Xsn + off)) = pack_fp8x4(xo[0], xo[1], xo[2], xo[3]);
+          } else if constexpr (P == P_I8) {
+            *gptr((uint32_t*)(Xsn + off)) = pack_q8x4(xo[0], xo[1], xo[2], xo[3]);
+          }
+        }
+      }
+    }
+  } else {
+    int64_t sS[FN], sC[FN];
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) sS[fn] = sC[fn] = 0;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+      const int i = ibase + fm * 16;
+      if (i >= n) continue;
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn) {
+        const int b = bbase + fn * 16;
+        if (b >= B) continue;
+        const uint32_t xr = *gptr((const uint32_t*)(I.Xr + (size_t)b * ld + i));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (((xr >> (8 * r)) & 1u) && (i + r < n)) {
+            sS[fn] += acc[fm][fn][r];
+            sC[fn] += *gptr(I.cp + i + r);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) {
+      sS[fn] += __shfl_xor(sS[fn], 16);
+      sS[fn] += __shfl_xor(sS[fn], 32);
+      sC[fn] += __shfl_xor(sC[fn], 16);
+      sC[fn] += __shfl_xor(sC[fn], 32);
+      const int b = bbase + fn * 16;
+      if (lane < 16 && b < B) {
+        if (sS[fn]) atomicAdd((unsigned long long*)(I.Sacc + b), (unsigned long long)sS[fn]);
+        if (sC[fn]) atomicAdd((unsigned long long*)(I.Cacc + b), (unsigned long long)sC[fn]);
+      }
+    }
+  }
 }
 
 template <int BM, int BN, int WM, int WN, int P, int EPI>
@@ -207,111 +329,172 @@ __global__ void __launch_bounds__(64 * WM * WN)
       __syncthreads();
     }
 
-    // ---------------------------------------------------------------- epilogue
-    const int ibase = td.m0 + wm * WTM + 4 * (lane >> 4);
-    const int bbase = td.n0 + wn * WTN + (lane & 15);
-    if constexpr (EPI == EPI_STEP || EPI == EPI_GRAD) {
-      const float kos = I.kos;
-      const GdaP gp = I.gp;
-      float* Xc = I.X[parity];
-      float* Xn = I.X[parity ^ 1];
-      float* Yp = I.Y;
-      uint8_t* Xsn = I.Xs[parity ^ 1];
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm) {
-        const int i = ibase + fm * 16;
-        if (i >= n) continue;
-        const f32x4 cs = *gptr((const f32x4*)(I.cps + i));
-        f32x4 sc = {kos, kos, kos, kos};
-        if constexpr (P == P_FP8) sc = sc * *gptr((const f32x4*)(I.rscale + i));
-#pragma unroll
-        for (int fn = 0; fn < FN; ++fn) {
-          const int b = bbase + fn * 16;
-          if (b >= B) continue;
-          const size_t off = (size_t)b * ld + i;
-          f32x4 G;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) G[r] = fmaf(acc[fm][fn][r], sc[r], cs[r]);
-          if constexpr (EPI == EPI_GRAD) {
-            *gptr((f32x4*)(I.G + off)) = G;
-          } else {
-            const f32x4 xv = *gptr((const f32x4*)(Xc + off));
-            const f32x4 yv = *gptr((const f32x4*)(Yp + off));
-            f32x4 xo, yo;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              float a, c;
-              gda_update(xv[r], yv[r], G[r], gp, a, c);
-              xo[r] = a;
-              yo[r] = c;
-            }
-            *gptr((f32x4*)(Xn + off)) = xo;
-            *gptr((f32x4*)(Yp + off)) = yo;
-            const uint32_t xr = (uint32_t)(xo[0] > 0.5f) | ((uint32_t)(xo[1] > 0.5f) << 8) |
-                                ((uint32_t)(xo[2] > 0.5f) << 16) |
-                                ((uint32_t)(xo[3] > 0.5f) << 24);
-            *gptr((uint32_t*)(I.Xr + off)) = xr;
-            if constexpr (P == P_BF16) {
-              u32x2 v;
-              v.x = (uint32_t)f32_to_bf16_rne(xo[0]) | ((uint32_t)f32_to_bf16_rne(xo[1]) << 16);
-              v.y = (uint32_t)f32_to_bf16_rne(xo[2]) | ((uint32_t)f32_to_bf16_rne(xo[3]) << 16);
-              *gptr((u32x2*)(Xsn + off * 2)) = v;
-            } else if constexpr (P == P_FP8) {
-              *gptr((uint32_t*)(Xsn + off)) = pack_fp8x4(xo[0], xo[1], xo[2], xo[3]);
-            }
-          }
-        }
-      }
-    } else {
-      int64_t sS[FN], sC[FN];
-#pragma unroll
-      for (int fn = 0; fn < FN; ++fn) sS[fn] = sC[fn] = 0;
-#pragma unroll
-      for (int fm = 0; fm < FM; ++fm) {
-        const int i = ibase + fm * 16;
-        if (i >= n) continue;
-#pragma unroll
-        for (int fn = 0; fn < FN; ++fn) {
-          const int b = bbase + fn * 16;
-          if (b >= B) continue;
-          const uint32_t xr = *gptr((const uint32_t*)(I.Xr + (size_t)b * ld + i));
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if (((xr >> (8 * r)) & 1u) && (i + r < n)) {
-              sS[fn] += acc[fm][fn][r];
-              sC[fn] += *gptr(I.cp + i + r);
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int fn = 0; fn < FN; ++fn) {
-        sS[fn] += __shfl_xor(sS[fn], 16);
-        sS[fn] += __shfl_xor(sS[fn], 32);
-        sC[fn] += __shfl_xor(sC[fn], 16);
-        sC[fn] += __shfl_xor(sC[fn], 32);
-        const int b = bbase + fn * 16;
-        if (lane < 16 && b < B) {
-          if (sS[fn]) atomicAdd((unsigned long long*)(I.Sacc + b), (unsigned long long)sS[fn]);
-          if (sC[fn]) atomicAdd((unsigned long long*)(I.Cacc + b), (unsigned long long)sC[fn]);
-        }
-      }
-    }
+    gemm_epilogue<BM, BN, WM, WN, P, EPI>(acc, td, I, parity, lane, wm, wn);
   }
+}
+
+// ------------------------------------------------- three-stage LDS pipeline
+//
+// Same tile, same MFMA sequence and same epilogue as dense_gemm, but the
+// operands go from global memory straight into LDS (global_load_lds_dwordx4:
+// lane L of a wave writes 16 bytes at LDS base + 16 L), so no registers are
+// spent on staging and two K chunks are in flight while a third is consumed.
+// Rows are stored unpadded (128 bytes) with the 16-byte chunks XOR-swizzled by
+// (row / 2) mod 8: one DMA instruction fills 8 whole rows, and the 16 rows of
+// a fragment read (two rows per 256-byte bank period of the 64-bank LDS) land
+// on 16 distinct 16-byte bank groups.  The three stages are
+// distinct LDS objects and the K loop is unrolled by three, so every stage is
+// addressed statically.
+
+// Waits until at most N vector-memory operations (here: this wave's LDS DMAs)
+// are outstanding AND every LDS read of this wave has returned, so that after
+// the following s_barrier no wave can refill a stage another wave still reads.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt_lds() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  // gfx9 encoding: vmcnt[3:0] and [15:14], expcnt[6:4], lgkmcnt[11:8] (= 0 here)
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (0 << 8) | ((N >> 4) << 14));
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+template <int BM, int BN, int WM, int WN, int P, int EPI>
+__global__ void __launch_bounds__(64 * WM * WN)
+    dense_gemm_dma(const TileDev* __restrict__ tiles, int ntiles, const InstDev* __restrict__ insts,
+                   int parity) {
+  constexpr int NW = WM * WN;
+  constexpr int WTM = BM / WM, WTN = BN / WN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int ROWS = BM + BN;
+  constexpr int STAGE = ROWS * 128;
+  constexpr int NI = ROWS / (8 * NW);
+  constexpr int EB = PT<P>::EB;
+  static_assert(ROWS % (8 * NW) == 0, "stage rows must split into 8-row DMA groups per wave");
+  static_assert(BM % 16 == 0 && WTM % 16 == 0 && WTN % 16 == 0, "fragment alignment");
+  using Acc = typename PT<P>::Acc;
+
+  __shared__ __attribute__((aligned(1024))) uint8_t st0[STAGE];
+  __shared__ __attribute__((aligned(1024))) uint8_t st1[STAGE];
+  __shared__ __attribute__((aligned(1024))) uint8_t st2[STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wm = wid % WM, wn = wid / WM;
+  // fragment read offsets: row (lane % 16) of a 16-row group, logical chunks
+  // 2q and 2q+1 (q = lane / 16) stored at physical chunk c ^ ((row / 2) mod 8)
+  const int sw = (lane & 15) >> 1, q = lane >> 4;
+  const int fo0 = (lane & 15) * 128 + (((2 * q) ^ sw) << 4);
+  const int fo1 = (lane & 15) * 128 + (((2 * q + 1) ^ sw) << 4);
+
+  for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    const TileDev td = tiles[w];
+    const InstDev& I = insts[td.inst];
+    const int n = I.n, B = I.B;
+    const size_t rbytes = (size_t)I.ld * EB;
+    const int nk = (int)(rbytes / 128);
+    const uint8_t* Ag = (EPI == EPI_EVAL) ? (const uint8_t*)I.A8 : I.A;
+    const uint8_t* Bg = (EPI == EPI_EVAL) ? (const uint8_t*)I.Xr : I.Xs[parity];
+
+    // DMA instruction j of this wave fills stage rows r0 .. r0+7, r0 = 8 (j NW + wid);
+    // lane L writes physical chunk L % 8 of row r = r0 + L / 8, so it loads
+    // logical chunk (L % 8) ^ ((r / 2) mod 8).
+    const uint8_t* src[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int r = (j * NW + wid) * 8 + (lane >> 3);
+      const int c = (lane & 7) ^ ((r >> 1) & 7);
+      const uint8_t* row = r < BM ? Ag + (size_t)min(td.m0 + r, n - 1) * rbytes
+                                  : Bg + (size_t)min(td.n0 + (r - BM), B - 1) * rbytes;
+      src[j] = row + c * 16;
+    }
+    auto issue = [&](uint8_t* st, int kc) {
+      const size_t off = (size_t)kc * 128;
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+        __builtin_amdgcn_global_load_lds(gptr((const void*)(src[j] + off)),
+                                         (lds_ptr)(st + (j * NW + wid) * 1024), 16, 0, 0);
+    };
+
+    Acc acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+    auto compute = [&](const uint8_t* st) {
+      const uint8_t* sA = st + (wm * WTM) * 128;
+      const uint8_t* sB = st + (BM + wn * WTN) * 128;
+      u32x4 fa[FM][2], fb[FN][2];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        fa[i][0] = *(const u32x4*)(sA + i * 16 * 128 + fo0);
+        fa[i][1] = *(const u32x4*)(sA + i * 16 * 128 + fo1);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        fb[j][0] = *(const u32x4*)(sB + j * 16 * 128 + fo0);
+        fb[j][1] = *(const u32x4*)(sB + j * 16 * 128 + fo1);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) mfma_chunk<P>(acc[i][j], fa[i], fb[j]);
+    };
+
+    // one K step: wait for chunk k, publish it, refill the stage freed by
+    // chunk k-1 with chunk k+2, then consume chunk k
+    // A bare s_barrier, not __syncthreads(): the latter's workgroup fence would
+    // wait for every outstanding DMA, including the two chunks being prefetched.
+    // This wave's DMAs for chunk k are complete after the explicit vmcnt wait,
+    // and its LDS reads of the stage being refilled were consumed by MFMAs
+    // issued before the barrier.
+    // Every step issues exactly one chunk of DMAs (past the end it reloads the
+    // last chunk into a stage nobody reads again), so the number of DMAs in
+    // flight is always the same and the steady-state loop has no branches that
+    // would make the compiler give up tracking which stage each DMA writes.
+    auto kstep = [&](const uint8_t* cur, uint8_t* nxt, int k) {
+      wait_vmcnt_lds<NI>();
+      __builtin_amdgcn_s_barrier();
+      issue(nxt, min(k + 2, nk - 1));
+      compute(cur);
+    };
+
+    wait_vmcnt_lds<63>();
+    __builtin_amdgcn_s_barrier();  // the previous tile's last reads of the stages are done
+    issue(st0, 0);
+    issue(st1, min(1, nk - 1));
+    int kc = 0;
+    for (; kc + 3 <= nk; kc += 3) {
+      kstep(st0, st2, kc);
+      kstep(st1, st0, kc + 1);
+      kstep(st2, st1, kc + 2);
+    }
+    if (kc < nk) kstep(st0, st2, kc);
+    if (kc + 1 < nk) kstep(st1, st0, kc + 1);
+    gemm_epilogue<BM, BN, WM, WN, P, EPI>(acc, td, I, parity, lane, wm, wn);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // no DMA into LDS may outlive the workgroup
 }
 
 // ---------------------------------------------------------------- tile table
 
+// id, block tile BM x BN, waves WM x WN, main loop (0: register-staged double
+// buffer, 1: three-stage direct-to-LDS pipeline)
 #define PDBO_TILE_CFGS(X)      \
-  X(0, 128, 128, 2, 2)         \
-  X(1, 64, 64, 2, 2)           \
-  X(2, 256, 128, 4, 2)         \
-  X(3, 128, 256, 2, 4)         \
-  X(4, 160, 256, 2, 2)         \
-  X(5, 192, 256, 2, 2)
+  X(0, 128, 128, 2, 2, 0)      \
+  X(1, 64, 64, 2, 2, 0)        \
+  X(2, 256, 128, 4, 2, 0)      \
+  X(3, 128, 256, 2, 4, 0)      \
+  X(4, 160, 256, 2, 2, 0)      \
+  X(5, 192, 256, 2, 2, 0)      \
+  X(6, 160, 256, 2, 2, 1)      \
+  X(7, 128, 128, 2, 2, 1)      \
+  X(8, 256, 128, 4, 2, 1)      \
+  X(9, 64, 64, 2, 2, 1)
 
 static const TileCfgInfo kCfgs[] = {
-#define X(id, bm, bn, wm, wn) {#bm "x" #bn "_w" #wm "x" #wn, bm, bn, wm, wn, 64 * wm * wn},
+#define X(id, bm, bn, wm, wn, dma) \
+  {#bm "x" #bn "_w" #wm "x" #wn "_" #dma, bm, bn, wm, wn, 64 * wm * wn, dma},
     PDBO_TILE_CFGS(X)
 #undef X
 };
@@ -319,53 +502,55 @@ static const TileCfgInfo kCfgs[] = {
 int dense_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 const TileCfgInfo& dense_cfg(int id) { return kCfgs[id]; }
 
-template <int BM, int BN, int WM, int WN, int P, int EPI>
+template <int BM, int BN, int WM, int WN, int P, int EPI, int DMA>
 static hipError_t launch_one(const TileDev* tiles, int ntiles, const InstDev* insts, int parity,
                              int grid, hipStream_t s) {
-  constexpr int lds = gemm_lds_bytes<BM, BN>();
-  auto kern = dense_gemm<BM, BN, WM, WN, P, EPI>;
-  static bool attr_done = false;
-  if (!attr_done) {
-    hipError_t e =
-        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    attr_done = true;
-  }
   if (grid <= 0 || grid > ntiles) grid = ntiles;
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds, s, tiles, ntiles, insts, parity);
+  if constexpr (DMA) {
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL((dense_gemm_dma<BM, BN, WM, WN, P, EPI>), dim3(grid), dim3(64 * WM * WN), 0,
+                       s, tiles, ntiles, insts, parity);
+  } else {
+    constexpr int lds = gemm_lds_bytes<BM, BN>();
+    auto kern = dense_gemm<BM, BN, WM, WN, P, EPI>;
+    static bool attr_done = false;
+    if (!attr_done) {
+      hipError_t e =
+          hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      if (e != hipSuccess) return e;
+      attr_done = true;
+    }
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds, s, tiles, ntiles, insts, parity);
+  }
   return hipGetLastError();
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int DMA>
 static hipError_t launch_cfg(int prec, int epi, const TileDev* tiles, int ntiles,
                              const InstDev* insts, int parity, int grid, hipStream_t s) {
-  if (epi == EPI_EVAL)
-    return launch_one<BM, BN, WM, WN, P_I8, EPI_EVAL>(tiles, ntiles, insts, parity, grid, s);
+#define PDBO_L(P, E) launch_one<BM, BN, WM, WN, P, E, DMA>(tiles, ntiles, insts, parity, grid, s)
+  if (epi == EPI_EVAL) return PDBO_L(P_I8, EPI_EVAL);
   switch (prec * 2 + epi) {
-    case P_F32 * 2 + EPI_STEP:
-      return launch_one<BM, BN, WM, WN, P_F32, EPI_STEP>(tiles, ntiles, insts, parity, grid, s);
-    case P_F32 * 2 + EPI_GRAD:
-      return launch_one<BM, BN, WM, WN, P_F32, EPI_GRAD>(tiles, ntiles, insts, parity, grid, s);
-    case P_BF16 * 2 + EPI_STEP:
-      return launch_one<BM, BN, WM, WN, P_BF16, EPI_STEP>(tiles, ntiles, insts, parity, grid, s);
-    case P_BF16 * 2 + EPI_GRAD:
-      return launch_one<BM, BN, WM, WN, P_BF16, EPI_GRAD>(tiles, ntiles, insts, parity, grid, s);
-    case P_FP8 * 2 + EPI_STEP:
-      return launch_one<BM, BN, WM, WN, P_FP8, EPI_STEP>(tiles, ntiles, insts, parity, grid, s);
-    case P_FP8 * 2 + EPI_GRAD:
-      return launch_one<BM, BN, WM, WN, P_FP8, EPI_GRAD>(tiles, ntiles, insts, parity, grid, s);
-    default:
-      return hipErrorInvalidValue;
+    case P_F32 * 2 + EPI_STEP: return PDBO_L(P_F32, EPI_STEP);
+    case P_F32 * 2 + EPI_GRAD: return PDBO_L(P_F32, EPI_GRAD);
+    case P_BF16 * 2 + EPI_STEP: return PDBO_L(P_BF16, EPI_STEP);
+    case P_BF16 * 2 + EPI_GRAD: return PDBO_L(P_BF16, EPI_GRAD);
+    case P_FP8 * 2 + EPI_STEP: return PDBO_L(P_FP8, EPI_STEP);
+    case P_FP8 * 2 + EPI_GRAD: return PDBO_L(P_FP8, EPI_GRAD);
+    case P_I8 * 2 + EPI_STEP: return PDBO_L(P_I8, EPI_STEP);
+    case P_I8 * 2 + EPI_GRAD: return PDBO_L(P_I8, EPI_GRAD);
+    default: return hipErrorInvalidValue;
   }
+#undef PDBO_L
 }
 
 hipError_t launch_dense_gemm(int cfg, int prec, int epi, const TileDev* tiles, int ntiles,
                              const InstDev* insts, int parity, int grid, hipStream_t s) {
   switch (cfg) {
-#define X(id, bm, bn, wm, wn) \
-  case id:                    \
-    return launch_cfg<bm, bn, wm, wn>(prec, epi, tiles, ntiles, insts, parity, grid, s);
+#define X(id, bm, bn, wm, wn, dma) \
+  case id:                         \
+    return launch_cfg<bm, bn, wm, wn, dma>(prec, epi, tiles, ntiles, insts, parity, grid, s);
     PDBO_TILE_CFGS(X)
 #undef X
     default:
@@ -466,6 +651,8 @@ __device__ __forceinline__ void store_shadow(uint8_t* Xs, size_t off, float v, i
     ((uint16_t*)Xs)[off] = f32_to_bf16_rne(v);
   } else if (prec == P_FP8) {
     Xs[off] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xff);
+  } else if (prec == P_I8) {
+    Xs[off] = (uint8_t)quant8(v);
   }
 }
 

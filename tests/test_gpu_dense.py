@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 # normwise gradient tolerances: 1e-5 (fp32) and 1e-2 (bf16) as required for
 # the hot path; fp8 (3 mantissa bits on both operands) is measured and held to
 # a loose bound
-GTOL = {"fp32": 1e-5, "bf16": 1e-2, "fp8": 1e-1}
+GTOL = {"fp32": 1e-5, "bf16": 1e-2, "fp8": 1e-1, "i8": 1e-2}
 
 
 def _cases():
@@ -37,7 +37,7 @@ def _scale(q, s):
     return W.qubo_scale(q) if s is None else s
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "i8"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_gradient_parity(name, prec):
     P = require_gpu()
@@ -54,7 +54,7 @@ def test_gradient_parity(name, prec):
     assert err <= GTOL[prec], err
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tile", list(range(1, 11)))
 def test_gradient_parity_every_tile(tile):
     P = require_gpu()
     q = W.random_dense_qubo(517, -100, 100, W.rng_for(3, 1, 0, 517))
@@ -62,14 +62,14 @@ def test_gradient_parity_every_tile(tile):
     B = 150
     say(f"[dense grad tile] tile={tile} n={q.n} B={B}")
     x = W.x0_uniform(7, 1, B, q.n).astype(np.float32)
-    for prec in ("fp32", "bf16"):
+    for prec in ("fp32", "bf16", "i8"):
         ctx = P.qubo_gda_init(q, W.gda_params("qubo", B=B, T=1, scale=s, precision=prec, tile=tile),
                               x.astype(np.float64))
         err = normwise(ctx.grad(x), oq.grad_f(*oq.canonicalize(q), x.astype(np.float64), s))
         assert err <= GTOL[prec], (tile, prec, err)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "i8"])
 @pytest.mark.parametrize("name", ["gnp_n200", "dense_u100_n700", "asym_diag_n150", "n7_B3"])
 def test_lockstep_iteration(name, prec):
     P = require_gpu()
@@ -147,7 +147,7 @@ def test_twin_reaches_brute_force_optimum(rep):
     P = require_gpu()
     q = W.qubo_c1_twin(rep)
     Fstar, _ = en.brute_force(lambda X: oq.objective(q, X), q.n)
-    for prec in ("fp32", "bf16"):
+    for prec in ("fp32", "bf16", "i8"):
         r = P.qubo_gda_solve(q, W.gda_params("maxcut", B=16, T=1000, precision=prec),
                              W.x0_uniform(1, rep, 16, q.n, q.n), 1000)
         assert r["best_obj"] == Fstar, (rep, prec)
