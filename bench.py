@@ -295,6 +295,9 @@ def main():
                     help="c3 (default) is the headline dense n=10k line; the others report "
                          "the sparse, batched and MaxSAT configurations")
     ap.add_argument("--c4-prec", default="bf16")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (the reference for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); restarts shard trivially "
@@ -309,6 +312,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = 256 * 1024 * 1024
+        src = torch.rand(nbytes // 4, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes_per_dispatch=nbytes, dispatches=3)), flush=True)
+        return
     P.load()
     if args.workload != "c3":
         fn = {"c2": workload_c2, "c4": workload_c4, "c5": workload_c5}[args.workload]

@@ -1004,7 +1004,7 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
   CsrCanon C;
   STCHK(canon_csr(q, C));
   const int n = q->n;
-  const bool compact = n <= 65536 && C.amax <= 127;
+  const bool compact = n <= 65536 && C.amax <= 32767;  // packed 16-bit column / 16-bit value
   if (!csr_fits(n, (int64_t)C.col.size(), compact, nullptr))
     return fail(nullptr, PDBO_EUNSUPPORTED, "instance too large for the restart-resident CSR kernel");
   pdbo_ctx* c = new pdbo_ctx();
@@ -1029,28 +1029,23 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
     HIPCHK(c, hipMemcpyAsync(rp, C.rp.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream));
     d.row_ptr = rp;
     // host staging lives until the stream is synchronised at the end of init
-    std::vector<uint16_t> cc;
-    std::vector<int8_t> vv;
+    std::vector<uint32_t> pk;
+    int32_t* col = nullptr;
+    int32_t* val = nullptr;
+    STCHK(dalloc(c, &col, nnz));
+    STCHK(dalloc(c, &val, nnz));
+    HIPCHK(c, hipMemcpyAsync(col, C.col.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(val, C.val.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
+    d.col = col;
+    d.val = val;
     if (compact) {
-      cc.assign(C.col.begin(), C.col.end());
-      vv.assign(C.val.begin(), C.val.end());
-      uint16_t* col = nullptr;
-      int8_t* val = nullptr;
-      STCHK(dalloc(c, &col, nnz));
-      STCHK(dalloc(c, &val, nnz));
-      HIPCHK(c, hipMemcpyAsync(col, cc.data(), nnz * 2, hipMemcpyHostToDevice, c->stream));
-      HIPCHK(c, hipMemcpyAsync(val, vv.data(), nnz, hipMemcpyHostToDevice, c->stream));
-      d.col = col;
-      d.val = val;
-    } else {
-      int32_t* col = nullptr;
-      int32_t* val = nullptr;
-      STCHK(dalloc(c, &col, nnz));
-      STCHK(dalloc(c, &val, nnz));
-      HIPCHK(c, hipMemcpyAsync(col, C.col.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
-      HIPCHK(c, hipMemcpyAsync(val, C.val.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
-      d.col = col;
-      d.val = val;
+      pk.resize(nnz);
+      for (int64_t q = 0; q < nnz; ++q)
+        pk[q] = (uint32_t)C.col[q] | ((uint32_t)(uint16_t)(int16_t)C.val[q] << 16);
+      uint32_t* dp = nullptr;
+      STCHK(dalloc(c, &dp, nnz));
+      HIPCHK(c, hipMemcpyAsync(dp, pk.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
+      d.packed = dp;
     }
     std::vector<float> hcps(ld, 0.f);
     std::vector<int64_t> hcp(ld, 0);
@@ -1280,7 +1275,7 @@ pdbo_status qubo_gda_grad(pdbo_ctx* c, const float* x, float* G) {
     ld = c->csr.ld;
     HIPCHK(c, launch_set_state((const float*)tx.p, nullptr, c->B, n, ld, c->gx_scratch, nullptr,
                                nullptr, P_F32, c->stream));
-    HIPCHK(c, launch_csr_grad(c->csr, c->compact, c->gx_scratch, c->g_scratch, c->B, c->stream));
+    HIPCHK(c, launch_csr_grad(c->csr, c->gx_scratch, c->g_scratch, c->B, c->stream));
   } else {
     ld = c->sat.ld;
     HIPCHK(c, launch_set_state((const float*)tx.p, nullptr, c->B, n, ld, c->gx_scratch, nullptr,
@@ -1318,7 +1313,7 @@ pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F
                                 c->scratch_inst_d, 0, 0, c->stream));
     HIPCHK(c, launch_argmin(c->scratch_inst_d, 0, 1, 2, c->stream));
   } else if (c->kind == 1) {
-    HIPCHK(c, launch_csr_eval(c->csr, c->compact, c->xr_scratch, nb, c->f_scratch, c->stream));
+    HIPCHK(c, launch_csr_eval(c->csr, c->xr_scratch, nb, c->f_scratch, c->stream));
   } else {
     HIPCHK(c, launch_sat_eval(c->sat, c->xr_scratch, nb, c->f_scratch, c->stream));
   }
@@ -1413,6 +1408,7 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
       inc[(size_t)e * k + (k - 1)] = meta;
     }
 
+  std::vector<uint64_t> inc3;  // host staging of the compact entries, alive until init syncs
   pdbo_ctx* c = new pdbo_ctx();
   c->kind = 2;
   c->n_of.push_back(n);
@@ -1441,6 +1437,22 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
     d.inc = di;
     d.lits = dl;
     d.w = dw;
+    if (k == 3) {
+      // compact 3-SAT entries: 16-bit codes (variable | negated << 15), n <= 32768
+      inc3.resize(ptr[n]);
+      auto c16 = [](int32_t code) {
+        return (uint32_t)(code & 0x7fffffff) | ((code < 0 ? 1u : 0u) << 15);
+      };
+      for (int e = 0; e < ptr[n]; ++e) {
+        const uint32_t lo = c16(inc[(size_t)e * 3]) | (c16(inc[(size_t)e * 3 + 1]) << 16);
+        inc3[e] = (uint64_t)lo | ((uint64_t)(uint32_t)inc[(size_t)e * 3 + 2] << 32);
+      }
+      uint64_t* d3 = nullptr;
+      STCHK(dalloc(c, &d3, inc3.size()));
+      HIPCHK(c, hipMemcpyAsync(d3, inc3.data(), inc3.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
+                               c->stream));
+      d.inc3 = d3;
+    }
     STCHK(dalloc(c, &d.X, (size_t)B * ld));
     STCHK(dalloc(c, &d.Y, (size_t)B * ld));
     STCHK(dalloc(c, &d.rbestF, B));

@@ -137,8 +137,9 @@ hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t cnt, hipStream_t s);
 
 struct CsrDev {
   const int32_t* row_ptr;
-  const void* col;        // uint16 or int32
-  const void* val;        // int8 or int32
+  const void* col;        // int32 column indices
+  const void* val;        // int32 values of Ahat
+  const uint32_t* packed; // column | value << 16 when n <= 65536 and |Ahat_ij| < 2^15
   const float* cps;
   const int64_t* cp;
   float* X;               // [B][ld]
@@ -153,13 +154,11 @@ struct CsrDev {
   float kos;
   GdaP gp;
 };
-bool csr_fits(int n, int64_t nnz, bool compact, size_t* lds_bytes);
-hipError_t launch_csr_persistent(const CsrDev& d, bool compact, int64_t t0, int nsteps,
+bool csr_fits(int n, int64_t nnz, bool packed, size_t* lds_bytes);
+hipError_t launch_csr_persistent(const CsrDev& d, bool packed, int64_t t0, int nsteps,
                                  hipStream_t s);
-hipError_t launch_csr_grad(const CsrDev& d, bool compact, const float* X, float* G, int nb,
-                           hipStream_t s);
-hipError_t launch_csr_eval(const CsrDev& d, bool compact, const int8_t* xr, int nb, int64_t* F,
-                           hipStream_t s);
+hipError_t launch_csr_grad(const CsrDev& d, const float* X, float* G, int nb, hipStream_t s);
+hipError_t launch_csr_eval(const CsrDev& d, const int8_t* xr, int nb, int64_t* F, hipStream_t s);
 
 // Reduction of per-restart bests to the incumbent (persistent paths).
 hipError_t launch_restart_best(const int64_t* rbestF, const int64_t* rbestT,
@@ -171,6 +170,7 @@ hipError_t launch_restart_best(const int64_t* rbestF, const int64_t* rbestT,
 struct SatDev {
   const int32_t* inc_ptr;   // [n+1] per-variable incidence ranges
   const int32_t* inc;       // entries of k int32: (k-1) other literal codes, then meta
+  const uint64_t* inc3;     // 3-SAT only: the same entries as (code | code << 16) | meta << 32
   const int32_t* lits;      // [m][k] literal codes (var | neg<<31)
   const int32_t* w;         // [m]
   float* X;                 // [B][ld]

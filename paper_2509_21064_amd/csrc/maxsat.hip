@@ -10,7 +10,9 @@
 // weight (bits 0-23), "this literal is negated" (bit 30) and "this is the first
 // literal of its clause" (bit 29); the exact weighted unsatisfied count of
 // round(x) is fused into the same pass by counting each clause at its first
-// literal.  Literal codes are (variable index) | (negated << 31).
+// literal.  Literal codes are (variable index) | (negated << 31); for 3-SAT the
+// persistent kernel reads a compact 8-byte copy of each entry (two 16-bit codes
+// and the meta word).
 #include <climits>
 
 #include "common.h"
@@ -56,7 +58,43 @@ __device__ __forceinline__ float sat_adjoint(const SatDev& D, const float* __res
   return g;
 }
 
-template <int NT, int RMAX>
+// 3-SAT occurrence entry in 8 bytes: the other two literals as 16-bit codes
+// (variable | negated << 15) in the low word, the meta word in the high word.
+__device__ __forceinline__ void sat3_term(uint64_t en, const float* __restrict__ xs, bool own_true,
+                                          bool want_eval, float& g, int64_t& unsat) {
+  const uint32_t codes = (uint32_t)en;
+  const uint32_t ca = codes & 0xffffu, cb = codes >> 16;
+  const float xa = xs[ca & 0x7fffu], xb = xs[cb & 0x7fffu];
+  const bool na = (ca >> 15) != 0, nb = (cb >> 15) != 0;
+  const float prod = (na ? xa : 1.f - xa) * (nb ? xb : 1.f - xb);
+  const int32_t meta = (int32_t)(en >> 32);
+  const float w = (float)(meta & 0xffffff);
+  const bool own_neg = (meta >> 30) & 1;
+  g = fmaf(own_neg ? w : -w, prod, g);
+  if (want_eval && ((meta >> 29) & 1) && ((xa > 0.5f) == na) && ((xb > 0.5f) == nb) &&
+      (own_true == own_neg))
+    unsat += (meta & 0xffffff);
+}
+
+__device__ __forceinline__ float sat3_adjoint(const SatDev& D, const float* __restrict__ xs, int i,
+                                              float xi, bool want_eval, int64_t& unsat) {
+  const __attribute__((address_space(1))) uint64_t* E =
+      (const __attribute__((address_space(1))) uint64_t*)D.inc3;
+  const int pe = D.inc_ptr[i + 1];
+  int e = D.inc_ptr[i];
+  const bool own_true = xi > 0.5f;
+  float g0 = 0.f, g1 = 0.f;
+  for (; e + 2 <= pe; e += 2) {
+    const uint64_t a = E[e];
+    const uint64_t b = E[e + 1];
+    sat3_term(a, xs, own_true, want_eval, g0, unsat);
+    sat3_term(b, xs, own_true, want_eval, g1, unsat);
+  }
+  if (e < pe) sat3_term(E[e], xs, own_true, want_eval, g0, unsat);
+  return g0 + g1;
+}
+
+template <bool K3, int NT, int RMAX>
 __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int nsteps) {
   constexpr int NW = NT / 64;
   extern __shared__ __attribute__((aligned(16))) float xs[];
@@ -89,7 +127,8 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
     for (int j = 0; j < RMAX; ++j) {
       const int i = tid + j * NT;
       if (i < n) {
-        const float g = sat_adjoint(D, xs, i, xr[j], ev, S);
+        const float g = K3 ? sat3_adjoint(D, xs, i, xr[j], ev, S)
+                           : sat_adjoint(D, xs, i, xr[j], ev, S);
         if (upd) {
           float a, c;
           gda_update(xr[j], yr[j], g * ios, gp, a, c);
@@ -149,9 +188,9 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
   }
 }
 
-template <int NT, int RMAX>
+template <bool K3, int NT, int RMAX>
 static hipError_t launch_sat_k(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
-  auto kern = sat_persistent<NT, RMAX>;
+  auto kern = sat_persistent<K3, NT, RMAX>;
   const size_t lds = align16s((size_t)d.n * 4);
   hipError_t e =
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -160,15 +199,23 @@ static hipError_t launch_sat_k(const SatDev& d, int64_t t0, int nsteps, hipStrea
   return hipGetLastError();
 }
 
+// 1024 threads per restart (sixteen waves of gathers in flight) up to 8
+// variables per thread, 512 threads with a larger register budget beyond.
+template <bool K3>
+static hipError_t launch_sat_r(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
+  const int r = (d.n + 1023) / 1024;
+  if (r <= 4) return launch_sat_k<K3, 1024, 4>(d, t0, nsteps, s);
+  if (r <= 8) return launch_sat_k<K3, 1024, 8>(d, t0, nsteps, s);
+  const int r2 = (d.n + 511) / 512;
+  if (r2 <= 40) return launch_sat_k<K3, 512, 40>(d, t0, nsteps, s);
+  if (r2 <= 64) return launch_sat_k<K3, 512, 64>(d, t0, nsteps, s);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_sat_persistent(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
   if (nsteps <= 0) return hipSuccess;
-  const int r = (d.n + 511) / 512;
-  if (r <= 8) return launch_sat_k<512, 8>(d, t0, nsteps, s);
-  if (r <= 16) return launch_sat_k<512, 16>(d, t0, nsteps, s);
-  if (r <= 32) return launch_sat_k<512, 32>(d, t0, nsteps, s);
-  if (r <= 48) return launch_sat_k<512, 48>(d, t0, nsteps, s);
-  if (r <= 64) return launch_sat_k<512, 64>(d, t0, nsteps, s);
-  return hipErrorInvalidValue;
+  if (d.inc3) return launch_sat_r<true>(d, t0, nsteps, s);
+  return launch_sat_r<false>(d, t0, nsteps, s);
 }
 
 // ---- adjoint at given points: gradient (mode 0) or Lagrangian backward (mode 1)

@@ -19,29 +19,79 @@ namespace pdbo {
 
 __host__ __device__ static inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
-static size_t csr_lds_need(int n, int64_t nnz, bool compact, bool with_csr) {
+static size_t csr_lds_need(int n, int64_t nnz, bool packed) {
   size_t b = align16((size_t)n * 4);
-  if (with_csr) {
-    b += align16((size_t)(n + 1) * 4);
-    b += align16((size_t)nnz * (compact ? 2 : 4));
-    b += align16((size_t)nnz * (compact ? 1 : 4));
-  }
+  if (packed) b += align16((size_t)(n + 1) * 4) + align16((size_t)nnz * 4);
   return b;
 }
 
 constexpr size_t kLdsBudget = 150 * 1024;
 
 // The persistent kernel needs x of one restart in LDS and at most 32768 rows
-// (1024 threads x 32 rows in registers); the CSR arrays are staged in LDS when
-// they fit as well and are read through the L2 otherwise.
-bool csr_fits(int n, int64_t nnz, bool compact, size_t* lds_bytes) {
-  const bool with_csr = csr_lds_need(n, nnz, compact, true) <= kLdsBudget;
-  const size_t need = csr_lds_need(n, nnz, compact, with_csr);
+// (1024 threads x 32 rows in registers).  With packed entries (16-bit column,
+// 16-bit value) the whole canonical matrix is staged in LDS too when it fits;
+// otherwise the CSR arrays are read through the L2.
+bool csr_fits(int n, int64_t nnz, bool packed, size_t* lds_bytes) {
+  const bool in_lds = packed && csr_lds_need(n, nnz, true) <= kLdsBudget;
+  const size_t need = csr_lds_need(n, nnz, in_lds);
   if (lds_bytes) *lds_bytes = need;
   return n <= 32768 && need <= kLdsBudget;
 }
 
-template <typename ColT, typename ValT, bool CSR_LDS, int NT, int RMAX>
+// sum_k Ahat_ik x_k (float) and sum_k Ahat_ik [x_k > 1/2] (int) over row i,
+// four entries at a time so that their LDS reads are in flight together.
+template <bool PACKED>
+__device__ __forceinline__ void row_gather(int i, const int32_t* __restrict__ rp,
+                                           const uint32_t* __restrict__ ent,
+                                           const int32_t* __restrict__ col,
+                                           const int32_t* __restrict__ val,
+                                           const float* __restrict__ xs, float& acc, int& accr) {
+  const int pe = rp[i + 1];
+  int p = rp[i];
+  float a0 = 0.f, a1 = 0.f;
+  int r0 = 0, r1 = 0;
+  for (; p + 4 <= pe; p += 4) {
+    int c[4], v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if constexpr (PACKED) {
+        const uint32_t e = ent[p + u];
+        c[u] = (int)(e & 0xffffu);
+        v[u] = (int)(int16_t)(e >> 16);
+      } else {
+        c[u] = col[p + u];
+        v[u] = val[p + u];
+      }
+    }
+    float xk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xk[u] = xs[c[u]];
+    a0 = fmaf((float)v[0], xk[0], a0);
+    a1 = fmaf((float)v[1], xk[1], a1);
+    a0 = fmaf((float)v[2], xk[2], a0);
+    a1 = fmaf((float)v[3], xk[3], a1);
+    r0 += (xk[0] > 0.5f ? v[0] : 0) + (xk[2] > 0.5f ? v[2] : 0);
+    r1 += (xk[1] > 0.5f ? v[1] : 0) + (xk[3] > 0.5f ? v[3] : 0);
+  }
+  for (; p < pe; ++p) {
+    int c, v;
+    if constexpr (PACKED) {
+      const uint32_t e = ent[p];
+      c = (int)(e & 0xffffu);
+      v = (int)(int16_t)(e >> 16);
+    } else {
+      c = col[p];
+      v = val[p];
+    }
+    const float xk = xs[c];
+    a0 = fmaf((float)v, xk, a0);
+    r0 += xk > 0.5f ? v : 0;
+  }
+  acc = a0 + a1;
+  accr = r0 + r1;
+}
+
+template <bool PACKED, int NT, int RMAX>
 __global__ void __launch_bounds__(NT)
     csr_persistent(CsrDev D, int64_t t0, int nsteps) {
   constexpr int NW = NT / 64;
@@ -52,23 +102,18 @@ __global__ void __launch_bounds__(NT)
   const int n = D.n;
   float* xs = (float*)lds;
   const int32_t* rp = D.row_ptr;
-  const ColT* col = (const ColT*)D.col;
-  const ValT* val = (const ValT*)D.val;
-  if constexpr (CSR_LDS) {
+  const uint32_t* ent = D.packed;
+  if constexpr (PACKED) {
     int32_t* rpl = (int32_t*)(lds + align16((size_t)n * 4));
+    uint32_t* entl = (uint32_t*)((uint8_t*)rpl + align16((size_t)(n + 1) * 4));
     const int nnz = (int)D.nnz;
-    ColT* coll = (ColT*)((uint8_t*)rpl + align16((size_t)(n + 1) * 4));
-    ValT* vall = (ValT*)((uint8_t*)coll + align16((size_t)nnz * sizeof(ColT)));
-    for (int p = tid; p <= n; p += NT) rpl[p] = D.row_ptr[p];
-    for (int p = tid; p < nnz; p += NT) {
-      coll[p] = col[p];
-      vall[p] = val[p];
-    }
+    for (int q = tid; q <= n; q += NT) rpl[q] = D.row_ptr[q];
+    for (int q = tid; q < nnz; q += NT) entl[q] = D.packed[q];
     rp = rpl;
-    col = coll;
-    val = vall;
+    ent = entl;
   }
-  const float* Xg = D.X + (size_t)b * D.ld;
+  const int32_t* col = (const int32_t*)D.col;
+  const int32_t* val = (const int32_t*)D.val;
   float xr[RMAX], yr[RMAX], xn[RMAX];
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
@@ -76,7 +121,7 @@ __global__ void __launch_bounds__(NT)
     xr[j] = 0.f;
     yr[j] = 0.f;
     if (i < n) {
-      xr[j] = Xg[i];
+      xr[j] = D.X[(size_t)b * D.ld + i];
       yr[j] = D.Y[(size_t)b * D.ld + i];
       xs[i] = xr[j];
     }
@@ -96,15 +141,9 @@ __global__ void __launch_bounds__(NT)
     for (int j = 0; j < RMAX; ++j) {
       const int i = tid + j * NT;
       if (i < n) {
-        float acc = 0.f;
-        int accr = 0;
-        const int pe = rp[i + 1];
-        for (int p = rp[i]; p < pe; ++p) {
-          const float xk = xs[col[p]];
-          const int v = (int)val[p];
-          acc = fmaf((float)v, xk, acc);
-          accr += xk > 0.5f ? v : 0;
-        }
+        float acc;
+        int accr;
+        row_gather<PACKED>(i, rp, ent, col, val, xs, acc, accr);
         if (ev && xr[j] > 0.5f) {
           S += accr;
           C += D.cp[i];
@@ -178,14 +217,10 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-template <typename ColT, typename ValT, bool CSR_LDS, int NT, int RMAX>
-static hipError_t launch_csr_k(const CsrDev& d, int64_t nnz, int64_t t0, int nsteps,
-                               hipStream_t s) {
-  auto kern = csr_persistent<ColT, ValT, CSR_LDS, NT, RMAX>;
-  size_t lds = align16((size_t)d.n * 4);
-  if (CSR_LDS)
-    lds += align16((size_t)(d.n + 1) * 4) + align16((size_t)nnz * sizeof(ColT)) +
-           align16((size_t)nnz * sizeof(ValT));
+template <bool PACKED, int NT, int RMAX>
+static hipError_t launch_csr_k(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
+  auto kern = csr_persistent<PACKED, NT, RMAX>;
+  const size_t lds = csr_lds_need(d.n, d.nnz, PACKED);
   hipError_t e =
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -193,36 +228,36 @@ static hipError_t launch_csr_k(const CsrDev& d, int64_t nnz, int64_t t0, int nst
   return hipGetLastError();
 }
 
-template <typename ColT, typename ValT, bool CSR_LDS>
-static hipError_t launch_csr_r(const CsrDev& d, int64_t nnz, int64_t t0, int nsteps,
-                               hipStream_t s) {
-  const int r = (d.n + 255) / 256;
-  if (r <= 8) return launch_csr_k<ColT, ValT, CSR_LDS, 256, 8>(d, nnz, t0, nsteps, s);
-  if (r <= 16) return launch_csr_k<ColT, ValT, CSR_LDS, 256, 16>(d, nnz, t0, nsteps, s);
-  if (r <= 32) return launch_csr_k<ColT, ValT, CSR_LDS, 256, 32>(d, nnz, t0, nsteps, s);
-  if (r <= 64) return launch_csr_k<ColT, ValT, CSR_LDS, 256, 64>(d, nnz, t0, nsteps, s);
-  if (r <= 128) return launch_csr_k<ColT, ValT, CSR_LDS, 1024, 32>(d, nnz, t0, nsteps, s);
+// 1024 threads per restart (sixteen waves keep enough LDS gathers in flight)
+// up to 8 rows per thread; beyond that 512 threads, whose larger register
+// budget holds up to 64 rows per thread without spilling.
+template <bool PACKED>
+static hipError_t launch_csr_r(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
+  const int r = (d.n + 1023) / 1024;
+  if (r <= 1) return launch_csr_k<PACKED, 1024, 1>(d, t0, nsteps, s);
+  if (r <= 2) return launch_csr_k<PACKED, 1024, 2>(d, t0, nsteps, s);
+  if (r <= 4) return launch_csr_k<PACKED, 1024, 4>(d, t0, nsteps, s);
+  if (r <= 8) return launch_csr_k<PACKED, 1024, 8>(d, t0, nsteps, s);
+  const int r2 = (d.n + 511) / 512;
+  if (r2 <= 32) return launch_csr_k<PACKED, 512, 32>(d, t0, nsteps, s);
+  if (r2 <= 64) return launch_csr_k<PACKED, 512, 64>(d, t0, nsteps, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_csr_persistent(const CsrDev& d, bool compact, int64_t t0, int nsteps,
+hipError_t launch_csr_persistent(const CsrDev& d, bool packed, int64_t t0, int nsteps,
                                  hipStream_t s) {
   if (nsteps <= 0) return hipSuccess;
-  const int64_t nnz = d.nnz;
-  const size_t need = csr_lds_need(d.n, nnz, compact, true);
-  if (need <= kLdsBudget) {
-    if (compact) return launch_csr_r<uint16_t, int8_t, true>(d, nnz, t0, nsteps, s);
-    return launch_csr_r<int32_t, int32_t, true>(d, nnz, t0, nsteps, s);
-  }
-  if (compact) return launch_csr_r<uint16_t, int8_t, false>(d, nnz, t0, nsteps, s);
-  return launch_csr_r<int32_t, int32_t, false>(d, nnz, t0, nsteps, s);
+  if (packed && csr_lds_need(d.n, d.nnz, true) <= kLdsBudget)
+    return launch_csr_r<true>(d, t0, nsteps, s);
+  return launch_csr_r<false>(d, t0, nsteps, s);
 }
 
 // ---- gradient and exact evaluation at given points (tests, qubo_gda_grad/eval)
 
-template <typename ColT, typename ValT>
 __global__ void csr_grad_kernel(CsrDev D, const float* __restrict__ X, float* __restrict__ G,
                                 int nb) {
+  using ColT = int32_t;
+  using ValT = int32_t;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nb * D.n) return;
   const int b = (int)(idx / D.n), i = (int)(idx % D.n);
@@ -234,9 +269,10 @@ __global__ void csr_grad_kernel(CsrDev D, const float* __restrict__ X, float* __
   G[(size_t)b * D.ld + i] = fmaf(acc, D.kos, D.cps[i]);
 }
 
-template <typename ColT, typename ValT>
 __global__ void __launch_bounds__(256)
     csr_eval_kernel(CsrDev D, const int8_t* __restrict__ xr, int64_t* __restrict__ F) {
+  using ColT = int32_t;
+  using ValT = int32_t;
   __shared__ int64_t red[4][2];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int8_t* x = xr + (size_t)b * D.ld;
@@ -269,25 +305,17 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-hipError_t launch_csr_grad(const CsrDev& d, bool compact, const float* X, float* G, int nb,
-                           hipStream_t s) {
+hipError_t launch_csr_grad(const CsrDev& d, const float* X, float* G, int nb, hipStream_t s) {
   const size_t tot = (size_t)nb * d.n;
   if (tot == 0) return hipSuccess;
   const dim3 grid((unsigned)((tot + 255) / 256));
-  if (compact)
-    hipLaunchKernelGGL((csr_grad_kernel<uint16_t, int8_t>), grid, dim3(256), 0, s, d, X, G, nb);
-  else
-    hipLaunchKernelGGL((csr_grad_kernel<int32_t, int32_t>), grid, dim3(256), 0, s, d, X, G, nb);
+  hipLaunchKernelGGL(csr_grad_kernel, grid, dim3(256), 0, s, d, X, G, nb);
   return hipGetLastError();
 }
 
-hipError_t launch_csr_eval(const CsrDev& d, bool compact, const int8_t* xr, int nb, int64_t* F,
-                           hipStream_t s) {
+hipError_t launch_csr_eval(const CsrDev& d, const int8_t* xr, int nb, int64_t* F, hipStream_t s) {
   if (nb == 0) return hipSuccess;
-  if (compact)
-    hipLaunchKernelGGL((csr_eval_kernel<uint16_t, int8_t>), dim3(nb), dim3(256), 0, s, d, xr, F);
-  else
-    hipLaunchKernelGGL((csr_eval_kernel<int32_t, int32_t>), dim3(nb), dim3(256), 0, s, d, xr, F);
+  hipLaunchKernelGGL(csr_eval_kernel, dim3(nb), dim3(256), 0, s, d, xr, F);
   return hipGetLastError();
 }
 
