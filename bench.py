@@ -50,9 +50,9 @@ def read_traffic(form, n, B):
         return None
     kv = {}
     for line in open(p):
-        if ":" in line:
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
+        for key in ("dense.hip sha256[:16]", "hbm_bytes_per_launch"):
+            if line.startswith(key + ":"):
+                kv[key] = line[len(key) + 1:].strip()
     if kv.get("dense.hip sha256[:16]") != dense_source_hash():
         return None
     try:
