@@ -82,6 +82,37 @@ __device__ __forceinline__ void mfma_chunk<P_I8>(i32x4& c, const u32x4 (&a)[2],
                                               __builtin_bit_cast(i32x4, b[h]), c, 0, 0, 0);
 }
 
+// Half of a 128-byte K chunk (the 16 bytes a lane holds of one fragment row):
+// the software-pipelined main loop issues the MFMAs of one half while it reads
+// the other half's fragments.  Per accumulator the sequence of MFMAs is the
+// same as mfma_chunk's (half 0, then half 1 of every chunk).  FP8 has no half
+// form: its single MFMA per chunk consumes all 32 bytes of a lane.
+template <int P> struct HasHalf { static constexpr bool value = P != P_FP8; };
+template <int P> struct HalfMfmas { static constexpr int value = P == P_F32 ? 4 : 1; };
+
+template <int P>
+__device__ __forceinline__ void mfma_half(typename PT<P>::Acc& c, const u32x4& a, const u32x4& b);
+
+template <>
+__device__ __forceinline__ void mfma_half<P_F32>(f32x4& c, const u32x4& a, const u32x4& b) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[s]), __uint_as_float(b[s]), c, 0, 0,
+                                             0);
+}
+
+template <>
+__device__ __forceinline__ void mfma_half<P_BF16>(f32x4& c, const u32x4& a, const u32x4& b) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                              __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ void mfma_half<P_I8>(i32x4& c, const u32x4& a, const u32x4& b) {
+  c = __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i32x4, a),
+                                            __builtin_bit_cast(i32x4, b), c, 0, 0, 0);
+}
+
 // x in [0,1] -> q = round(254 x) - 127 in [-127, 127] (x ~ (q + 127) / 254)
 __device__ __forceinline__ uint32_t quant8(float x) {
   return (uint32_t)(uint8_t)(int8_t)((int)rintf(x * 254.f) - 127);
@@ -132,19 +163,45 @@ __device__ __forceinline__ void gemm_epilogue(
     float* Xn = I.X[parity ^ 1];
     float* Yp = I.Y;
     uint8_t* Xsn = I.Xs[parity ^ 1];
-#pragma unroll
-    for (int fm = 0; fm < FM; ++fm) {
-      const int i = ibase + fm * 16;
-      if (i >= n) continue;
-      const f32x4 cs = *gptr((const f32x4*)(I.cps + i));
-      f32x4 sc = {kos, kos, kos, kos};
-      if constexpr (P == P_FP8) sc = sc * *gptr((const f32x4*)(I.rscale + i));
-      i32x4 off8 = {0, 0, 0, 0};
+    // Row group fm (16 rows of the wave tile) needs c'/s, the row scales and,
+    // for STEP, x and y at every (row, restart) of the group.  The loads of
+    // group fm+1 are issued before the stores of group fm: Y is updated in
+    // place, so the compiler may not move a load above an earlier store, and
+    // in plain program order every fragment would wait a full memory round
+    // trip.  Loads use clamped (always valid) offsets; only stores are guarded.
+    struct Rows {
+      f32x4 cs, sc;
+      i32x4 off8;
+      f32x4 x[FN], y[FN];
+    };
+    auto fetch = [&](int fm, Rows& r) {
+      const int ic = min(ibase + fm * 16, ld - 4);
+      r.cs = *gptr((const f32x4*)(I.cps + ic));
+      r.sc = f32x4{kos, kos, kos, kos};
+      if constexpr (P == P_FP8) r.sc = r.sc * *gptr((const f32x4*)(I.rscale + ic));
+      r.off8 = i32x4{0, 0, 0, 0};
       if constexpr (P == P_I8) {
         // A x ~ (A q + 127 A 1) / 254 for the quantised iterate q
-        sc = sc * (1.f / 254.f);
-        off8 = *gptr((const i32x4*)(I.rsum + i)) * 127;
+        r.sc = r.sc * (1.f / 254.f);
+        r.off8 = *gptr((const i32x4*)(I.rsum + ic)) * 127;
       }
+      if constexpr (EPI == EPI_STEP) {
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+          const size_t off = (size_t)min(bbase + fn * 16, B - 1) * ld + ic;
+          r.x[fn] = *gptr((const f32x4*)(Xc + off));
+          r.y[fn] = *gptr((const f32x4*)(Yp + off));
+        }
+      }
+    };
+    Rows rb[2];
+    fetch(0, rb[0]);
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm) {
+      if (fm + 1 < FM) fetch(fm + 1, rb[(fm + 1) & 1]);
+      const Rows& r = rb[fm & 1];
+      const int i = ibase + fm * 16;
+      if (i >= n) continue;
 #pragma unroll
       for (int fn = 0; fn < FN; ++fn) {
         const int b = bbase + fn * 16;
@@ -152,24 +209,24 @@ __device__ __forceinline__ void gemm_epilogue(
         const size_t off = (size_t)b * ld + i;
         f32x4 G;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int q = 0; q < 4; ++q) {
           if constexpr (P == P_I8)
-            G[r] = fmaf((float)(acc[fm][fn][r] + off8[r]), sc[r], cs[r]);
+            G[q] = fmaf((float)(acc[fm][fn][q] + r.off8[q]), r.sc[q], r.cs[q]);
           else
-            G[r] = fmaf(acc[fm][fn][r], sc[r], cs[r]);
+            G[q] = fmaf(acc[fm][fn][q], r.sc[q], r.cs[q]);
         }
         if constexpr (EPI == EPI_GRAD) {
           *gptr((f32x4*)(I.G + off)) = G;
         } else {
-          const f32x4 xv = *gptr((const f32x4*)(Xc + off));
-          const f32x4 yv = *gptr((const f32x4*)(Yp + off));
+          const f32x4 xv = r.x[fn];
+          const f32x4 yv = r.y[fn];
           f32x4 xo, yo;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
+          for (int q = 0; q < 4; ++q) {
             float a, c;
-            gda_update(xv[r], yv[r], G[r], gp, a, c);
-            xo[r] = a;
-            yo[r] = c;
+            gda_update(xv[q], yv[q], G[q], gp, a, c);
+            xo[q] = a;
+            yo[q] = c;
           }
           *gptr((f32x4*)(Xn + off)) = xo;
           *gptr((f32x4*)(Yp + off)) = yo;
@@ -194,20 +251,38 @@ __device__ __forceinline__ void gemm_epilogue(
     int64_t sS[FN], sC[FN];
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) sS[fn] = sC[fn] = 0;
+    // x_r and c' of row group fm+1 are fetched before group fm is reduced
+    // (clamped offsets; c' is zero-padded to ld), so the loads never wait
+    // behind the data-dependent selection of the previous group.
+    struct ERows {
+      int64_t cp[4];
+      uint32_t xr[FN];
+    };
+    auto fetch = [&](int fm, ERows& r) {
+      const int ic = min(ibase + fm * 16, ld - 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r.cp[q] = *gptr(I.cp + ic + q);
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+        r.xr[fn] = *gptr((const uint32_t*)(I.Xr + (size_t)min(bbase + fn * 16, B - 1) * ld + ic));
+    };
+    ERows rb[2];
+    fetch(0, rb[0]);
 #pragma unroll
     for (int fm = 0; fm < FM; ++fm) {
+      if (fm + 1 < FM) fetch(fm + 1, rb[(fm + 1) & 1]);
+      const ERows& r = rb[fm & 1];
       const int i = ibase + fm * 16;
       if (i >= n) continue;
 #pragma unroll
       for (int fn = 0; fn < FN; ++fn) {
         const int b = bbase + fn * 16;
         if (b >= B) continue;
-        const uint32_t xr = *gptr((const uint32_t*)(I.Xr + (size_t)b * ld + i));
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (((xr >> (8 * r)) & 1u) && (i + r < n)) {
-            sS[fn] += acc[fm][fn][r];
-            sC[fn] += *gptr(I.cp + i + r);
+        for (int q = 0; q < 4; ++q) {
+          if (((r.xr[fn] >> (8 * q)) & 1u) && (i + q < n)) {
+            sS[fn] += acc[fm][fn][q];
+            sC[fn] += r.cp[q];
           }
         }
       }
@@ -461,16 +536,81 @@ __global__ void __launch_bounds__(64 * WM * WN)
 
     wait_vmcnt_lds<63>();
     __builtin_amdgcn_s_barrier();  // the previous tile's last reads of the stages are done
-    issue(st0, 0);
-    issue(st1, min(1, nk - 1));
-    int kc = 0;
-    for (; kc + 3 <= nk; kc += 3) {
-      kstep(st0, st2, kc);
-      kstep(st1, st0, kc + 1);
-      kstep(st2, st1, kc + 2);
+    if constexpr (!HasHalf<P>::value) {
+      issue(st0, 0);
+      issue(st1, min(1, nk - 1));
+      int kc = 0;
+      for (; kc + 3 <= nk; kc += 3) {
+        kstep(st0, st2, kc);
+        kstep(st1, st0, kc + 1);
+        kstep(st2, st1, kc + 2);
+      }
+      if (kc < nk) kstep(st0, st2, kc);
+      if (kc + 1 < nk) kstep(st1, st0, kc + 1);
+    } else {
+      // Software pipeline over half chunks.  Entering step k, the registers
+      // f0 hold half 0 of chunk k.  First half: read half 1 of chunk k into
+      // f1 while the MFMAs on f0 run.  Then wait for this wave's DMAs of chunk
+      // k+1 and for its reads of f1, and pass the barrier: now every wave is
+      // done with the stage of chunk k and chunk k+1 is in LDS.  Second half:
+      // refill chunk k's stage with chunk k+3, and read half 0 of chunk k+1
+      // into f0 while the MFMAs on f1 run.  The sched_group_barrier chains
+      // spread the LDS reads and DMA issues between the MFMAs; left to itself
+      // the scheduler clusters the reads, and the MFMA pipe idles behind them.
+      constexpr int MPH = FM * FN * HalfMfmas<P>::value;  // MFMAs per half step
+      constexpr int NDS = FM + FN;                        // fragment reads per half step
+      constexpr int MF = MPH / NDS >= 3 ? 3 : (MPH / NDS >= 1 ? MPH / NDS : 1);
+      u32x4 f0a[FM], f0b[FN], f1a[FM], f1b[FN];
+      auto load = [&](u32x4 (&fa)[FM], u32x4 (&fb)[FN], const uint8_t* st, int fo) {
+        const uint8_t* sA = st + (wm * WTM) * 128;
+        const uint8_t* sB = st + (BM + wn * WTN) * 128;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) fa[i] = *(const u32x4*)(sA + i * 16 * 128 + fo);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) fb[j] = *(const u32x4*)(sB + j * 16 * 128 + fo);
+      };
+      auto mm = [&](const u32x4 (&fa)[FM], const u32x4 (&fb)[FN]) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) mfma_half<P>(acc[i][j], fa[i], fb[j]);
+      };
+      auto interleave = [&](bool with_dma) {
+#pragma unroll
+        for (int u = 0; u < NDS; ++u) {
+          if (with_dma && u < NI) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                          // DS read
+          if (MF * (u + 1) <= MPH) __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);  // MFMA
+        }
+        if (with_dma && NI > NDS) __builtin_amdgcn_sched_group_barrier(0x020, NI - NDS, 0);
+        if (MPH > MF * NDS) __builtin_amdgcn_sched_group_barrier(0x008, MPH - MF * NDS, 0);
+      };
+      auto pstep = [&](const uint8_t* cur, const uint8_t* nx, int k) {
+        load(f1a, f1b, cur, fo1);
+        mm(f0a, f0b);
+        interleave(false);
+        wait_vmcnt_lds<NI>();  // chunk k+1 landed; chunk k+2 may be in flight
+        __builtin_amdgcn_s_barrier();
+        issue((uint8_t*)cur, min(k + 3, nk - 1));
+        load(f0a, f0b, nx, fo0);  // past the last chunk: reads a stage nobody uses
+        mm(f1a, f1b);
+        interleave(true);
+      };
+      issue(st0, 0);
+      issue(st1, min(1, nk - 1));
+      issue(st2, min(2, nk - 1));
+      wait_vmcnt_lds<2 * NI>();
+      __builtin_amdgcn_s_barrier();
+      load(f0a, f0b, st0, fo0);
+      int kc = 0;
+      for (; kc + 3 <= nk; kc += 3) {
+        pstep(st0, st1, kc);
+        pstep(st1, st2, kc + 1);
+        pstep(st2, st0, kc + 2);
+      }
+      if (kc < nk) pstep(st0, st1, kc);
+      if (kc + 1 < nk) pstep(st1, st2, kc + 1);
     }
-    if (kc < nk) kstep(st0, st2, kc);
-    if (kc + 1 < nk) kstep(st1, st0, kc + 1);
     gemm_epilogue<BM, BN, WM, WN, P, EPI>(acc, td, I, parity, lane, wm, wn);
   }
   __builtin_amdgcn_s_waitcnt(0);  // no DMA into LDS may outlive the workgroup
