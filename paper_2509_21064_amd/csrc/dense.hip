@@ -302,6 +302,173 @@ __device__ __forceinline__ void gemm_epilogue(
   }
 }
 
+// STEP/GRAD epilogue through LDS, for the DMA kernel.  The fragment layout
+// gives a store instruction 16 restarts x 64 contiguous bytes; moving G
+// through LDS lets the whole workgroup walk each restart's BM contiguous
+// floats instead, which takes the x/y traffic from about 3.7 to 6.8 TB/s.
+// The tile is done in passes of PR restarts, whose G block fits in one stage
+// buffer (the stages must stay distinct LDS objects: over one array the
+// compiler cannot tell the DMA into one stage from the reads of another and
+// makes every DMA wait for all outstanding LDS reads).  Passes alternate
+// between two stage buffers, so one barrier per pass suffices.
+//   phase 1 of pass p: the waves owning restarts [PR p, PR p + PR) write G
+//            for those fragments, row = restart within the pass, 16-byte
+//            column group c (BM/4 per row) stored at (c & ~7) | ((c ^ row) & 7)
+//            so that the 16 restarts of one fragment store and the
+//            consecutive columns of one row read both hit distinct banks;
+//   phase 2 of pass p: element e = (row, c) goes to thread e mod NT.  x and y
+//            are fetched one group of PF elements ahead, across passes (y is
+//            updated in place, so the compiler keeps loads behind earlier
+//            stores and would otherwise wait a memory round trip per group).
+template <int BM, int BN, int STAGE>
+constexpr int rows_per_pass() {
+  return (64 * BM * 4 <= STAGE && BN % 64 == 0) ? 64 : (32 * BM * 4 <= STAGE && BN % 32 == 0) ? 32 : 16;
+}
+
+template <int BM, int BN, int WM, int WN, int P, int EPI, int STAGE>
+__device__ __forceinline__ void gemm_epilogue_rows(
+    typename PT<P>::Acc (&acc)[BM / WM / 16][BN / WN / 16], const TileDev& td, const InstDev& I,
+    int parity, int tid, int lane, int wm, int wn, uint8_t* buf0, uint8_t* buf1) {
+  static_assert(EPI == EPI_STEP || EPI == EPI_GRAD, "row epilogue is for STEP and GRAD");
+  constexpr int NT = 64 * WM * WN;
+  constexpr int WTM = BM / WM, WTN = BN / WN;
+  constexpr int FM = WTM / 16, FN = WTN / 16;
+  constexpr int C4 = BM / 4;                       // 16-byte column groups per tile row
+  constexpr int PR = rows_per_pass<BM, BN, STAGE>();
+  constexpr int NP = BN / PR;                      // passes
+  constexpr int EPP = PR * C4 / NT;                // elements per thread and pass
+  constexpr int PF = 2;                            // elements per prefetch group
+  constexpr int GPP = EPP / PF;                    // groups per pass
+  static_assert(PR * BM * 4 <= STAGE && BN % PR == 0 && PR % 16 == 0, "pass shape");
+  static_assert(C4 % 8 == 0 && (PR * C4) % NT == 0 && EPP % PF == 0, "row epilogue shape");
+  const int n = I.n, ld = I.ld, B = I.B;
+  // Opaque copies of the thread and lane ids: the index arithmetic below
+  // depends on nothing else, and hoisted above the main loop (whose registers
+  // are all in use) it would spill.
+  asm volatile("" : "+v"(tid), "+v"(lane));
+  auto slot = [](int row, int c) { return row * C4 + ((c & ~7) | ((c ^ row) & 7)); };
+
+  // scale and offset of every row group of the wave tile
+  const float kos = I.kos;
+  const int ibase = td.m0 + wm * WTM + 4 * (lane >> 4);
+  f32x4 cs[FM], sc[FM];
+  i32x4 off8[FM];
+#pragma unroll
+  for (int fm = 0; fm < FM; ++fm) {
+    const int ic = min(ibase + fm * 16, ld - 4);
+    cs[fm] = *gptr((const f32x4*)(I.cps + ic));
+    sc[fm] = f32x4{kos, kos, kos, kos};
+    if constexpr (P == P_FP8) sc[fm] = sc[fm] * *gptr((const f32x4*)(I.rscale + ic));
+    off8[fm] = i32x4{0, 0, 0, 0};
+    if constexpr (P == P_I8) {
+      // A x ~ (A q + 127 A 1) / 254 for the quantised iterate q
+      sc[fm] = sc[fm] * (1.f / 254.f);
+      off8[fm] = *gptr((const i32x4*)(I.rsum + ic)) * 127;
+    }
+  }
+  auto write_pass = [&](int p, uint8_t* buf) {
+    f32x4* G4 = (f32x4*)buf;
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) {
+      const int r0 = wn * WTN + 16 * fn;            // first restart of the fragment
+      if (r0 / PR != p) continue;                   // uniform over the wave
+      const int row = r0 - p * PR + (lane & 15);
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) {
+        const int c = (wm * WTM) / 4 + 4 * fm + (lane >> 4);
+        f32x4 G;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if constexpr (P == P_I8)
+            G[q] = fmaf((float)(acc[fm][fn][q] + off8[fm][q]), sc[fm][q], cs[fm][q]);
+          else
+            G[q] = fmaf(acc[fm][fn][q], sc[fm][q], cs[fm][q]);
+        }
+        G4[slot(row, c)] = G;
+      }
+    }
+  };
+
+  const GdaP gp = I.gp;
+  float* Xc = I.X[parity];
+  float* Xn = I.X[parity ^ 1];
+  float* Yp = I.Y;
+  uint8_t* Xsn = I.Xs[parity ^ 1];
+  struct Vals {
+    f32x4 x[PF], y[PF];
+  };
+  // element u of group g: pass g / GPP, index e = (g mod GPP) * PF + u within the
+  // thread's share of that pass
+  auto coords = [&](int g, int u, int& row, int& c) {
+    const int e = ((g % GPP) * PF + u) * NT + tid;
+    row = e / C4;
+    c = e % C4;
+  };
+  auto fetch = [&](int g, Vals& v) {
+    if constexpr (EPI == EPI_STEP) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        int row, c;
+        coords(g, u, row, c);
+        const int b = min(td.n0 + (g / GPP) * PR + row, B - 1);
+        const size_t off = (size_t)b * ld + min(td.m0 + 4 * c, ld - 4);
+        v.x[u] = *gptr((const f32x4*)(Xc + off));
+        v.y[u] = *gptr((const f32x4*)(Yp + off));
+      }
+    }
+  };
+  Vals vb[2];
+  fetch(0, vb[0]);
+#pragma unroll
+  for (int g = 0; g < NP * GPP; ++g) {
+    const int p = g / GPP;
+    uint8_t* buf = (p & 1) ? buf1 : buf0;
+    if (g % GPP == 0) {
+      write_pass(p, buf);
+      __syncthreads();
+    }
+    if (g + 1 < NP * GPP) fetch(g + 1, vb[(g + 1) & 1]);
+    const Vals& v = vb[g & 1];
+    const f32x4* G4 = (const f32x4*)buf;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      int row, c;
+      coords(g, u, row, c);
+      const int b = td.n0 + p * PR + row, i = td.m0 + 4 * c;
+      if (b >= B || i >= n) continue;
+      const size_t off = (size_t)b * ld + i;
+      const f32x4 G = G4[slot(row, c)];
+      if constexpr (EPI == EPI_GRAD) {
+        *gptr((f32x4*)(I.G + off)) = G;
+      } else {
+        f32x4 xo, yo;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float a, cc;
+          gda_update(v.x[u][q], v.y[u][q], G[q], gp, a, cc);
+          xo[q] = a;
+          yo[q] = cc;
+        }
+        *gptr((f32x4*)(Xn + off)) = xo;
+        *gptr((f32x4*)(Yp + off)) = yo;
+        const uint32_t xr = (uint32_t)(xo[0] > 0.5f) | ((uint32_t)(xo[1] > 0.5f) << 8) |
+                            ((uint32_t)(xo[2] > 0.5f) << 16) | ((uint32_t)(xo[3] > 0.5f) << 24);
+        *gptr((uint32_t*)(I.Xr + off)) = xr;
+        if constexpr (P == P_BF16) {
+          u32x2 w;
+          w.x = (uint32_t)f32_to_bf16_rne(xo[0]) | ((uint32_t)f32_to_bf16_rne(xo[1]) << 16);
+          w.y = (uint32_t)f32_to_bf16_rne(xo[2]) | ((uint32_t)f32_to_bf16_rne(xo[3]) << 16);
+          *gptr((u32x2*)(Xsn + off * 2)) = w;
+        } else if constexpr (P == P_FP8) {
+          *gptr((uint32_t*)(Xsn + off)) = pack_fp8x4(xo[0], xo[1], xo[2], xo[3]);
+        } else if constexpr (P == P_I8) {
+          *gptr((uint32_t*)(Xsn + off)) = pack_q8x4(xo[0], xo[1], xo[2], xo[3]);
+        }
+      }
+    }
+  }
+}
+
 template <int BM, int BN, int WM, int WN, int P, int EPI>
 __global__ void __launch_bounds__(64 * WM * WN)
     dense_gemm(const TileDev* __restrict__ tiles, int ntiles, const InstDev* __restrict__ insts,
@@ -611,7 +778,16 @@ __global__ void __launch_bounds__(64 * WM * WN)
       if (kc < nk) pstep(st0, st1, kc);
       if (kc + 1 < nk) pstep(st1, st2, kc + 1);
     }
-    gemm_epilogue<BM, BN, WM, WN, P, EPI>(acc, td, I, parity, lane, wm, wn);
+    if constexpr (EPI == EPI_EVAL) {
+      gemm_epilogue<BM, BN, WM, WN, P, EPI>(acc, td, I, parity, lane, wm, wn);
+    } else {
+      // every DMA of this wave (including the reloads past the last chunk) has
+      // landed and every wave is done reading the stages before G goes in
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      gemm_epilogue_rows<BM, BN, WM, WN, P, EPI, STAGE>(acc, td, I, parity, tid, lane, wm, wn, st0,
+                                                        st1);
+    }
   }
   __builtin_amdgcn_s_waitcnt(0);  // no DMA into LDS may outlive the workgroup
 }
