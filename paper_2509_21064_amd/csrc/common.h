@@ -61,7 +61,7 @@ struct InstDev {
   int64_t* Cacc;          // [B] c'^T x_r, accumulated by integer atomics
   int64_t* Fall;          // [B] objectives of the last evaluation
   Incumbent* inc;
-  uint8_t* best_x;        // [n]
+  uint8_t* best_x;        // [ld]; the first n bytes are the best rounded vector
   TraceRec* trace;
   int32_t* trace_len;
   int64_t* t_dev;         // completed iterations

@@ -145,6 +145,100 @@ constexpr int gemm_lds_bytes() {
   return 2 * (BM + BN) * kRow;
 }
 
+// Best of B for one instance, by one workgroup of NT threads:
+// F_b = (kappa * S_b) / 2 + C_b from the evaluation's integer partials (which
+// are reset to zero for the next evaluation), first argmin over b, strict-
+// improvement update of the incumbent, copy of the winning rounded vector.
+// mode 0: no evaluation this iteration (only the iteration counter advances);
+// mode 1: evaluation and incumbent update; mode 2: objectives only.
+template <int NT>
+__device__ void best_of_B(const InstDev& I, int mode, int tid, int64_t* sF, int* sb,
+                          int* improved) {
+  const int64_t t = *I.t_dev + 1;
+  if (mode != 0) {
+    // Loads are batched ahead of the stores: Fall, Sacc and Cacc are distinct
+    // arrays, but the compiler cannot know it and would otherwise wait a
+    // memory round trip per restart.  Each thread visits its restarts in
+    // increasing order, so the strict comparison keeps the first minimum.
+    constexpr int U = 4;
+    int64_t bestF = LLONG_MAX;
+    int bestb = INT_MAX;
+    for (int b0 = 0; b0 < I.B; b0 += U * NT) {
+      int64_t S[U], C[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int b = b0 + u * NT + tid;
+        S[u] = b < I.B ? I.Sacc[b] : 0;
+        C[u] = b < I.B ? I.Cacc[b] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int b = b0 + u * NT + tid;
+        if (b >= I.B) continue;
+        I.Sacc[b] = 0;  // ready for the next evaluation
+        I.Cacc[b] = 0;
+        const int64_t F = (I.kappa == 2 ? S[u] : S[u] / 2) + C[u];
+        I.Fall[b] = F;
+        if (F < bestF) {
+          bestF = F;
+          bestb = b;
+        }
+      }
+    }
+    sF[tid] = bestF;
+    sb[tid] = bestb;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+      if (tid < h) {
+        const int64_t f2 = sF[tid + h];
+        const int b2 = sb[tid + h];
+        if (f2 < sF[tid] || (f2 == sF[tid] && b2 < sb[tid])) {
+          sF[tid] = f2;
+          sb[tid] = b2;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      *improved = 0;
+      if (mode == 1 && sF[0] < I.inc->F) {
+        const uint64_t ts = wall_clock();
+        I.inc->F = sF[0];
+        I.inc->t = t;
+        I.inc->b = sb[0];
+        I.inc->ts = ts;
+        const int k = *I.trace_len;
+        if (k < I.trace_cap) {
+          I.trace[k] = TraceRec{t, sF[0], (int64_t)sb[0], ts};
+          *I.trace_len = k + 1;
+        }
+        *improved = 1;
+      }
+    }
+    __syncthreads();
+    if (*improved) {
+      // whole 16-byte words of the winning row (best_x holds ld bytes)
+      const u32x4* src = (const u32x4*)(I.Xr + (size_t)sb[0] * I.ld);
+      u32x4* dst = (u32x4*)I.best_x;
+      const int nv = I.ld / 16;
+      for (int v0 = 0; v0 < nv; v0 += U * NT) {
+        u32x4 r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int v = v0 + u * NT + tid;
+          if (v < nv) r[u] = src[v];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int v = v0 + u * NT + tid;
+          if (v < nv) dst[v] = r[u];
+        }
+      }
+    }
+  }
+  if (tid == 0 && mode != 2) *I.t_dev = t;
+}
+
 // Epilogue of one tile, shared by both main loops.  STEP/GRAD: lane holds
 // rows ibase+16*fm+r (r = 0..3) of restart column bbase+16*fn.
 template <int BM, int BN, int WM, int WN, int P, int EPI>
@@ -876,73 +970,14 @@ hipError_t launch_dense_gemm(int cfg, int prec, int epi, const TileDev* tiles, i
 
 // ---------------------------------------------------------------- best of B
 
-// One workgroup per instance: F_b = (kappa * S_b) / 2 + C_b from the tile
-// partials (fixed summation order), first argmin over b, strict-improvement
-// update of the incumbent, copy of the winning rounded column.
-// mode 0: no evaluation this iteration (only the iteration counter advances);
-// mode 1: evaluation and incumbent update; mode 2: objectives only.
 constexpr int kArgThreads = 1024;
 
 __global__ void __launch_bounds__(kArgThreads)
     argmin_kernel(const InstDev* __restrict__ insts, int inst0, int mode) {
-  const int do_eval = mode != 0;
-  const InstDev& I = insts[inst0 + blockIdx.x];
   __shared__ int64_t sF[kArgThreads];
   __shared__ int sb[kArgThreads];
   __shared__ int improved;
-  const int tid = threadIdx.x;
-  const int64_t t = *I.t_dev + 1;
-  if (do_eval) {
-    int64_t bestF = LLONG_MAX;
-    int bestb = INT_MAX;
-    for (int b = tid; b < I.B; b += kArgThreads) {
-      const int64_t S = I.Sacc[b], C = I.Cacc[b];
-      I.Sacc[b] = 0;  // ready for the next evaluation
-      I.Cacc[b] = 0;
-      const int64_t F = (I.kappa == 2 ? S : S / 2) + C;
-      I.Fall[b] = F;
-      if (F < bestF) {
-        bestF = F;
-        bestb = b;
-      }
-    }
-    sF[tid] = bestF;
-    sb[tid] = bestb;
-    __syncthreads();
-    for (int h = kArgThreads / 2; h > 0; h >>= 1) {
-      if (tid < h) {
-        const int64_t f2 = sF[tid + h];
-        const int b2 = sb[tid + h];
-        if (f2 < sF[tid] || (f2 == sF[tid] && b2 < sb[tid])) {
-          sF[tid] = f2;
-          sb[tid] = b2;
-        }
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      improved = 0;
-      if (mode == 1 && sF[0] < I.inc->F) {
-        const uint64_t ts = wall_clock();
-        I.inc->F = sF[0];
-        I.inc->t = t;
-        I.inc->b = sb[0];
-        I.inc->ts = ts;
-        const int k = *I.trace_len;
-        if (k < I.trace_cap) {
-          I.trace[k] = TraceRec{t, sF[0], (int64_t)sb[0], ts};
-          *I.trace_len = k + 1;
-        }
-        improved = 1;
-      }
-    }
-    __syncthreads();
-    if (improved) {
-      const int8_t* src = I.Xr + (size_t)sb[0] * I.ld;
-      for (int i = tid; i < I.n; i += kArgThreads) I.best_x[i] = (uint8_t)src[i];
-    }
-  }
-  if (tid == 0 && mode != 2) *I.t_dev = t;
+  best_of_B<kArgThreads>(insts[inst0 + blockIdx.x], mode, threadIdx.x, sF, sb, &improved);
 }
 
 hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, hipStream_t s) {
