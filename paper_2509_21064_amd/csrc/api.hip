@@ -94,6 +94,7 @@ struct pdbo_ctx {
   // timing
   bool timing = false;
   std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> ev_pool;  // events already read, reused by later launches
   double ms[PDBO_K_COUNT] = {0, 0, 0, 0};
   int64_t cnt[PDBO_K_COUNT] = {0, 0, 0, 0};
 };
@@ -147,6 +148,8 @@ void free_all(pdbo_ctx* c) {
     (void)hipEventDestroy(t.b);
   }
   c->pending.clear();
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -424,18 +427,30 @@ int default_cfg(const std::vector<int>& ns, int B) {
 
 // ---------------------------------------------------------------- timing
 
+hipEvent_t ev_get(pdbo_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+// Brackets one launch with a pair of events on the context's stream.
 void t_begin(pdbo_ctx* c, TimedLaunch& tl, int cls) {
   tl.cls = -1;
   if (!c->timing) return;
-  if (hipEventCreate(&tl.a) != hipSuccess) return;
-  if (hipEventCreate(&tl.b) != hipSuccess) {
-    (void)hipEventDestroy(tl.a);
+  tl.a = ev_get(c);
+  if (!tl.a) return;
+  tl.b = ev_get(c);
+  if (!tl.b) {
+    c->ev_pool.push_back(tl.a);
     return;
   }
   tl.cls = cls;
   (void)hipEventRecord(tl.a, c->stream);
 }
-
 void t_end(pdbo_ctx* c, TimedLaunch& tl) {
   if (tl.cls < 0) return;
   (void)hipEventRecord(tl.b, c->stream);
@@ -449,8 +464,8 @@ void t_collect(pdbo_ctx* c) {
       c->ms[t.cls] += ms;
       c->cnt[t.cls] += 1;
     }
-    (void)hipEventDestroy(t.a);
-    (void)hipEventDestroy(t.b);
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
   }
   c->pending.clear();
 }
