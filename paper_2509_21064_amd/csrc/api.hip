@@ -325,6 +325,7 @@ struct CsrCanon {
   std::vector<int32_t> rp, col, val;
   std::vector<int64_t> cp;
   int32_t amax = 0;
+  int64_t rowabs = 0;  // max_i sum_j |Ahat_ij|
 };
 
 pdbo_status canon_csr(const pdbo_qubo* q, CsrCanon& C) {
@@ -376,6 +377,7 @@ pdbo_status canon_csr(const pdbo_qubo* q, CsrCanon& C) {
   for (int i = 0; i < n; ++i) {
     C.rp[i + 1] += C.rp[i];
     if (rs[i] >= (int64_t(1) << 31)) return fail(nullptr, PDBO_ERANGE, "a row of |Ahat| sums to 2^31 or more");
+    C.rowabs = std::max(C.rowabs, rs[i]);
   }
   return PDBO_OK;
 }
@@ -1039,6 +1041,13 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
     d.nnz = nnz;
     d.kos = (float)((double)C.kappa / p->scale);
     d.gp = make_gp(p);
+    {
+      // a wave of the 1024-thread kernel sums at most 64 x 8 rows
+      int64_t cmax = 0;
+      for (int i = 0; i < n; ++i) cmax = std::max<int64_t>(cmax, C.cp[i] < 0 ? -C.cp[i] : C.cp[i]);
+      const int64_t lim = int64_t(1) << 31;
+      d.small32 = (512 * C.rowabs < lim && 512 * cmax < lim) ? 1 : 0;
+    }
     int32_t* rp = nullptr;
     STCHK(dalloc(c, &rp, n + 1));
     HIPCHK(c, hipMemcpyAsync(rp, C.rp.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream));

@@ -151,6 +151,7 @@ struct CsrDev {
   int64_t* Flast;         // [B]
   int64_t nnz;
   int n, ld, B, kappa;
+  int small32;            // 512 * max_i sum_j |Ahat_ij| and 512 * max_i |c'_i| are below 2^31
   float kos;
   GdaP gp;
 };

@@ -4,14 +4,15 @@
 // one restart for the whole launch: x of that restart lives in LDS (every row's
 // neighbours are gathered from there), y and the thread's own x in registers,
 // and when it fits the canonical CSR matrix Ahat = offdiag(Q + Q^T)/kappa is
-// staged in LDS too.  Each iteration needs two barriers and no grid-wide
-// synchronisation.  The exact objective of round(x^t) is fused into the same
+// staged in LDS too.  Each iteration needs one barrier (two when x cannot be
+// double-buffered in LDS) and no grid-wide synchronisation.  The exact objective of round(x^t) is fused into the same
 // gathers: while row i accumulates sum_k Ahat_ik x_k for the gradient it also
 // accumulates sum_k Ahat_ik [x_k > 1/2] in int32, so F(round(x^t)) =
 // (kappa/2) x_r^T Ahat x_r + c'^T x_r costs no extra pass.  The best value of
 // each restart over time (and the vector that attained it) is kept per restart
 // and reduced to the incumbent by restart_best_kernel.
 #include <climits>
+#include <type_traits>
 
 #include "common.h"
 
@@ -91,20 +92,28 @@ __device__ __forceinline__ void row_gather(int i, const int32_t* __restrict__ rp
   accr = r0 + r1;
 }
 
-template <bool PACKED, int NT, int RMAX>
+// DBUF: x is double-buffered in LDS (iteration t gathers from buffer t mod 2
+// and writes x^{t+1} into the other), so one barrier per iteration suffices;
+// otherwise x is updated in place between two barriers.
+// SMALL: the host has bounded every wave's partial sums of x_r^T Ahat x_r and
+// c'^T x_r below 2^31, so the wave reductions run in int32 (half the shuffles
+// of int64); the sum over waves is always taken in int64.
+template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL>
 __global__ void __launch_bounds__(NT)
     csr_persistent(CsrDev D, int64_t t0, int nsteps) {
   constexpr int NW = NT / 64;
+  using Part = typename std::conditional<SMALL, int32_t, int64_t>::type;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-  __shared__ int64_t red[2][NW][2];
+  __shared__ Part red[2][NW][2];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int b = blockIdx.x;
   const int n = D.n;
   float* xs = (float*)lds;
   const int32_t* rp = D.row_ptr;
   const uint32_t* ent = D.packed;
+  const size_t xbytes = align16((size_t)n * 4) * (DBUF ? 2 : 1);
   if constexpr (PACKED) {
-    int32_t* rpl = (int32_t*)(lds + align16((size_t)n * 4));
+    int32_t* rpl = (int32_t*)(lds + xbytes);
     uint32_t* entl = (uint32_t*)((uint8_t*)rpl + align16((size_t)(n + 1) * 4));
     const int nnz = (int)D.nnz;
     for (int q = tid; q <= n; q += NT) rpl[q] = D.row_ptr[q];
@@ -114,15 +123,27 @@ __global__ void __launch_bounds__(NT)
   }
   const int32_t* col = (const int32_t*)D.col;
   const int32_t* val = (const int32_t*)D.val;
-  float xr[RMAX], yr[RMAX], xn[RMAX];
+  const int xstride = (int)(align16((size_t)n * 4) / 4);  // floats between the two x buffers
+  // c'/s and c' of the thread's rows stay in registers when there are few rows
+  constexpr bool CREG = RMAX <= 8;
+  float xr[RMAX], yr[RMAX], xn[RMAX], cps[CREG ? RMAX : 1];
+  Part cpr[CREG ? RMAX : 1];
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
     const int i = tid + j * NT;
     xr[j] = 0.f;
     yr[j] = 0.f;
+    if constexpr (CREG) {
+      cps[j] = 0.f;
+      cpr[j] = 0;
+    }
     if (i < n) {
       xr[j] = D.X[(size_t)b * D.ld + i];
       yr[j] = D.Y[(size_t)b * D.ld + i];
+      if constexpr (CREG) {
+        cps[j] = D.cps[i];
+        cpr[j] = (Part)D.cp[i];
+      }
       xs[i] = xr[j];
     }
   }
@@ -136,21 +157,25 @@ __global__ void __launch_bounds__(NT)
   for (int s = 0; s <= nsteps; ++s) {
     const bool upd = s < nsteps;
     const bool ev = s > 0;
-    int64_t S = 0, C = 0;
+    const float* xcur = DBUF ? xs + (s & 1) * xstride : xs;
+    Part S = 0, C = 0;
 #pragma unroll
     for (int j = 0; j < RMAX; ++j) {
       const int i = tid + j * NT;
       if (i < n) {
         float acc;
         int accr;
-        row_gather<PACKED>(i, rp, ent, col, val, xs, acc, accr);
+        row_gather<PACKED>(i, rp, ent, col, val, xcur, acc, accr);
         if (ev && xr[j] > 0.5f) {
-          S += accr;
-          C += D.cp[i];
+          S += (Part)accr;
+          if constexpr (CREG)
+            C += cpr[j];
+          else
+            C += (Part)D.cp[i];
         }
         if (upd) {
           float a, c;
-          gda_update(xr[j], yr[j], fmaf(acc, kos, D.cps[i]), gp, a, c);
+          gda_update(xr[j], yr[j], fmaf(acc, kos, CREG ? cps[j] : D.cps[i]), gp, a, c);
           xn[j] = a;
           yr[j] = c;
         }
@@ -165,6 +190,18 @@ __global__ void __launch_bounds__(NT)
       if (lane == 0) {
         red[s & 1][wid][0] = S;
         red[s & 1][wid][1] = C;
+      }
+    }
+    // x^{t+1} goes into the other buffer before the single barrier; the
+    // rounded x^t (xr) is still needed for the incumbent copy below
+    if constexpr (DBUF) {
+      if (upd) {
+        float* xnext = xs + ((s + 1) & 1) * xstride;
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) {
+          const int i = tid + j * NT;
+          if (i < n) xnext[i] = xn[j];
+        }
       }
     }
     __syncthreads();
@@ -194,12 +231,12 @@ __global__ void __launch_bounds__(NT)
       for (int j = 0; j < RMAX; ++j) {
         const int i = tid + j * NT;
         if (i < n) {
-          xs[i] = xn[j];
+          if constexpr (!DBUF) xs[i] = xn[j];
           xr[j] = xn[j];
         }
       }
     }
-    __syncthreads();
+    if constexpr (!DBUF) __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
@@ -217,10 +254,10 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-template <bool PACKED, int NT, int RMAX>
+template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL>
 static hipError_t launch_csr_k(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
-  auto kern = csr_persistent<PACKED, NT, RMAX>;
-  const size_t lds = csr_lds_need(d.n, d.nnz, PACKED);
+  auto kern = csr_persistent<PACKED, NT, RMAX, DBUF, SMALL>;
+  const size_t lds = csr_lds_need(d.n, d.nnz, PACKED) + (DBUF ? align16((size_t)d.n * 4) : 0);
   hipError_t e =
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -228,19 +265,29 @@ static hipError_t launch_csr_k(const CsrDev& d, int64_t t0, int nsteps, hipStrea
   return hipGetLastError();
 }
 
+template <bool PACKED, int NT, int RMAX>
+static hipError_t launch_csr_v(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
+  const bool dbuf = csr_lds_need(d.n, d.nnz, PACKED) + align16((size_t)d.n * 4) <= kLdsBudget;
+  if (dbuf && d.small32) return launch_csr_k<PACKED, NT, RMAX, true, true>(d, t0, nsteps, s);
+  if (dbuf) return launch_csr_k<PACKED, NT, RMAX, true, false>(d, t0, nsteps, s);
+  if (d.small32) return launch_csr_k<PACKED, NT, RMAX, false, true>(d, t0, nsteps, s);
+  return launch_csr_k<PACKED, NT, RMAX, false, false>(d, t0, nsteps, s);
+}
+
 // 1024 threads per restart (sixteen waves keep enough LDS gathers in flight)
-// up to 8 rows per thread; beyond that 512 threads, whose larger register
-// budget holds up to 64 rows per thread without spilling.
+// up to 8 rows per thread; beyond that (n > 8192) 512 threads with 32 or 64
+// rows per thread, whose per-row state does not fit the register budget and
+// partly lives in scratch memory.
 template <bool PACKED>
 static hipError_t launch_csr_r(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
   const int r = (d.n + 1023) / 1024;
-  if (r <= 1) return launch_csr_k<PACKED, 1024, 1>(d, t0, nsteps, s);
-  if (r <= 2) return launch_csr_k<PACKED, 1024, 2>(d, t0, nsteps, s);
-  if (r <= 4) return launch_csr_k<PACKED, 1024, 4>(d, t0, nsteps, s);
-  if (r <= 8) return launch_csr_k<PACKED, 1024, 8>(d, t0, nsteps, s);
+  if (r <= 1) return launch_csr_v<PACKED, 1024, 1>(d, t0, nsteps, s);
+  if (r <= 2) return launch_csr_v<PACKED, 1024, 2>(d, t0, nsteps, s);
+  if (r <= 4) return launch_csr_v<PACKED, 1024, 4>(d, t0, nsteps, s);
+  if (r <= 8) return launch_csr_v<PACKED, 1024, 8>(d, t0, nsteps, s);
   const int r2 = (d.n + 511) / 512;
-  if (r2 <= 32) return launch_csr_k<PACKED, 512, 32>(d, t0, nsteps, s);
-  if (r2 <= 64) return launch_csr_k<PACKED, 512, 64>(d, t0, nsteps, s);
+  if (r2 <= 32) return launch_csr_k<PACKED, 512, 32, false, false>(d, t0, nsteps, s);
+  if (r2 <= 64) return launch_csr_k<PACKED, 512, 64, false, false>(d, t0, nsteps, s);
   return hipErrorInvalidValue;
 }
 

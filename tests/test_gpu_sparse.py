@@ -29,10 +29,31 @@ def _wide_weights(n=900, M=4000, seed=0):
                   vals=S.data.astype(np.int32), c=g.integers(-100, 101, n).astype(np.int64))
 
 
+def _big_weights(n=700, M=2100, seed=5, mag=1 << 20):
+    """Weights and linear terms up to 2^20 in magnitude: a wave's partial sums of
+    the exact objective no longer fit in 32 bits, so the kernel keeps them in
+    int64 (the per-row sums still fit in int32)."""
+    base = W.maxcut_c2(rep=seed, n=n, M=M)
+    g = np.random.default_rng(seed)
+    vals = (g.integers(1, mag, size=base.vals.shape[0]) * np.sign(base.vals)).astype(np.int32)
+    return W.Qubo(n=n, row_ptr=base.row_ptr, col_idx=base.col_idx, vals=vals,
+                  c=g.integers(-mag, mag, n).astype(np.int64))
+
+
+# Each case reaches a different variant of the persistent kernel:
+#   n2000        x double-buffered in LDS, packed CSR in LDS, int32 wave sums
+#   n301         one row per thread, ragged last wave
+#   wide_n900    int32 column/value arrays read through L2 (values beyond 16 bits)
+#   big_n700     int64 wave sums
+#   n8000        CSR in LDS but no room for a second x buffer: x updated in place
+#   n12000       more than 8192 rows: 512 threads with 32 rows each, CSR through L2
 CASES = {
     "maxcut_n2000": (lambda: W.maxcut_c2(0), 256, 1.0),
     "maxcut_n301_ragged": (lambda: W.maxcut_c2(1, n=301, M=900), 37, 1.0),
     "wide_n900": (lambda: _wide_weights(), 20, None),
+    "big_n700": (lambda: _big_weights(), 24, None),
+    "maxcut_n8000_inplace": (lambda: W.maxcut_c2(4, n=8000, M=8000), 24, 1.0),
+    "maxcut_n12000_rows32": (lambda: W.maxcut_c2(3, n=12000, M=36000), 16, 1.0),
 }
 
 
