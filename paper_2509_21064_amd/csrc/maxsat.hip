@@ -22,6 +22,8 @@ namespace pdbo {
 __host__ __device__ static inline size_t align16s(size_t v) { return (v + 15) & ~size_t(15); }
 
 constexpr size_t kSatLdsBudget = 150 * 1024;
+// x and y of one restart, plus the kernel's small static arrays, in the 160 KB
+constexpr size_t kSatYldsBudget = 160 * 1024 - 1024;
 
 bool sat_fits(int n, size_t* lds_bytes) {
   const size_t need = align16s((size_t)n * 4);
@@ -83,36 +85,51 @@ __device__ __forceinline__ float sat3_adjoint(const SatDev& D, const float* __re
   const int pe = D.inc_ptr[i + 1];
   int e = D.inc_ptr[i];
   const bool own_true = xi > 0.5f;
-  float g0 = 0.f, g1 = 0.f;
-  for (; e + 2 <= pe; e += 2) {
-    const uint64_t a = E[e];
-    const uint64_t b = E[e + 1];
+  // four entries per round, so that their loads and gathers are in flight together
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+  for (; e + 4 <= pe; e += 4) {
+    const uint64_t a = E[e], b = E[e + 1], c = E[e + 2], d = E[e + 3];
     sat3_term(a, xs, own_true, want_eval, g0, unsat);
     sat3_term(b, xs, own_true, want_eval, g1, unsat);
+    sat3_term(c, xs, own_true, want_eval, g2, unsat);
+    sat3_term(d, xs, own_true, want_eval, g3, unsat);
   }
-  if (e < pe) sat3_term(E[e], xs, own_true, want_eval, g0, unsat);
-  return g0 + g1;
+  for (; e < pe; ++e) sat3_term(E[e], xs, own_true, want_eval, g0, unsat);
+  return (g0 + g1) + (g2 + g3);
 }
 
-template <bool K3, int NT, int RMAX>
+// YLDS: y lives in LDS beside x (both n floats), read and written in place by
+// the variable's owner, and x^t is read back from LDS; only x^{t+1} is held in
+// registers until the barrier.  Used when many variables fall to each thread
+// and both arrays fit, so that the per-variable state does not spill.
+template <bool K3, int NT, int RMAX, bool YLDS>
 __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int nsteps) {
   constexpr int NW = NT / 64;
   extern __shared__ __attribute__((aligned(16))) float xs[];
   __shared__ int64_t red[2][NW];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int b = blockIdx.x, n = D.n;
-  float xr[RMAX], yr[RMAX], xn[RMAX];
+  float* ys = xs + align16s((size_t)n * 4) / 4;
+  float xr[YLDS ? 1 : RMAX], yr[YLDS ? 1 : RMAX], xn[RMAX];
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
     const int i = tid + j * NT;
-    xr[j] = 0.f;
-    yr[j] = 0.f;
+    if constexpr (!YLDS) {
+      xr[j] = 0.f;
+      yr[j] = 0.f;
+    }
     if (i < n) {
-      xr[j] = D.X[(size_t)b * D.ld + i];
-      yr[j] = D.Y[(size_t)b * D.ld + i];
-      xs[i] = xr[j];
+      const float x = D.X[(size_t)b * D.ld + i], y = D.Y[(size_t)b * D.ld + i];
+      xs[i] = x;
+      if constexpr (YLDS) {
+        ys[i] = y;
+      } else {
+        xr[j] = x;
+        yr[j] = y;
+      }
     }
   }
+  auto xold = [&](int j, int i) { return YLDS ? xs[i] : xr[j]; };
   int64_t bF = D.rbestF[b], bT = D.rbestT[b];
   uint64_t bTs = D.rbestTs[b];
   int64_t Flast = D.Flast[b];
@@ -123,17 +140,22 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
     const bool upd = s < nsteps;
     const bool ev = s > 0;
     int64_t S = 0;
-#pragma unroll
+    // with y in LDS only x^{t+1} is kept per variable: the loop is not
+    // unrolled (twenty copies of the occurrence loop would spill)
+#pragma unroll(YLDS ? 1 : RMAX)
     for (int j = 0; j < RMAX; ++j) {
       const int i = tid + j * NT;
       if (i < n) {
-        const float g = K3 ? sat3_adjoint(D, xs, i, xr[j], ev, S)
-                           : sat_adjoint(D, xs, i, xr[j], ev, S);
+        const float xi = xold(j, i);
+        const float g = K3 ? sat3_adjoint(D, xs, i, xi, ev, S) : sat_adjoint(D, xs, i, xi, ev, S);
         if (upd) {
           float a, c;
-          gda_update(xr[j], yr[j], g * ios, gp, a, c);
+          gda_update(xi, YLDS ? ys[i] : yr[j], g * ios, gp, a, c);
           xn[j] = a;
-          yr[j] = c;
+          if constexpr (YLDS)
+            ys[i] = c;
+          else
+            yr[j] = c;
         }
       }
     }
@@ -156,7 +178,7 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
 #pragma unroll
         for (int j = 0; j < RMAX; ++j) {
           const int i = tid + j * NT;
-          if (i < n) dst[i] = (uint8_t)(xr[j] > 0.5f);
+          if (i < n) dst[i] = (uint8_t)(xold(j, i) > 0.5f);
         }
       }
     }
@@ -166,7 +188,7 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
         const int i = tid + j * NT;
         if (i < n) {
           xs[i] = xn[j];
-          xr[j] = xn[j];
+          if constexpr (!YLDS) xr[j] = xn[j];
         }
       }
     }
@@ -176,8 +198,8 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
   for (int j = 0; j < RMAX; ++j) {
     const int i = tid + j * NT;
     if (i < n) {
-      D.X[(size_t)b * D.ld + i] = xr[j];
-      D.Y[(size_t)b * D.ld + i] = yr[j];
+      D.X[(size_t)b * D.ld + i] = xold(j, i);
+      D.Y[(size_t)b * D.ld + i] = YLDS ? ys[i] : yr[j];
     }
   }
   if (tid == 0) {
@@ -188,10 +210,10 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
   }
 }
 
-template <bool K3, int NT, int RMAX>
+template <bool K3, int NT, int RMAX, bool YLDS = false>
 static hipError_t launch_sat_k(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
-  auto kern = sat_persistent<K3, NT, RMAX>;
-  const size_t lds = align16s((size_t)d.n * 4);
+  auto kern = sat_persistent<K3, NT, RMAX, YLDS>;
+  const size_t lds = align16s((size_t)d.n * 4) * (YLDS ? 2 : 1);
   hipError_t e =
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -200,12 +222,16 @@ static hipError_t launch_sat_k(const SatDev& d, int64_t t0, int nsteps, hipStrea
 }
 
 // 1024 threads per restart (sixteen waves of gathers in flight) up to 8
-// variables per thread, 512 threads with a larger register budget beyond.
+// variables per thread in registers, up to 20 with y in LDS (n <= 20000, both
+// arrays in the 160 KB); beyond that 512 threads with a larger register budget,
+// whose per-variable state partly spills to scratch memory.
 template <bool K3>
 static hipError_t launch_sat_r(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
   const int r = (d.n + 1023) / 1024;
   if (r <= 4) return launch_sat_k<K3, 1024, 4>(d, t0, nsteps, s);
   if (r <= 8) return launch_sat_k<K3, 1024, 8>(d, t0, nsteps, s);
+  if (r <= 20 && 2 * align16s((size_t)d.n * 4) <= kSatYldsBudget)
+    return launch_sat_k<K3, 1024, 20, true>(d, t0, nsteps, s);
   const int r2 = (d.n + 511) / 512;
   if (r2 <= 40) return launch_sat_k<K3, 512, 40>(d, t0, nsteps, s);
   if (r2 <= 64) return launch_sat_k<K3, 512, 64>(d, t0, nsteps, s);

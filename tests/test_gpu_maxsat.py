@@ -11,10 +11,18 @@ from oracle.binarity import Entropy
 
 pytestmark = pytest.mark.gpu
 
+# The larger cases reach the other variants of the persistent kernel: up to 8
+# variables per thread in registers (n6000), up to 20 with y in LDS (n12345,
+# and the general-k form n9001), and 512 threads with 64 variables each
+# (n25000).
 CASES = {
     "3sat_n500": (lambda: W.random_maxsat(500, 2100, 3, 1, 10, W.rng_for(5, 0, 0, 500, 2100)), 16),
     "4sat_n333": (lambda: W.random_maxsat(333, 2000, 4, 1, 10, W.rng_for(5, 1, 0, 333, 2000)), 7),
     "2sat_n65": (lambda: W.random_maxsat(65, 150, 2, 0, 3, W.rng_for(5, 2, 0, 65, 150)), 3),
+    "3sat_n6000": (lambda: W.random_maxsat(6000, 25200, 3, 1, 10, W.rng_for(5, 3, 0, 6000, 25200)), 8),
+    "3sat_n12345": (lambda: W.random_maxsat(12345, 51849, 3, 1, 10, W.rng_for(5, 4, 0, 12345, 51849)), 6),
+    "4sat_n9001": (lambda: W.random_maxsat(9001, 80000, 4, 1, 10, W.rng_for(5, 5, 0, 9001, 80000)), 4),
+    "3sat_n25000": (lambda: W.random_maxsat(25000, 105000, 3, 1, 10, W.rng_for(5, 6, 0, 25000, 105000)), 4),
 }
 
 
