@@ -84,18 +84,27 @@ def run_form(P, q, s, x0, form, args):
     k_step = ctx.kernel_time(P.PDBO_K_STEP)
     k_eval = ctx.kernel_time(P.PDBO_K_EVAL)
     k_arg = ctx.kernel_time(P.PDBO_K_ARGMIN)
+    k_inc = ctx.kernel_time(P.PDBO_K_INCR)
     ctx.timing(False)
     ctx.destroy()
+    # per-iteration averages over the timed steps (the evaluation GEMM skips the
+    # column blocks whose restarts changed few rounded coordinates)
     out = dict(value=B * args.steps / el, ms_per_step=1e3 * el / args.steps,
                step_kernel_ms=k_step[0] / max(k_step[1], 1),
                eval_kernel_ms=k_eval[0] / max(k_eval[1], 1),
+               eval_incr_kernel_ms=k_inc[0] / max(k_inc[1], 1),
                argmin_kernel_ms=k_arg[0] / max(k_arg[1], 1), launches=k_step[1])
     log(f"{form}: {out['value']:.4g} restart-it/s, {out['ms_per_step']:.3f} ms/step "
         f"(step {out['step_kernel_ms']:.3f} ms, eval {out['eval_kernel_ms']:.3f} ms, "
-        f"argmin {out['argmin_kernel_ms']:.3f} ms)")
+        f"incremental eval {out['eval_incr_kernel_ms']:.3f} ms, argmin {out['argmin_kernel_ms']:.3f} ms)")
     if not args.no_quality:
         ctx = P.qubo_gda_init(q, p, x0)
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
         ctx.step(args.T)
+        torch.cuda.synchronize()
+        tq = time.perf_counter() - tq
+        out.update(quality_run_s=tq, quality_run_restart_it_per_s=B * args.T / tq)
         r = ctx.result()
         tr = ctx.trace()
         ctx.destroy()

@@ -238,8 +238,23 @@ PDBO_API pdbo_status maxsat_lagrangian_bwd(pdbo_ctx* ctx, const float* x, const 
 PDBO_API pdbo_status qubo_gda_trace(pdbo_ctx* ctx, int32_t cap, int64_t* t, int64_t* F, int32_t* b,
                                     double* sec, int32_t* len);
 
+/* Kernel classes of pdbo_kernel_time:
+ *   PDBO_K_STEP        dense GEMM with the Alg. 1 update fused (one per iteration)
+ *   PDBO_K_EVAL        dense int8 GEMM of the exact objectives (Eq. 1); a column
+ *                      block of restarts is skipped when none of them needs a
+ *                      full product
+ *   PDBO_K_ARGMIN      best of B and incumbent update
+ *   PDBO_K_PERSISTENT  the CSR and MaxSAT persistent kernels (one per step call)
+ *   PDBO_K_INCR        exact objective differences from the recorded rounding
+ *                      changes: when at most 32 coordinates of a restart's
+ *                      rounded iterate changed since the previous evaluation,
+ *                      F(x') - F(x) = sum_i d_i (c'_i + kappa (Ahat x')_i)
+ *                                     - kappa sum_{i<j} d_i d_j Ahat_ij
+ *                      (d = x' - x, all in integers) replaces the full product;
+ *                      the first evaluation after init or set_state, and any
+ *                      restart with more changes, take the full product. */
 enum { PDBO_K_STEP = 0, PDBO_K_EVAL = 1, PDBO_K_ARGMIN = 2, PDBO_K_PERSISTENT = 3,
-       PDBO_K_COUNT = 4 };
+       PDBO_K_INCR = 4, PDBO_K_COUNT = 5 };
 
 /* Enables (1) or disables (0) HIP-event timing of every kernel launch of the
  * context, on the context's stream.  Clears the accumulated times. */

@@ -20,7 +20,7 @@ import numpy as np
 
 from . import _abi
 from ._abi import (PDBO_BF16, PDBO_CSR, PDBO_DENSE, PDBO_FP8, PDBO_FP32, PDBO_G_ENTROPY, PDBO_I8,
-                   PDBO_G_QUAD, PDBO_K_ARGMIN, PDBO_K_EVAL, PDBO_K_PERSISTENT, PDBO_K_STEP,
+                   PDBO_G_QUAD, PDBO_K_ARGMIN, PDBO_K_EVAL, PDBO_K_INCR, PDBO_K_PERSISTENT, PDBO_K_STEP,
                    PdboError, check, load)
 
 __all__ = [
@@ -30,7 +30,7 @@ __all__ = [
     "qubo_gda_batch_solve", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
     "maxsat_gda_solve", "maxsat_lagrangian_fwd", "maxsat_lagrangian_bwd", "MaxSATLagrangian",
     "PDBO_FP32", "PDBO_BF16", "PDBO_FP8", "PDBO_I8", "PDBO_K_STEP", "PDBO_K_EVAL", "PDBO_K_ARGMIN",
-    "PDBO_K_PERSISTENT",
+    "PDBO_K_PERSISTENT", "PDBO_K_INCR",
 ]
 
 _PREC = {"fp32": PDBO_FP32, "bf16": PDBO_BF16, "fp8": PDBO_FP8, "i8": PDBO_I8}

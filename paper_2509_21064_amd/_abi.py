@@ -16,7 +16,7 @@ PDBO_OK, PDBO_EINVAL, PDBO_ENOMEM, PDBO_EDEVICE, PDBO_ERANGE, PDBO_ESTATE, PDBO_
 PDBO_DENSE, PDBO_CSR = 0, 1
 PDBO_G_QUAD, PDBO_G_ENTROPY = 0, 1
 PDBO_FP32, PDBO_BF16, PDBO_FP8, PDBO_I8 = 0, 1, 2, 3
-PDBO_K_STEP, PDBO_K_EVAL, PDBO_K_ARGMIN, PDBO_K_PERSISTENT = 0, 1, 2, 3
+PDBO_K_STEP, PDBO_K_EVAL, PDBO_K_ARGMIN, PDBO_K_PERSISTENT, PDBO_K_INCR = 0, 1, 2, 3, 4
 
 
 class pdbo_qubo(ctypes.Structure):

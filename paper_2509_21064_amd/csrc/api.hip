@@ -72,6 +72,10 @@ struct pdbo_ctx {
   std::vector<TileDev> tiles_h;
   TileDev* tiles_d = nullptr;
   std::vector<int> tile_off, tile_cnt;
+  // incremental evaluation: one workgroup per (instance, restart), in instance order
+  int2* incr_work_d = nullptr;
+  std::vector<int> incr_off;  // first work item of each instance, plus the total
+  int incr_ld = 0;            // largest row length (bytes of one rounded row)
   int grouped = 1;
   InstDev* scratch_inst_d = nullptr;
   float* gx_scratch = nullptr;     // fp32 x for grad()
@@ -95,8 +99,8 @@ struct pdbo_ctx {
   bool timing = false;
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> ev_pool;  // events already read, reused by later launches
-  double ms[PDBO_K_COUNT] = {0, 0, 0, 0};
-  int64_t cnt[PDBO_K_COUNT] = {0, 0, 0, 0};
+  double ms[PDBO_K_COUNT] = {};
+  int64_t cnt[PDBO_K_COUNT] = {};
 };
 
 namespace {
@@ -568,6 +572,17 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
   STCHK(dalloc(c, &I.Sacc, (size_t)B));
   STCHK(dalloc(c, &I.Cacc, (size_t)B));
   STCHK(dalloc(c, &I.Fall, (size_t)B));
+  I.nflip = nullptr;
+  I.fbits = nullptr;
+  I.dF = nullptr;
+  if (p->eval_every == 1) {
+    // the first evaluation is a full product (nflip above kFlipMax); the
+    // bitmap starts clear (dalloc zeroes)
+    STCHK(dalloc(c, &I.nflip, (size_t)B));
+    STCHK(dalloc(c, &I.fbits, (size_t)B * (ld / 32)));
+    STCHK(dalloc(c, &I.dF, (size_t)B));
+    HIPCHK(c, launch_fill_i32(I.nflip, kFlipMax + 1, B, c->stream));
+  }
   STCHK(dalloc(c, &I.inc, 1));
   STCHK(dalloc(c, &I.best_x, (size_t)ld));
   STCHK(dalloc(c, &I.trace, kTraceCap));
@@ -636,6 +651,21 @@ void build_tiles(pdbo_ctx* c) {
 
 pdbo_status upload_dense_tables(pdbo_ctx* c) {
   build_tiles(c);
+  std::vector<int2> work;  // alive until the stream is synchronised below
+  c->incr_off.clear();
+  c->incr_ld = 0;
+  for (size_t k = 0; k < c->insts_h.size(); ++k) {
+    c->incr_off.push_back((int)work.size());
+    if (!c->insts_h[k].nflip) continue;
+    for (int b = 0; b < c->insts_h[k].B; ++b) work.push_back(make_int2((int)k, b));
+    c->incr_ld = std::max(c->incr_ld, c->insts_h[k].ld);
+  }
+  c->incr_off.push_back((int)work.size());
+  if (!work.empty()) {
+    STCHK(dalloc(c, &c->incr_work_d, work.size()));
+    HIPCHK(c, hipMemcpyAsync(c->incr_work_d, work.data(), work.size() * sizeof(int2),
+                             hipMemcpyHostToDevice, c->stream));
+  }
   STCHK(dalloc(c, &c->insts_d, c->insts_h.size()));
   STCHK(dalloc(c, &c->tiles_d, c->tiles_h.size()));
   HIPCHK(c, hipMemcpyAsync(c->insts_d, c->insts_h.data(), c->insts_h.size() * sizeof(InstDev),
@@ -802,10 +832,18 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
                                 c->insts_d, c->parity, 0, c->stream));
     t_end(c, tl);
     if (do_eval) {
+      // full products only for the column blocks that need them; then the
+      // exact differences of every restart with few rounding changes
       t_begin(c, tl, PDBO_K_EVAL);
       HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, c->tiles_d, (int)c->tiles_h.size(),
                                   c->insts_d, c->parity, 0, c->stream));
       t_end(c, tl);
+      if (c->incr_off.back() > 0) {
+        t_begin(c, tl, PDBO_K_INCR);
+        HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d, c->incr_off.back(), c->incr_ld,
+                                   c->stream));
+        t_end(c, tl);
+      }
     }
     t_begin(c, tl, PDBO_K_ARGMIN);
     HIPCHK(c, launch_argmin(c->insts_d, 0, ninst, do_eval ? 1 : 0, c->stream));
@@ -823,6 +861,12 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
         HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, c->tiles_d + c->tile_off[k],
                                     c->tile_cnt[k], c->insts_d, c->parity, 0, c->stream));
         t_end(c, tl);
+        const int w0 = c->incr_off[k], nw = c->incr_off[k + 1] - w0;
+        if (nw > 0) {
+          t_begin(c, tl, PDBO_K_INCR);
+          HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d + w0, nw, c->incr_ld, c->stream));
+          t_end(c, tl);
+        }
       }
     for (int k = 0; k < ninst; ++k) {
       t_begin(c, tl, PDBO_K_ARGMIN);
@@ -1235,7 +1279,12 @@ pdbo_status qubo_gda_set_state(pdbo_ctx* c, const float* x, const float* y, int6
   HIPCHK(c, launch_set_state((const float*)tx.p, (const float*)ty.p, c->B, n, ld, X, Y, Xs, c->prec,
                              c->stream));
   c->t_host = t;
-  if (c->kind == 0) HIPCHK(c, hipMemcpyAsync(c->insts_h[0].t_dev, &t, sizeof(t), hipMemcpyHostToDevice, c->stream));
+  if (c->kind == 0) {
+    HIPCHK(c, hipMemcpyAsync(c->insts_h[0].t_dev, &t, sizeof(t), hipMemcpyHostToDevice, c->stream));
+    // the rounded iterate no longer follows the recorded changes
+    if (c->insts_h[0].nflip)
+      HIPCHK(c, launch_fill_i32(c->insts_h[0].nflip, kFlipMax + 1, c->B, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return PDBO_OK;
 }
@@ -1330,6 +1379,7 @@ pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F
     I.Sacc = c->sp_scratch;
     I.Cacc = c->cp_scratch;
     I.Fall = c->f_scratch;
+    I.nflip = nullptr;  // full product for every restart
     I.B = nb;
     HIPCHK(c, hipMemcpyAsync(c->scratch_inst_d, &I, sizeof(I), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

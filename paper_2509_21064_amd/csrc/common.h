@@ -65,6 +65,13 @@ struct InstDev {
   TraceRec* trace;
   int32_t* trace_len;
   int64_t* t_dev;         // completed iterations
+  // Incremental evaluation (nullptr: every evaluation is a full product).
+  // The step epilogue records the coordinates whose rounding changed; an
+  // evaluation then updates F_b exactly from them unless more than kFlipMax
+  // changed (or nflip[b] was set above kFlipMax to ask for a full product).
+  int32_t* nflip;         // [B] rounding changes since the last evaluation
+  uint32_t* fbits;        // [B][ld / 32] bitmap of the changed coordinates
+  int64_t* dF;            // [B] F(x_r new) - F(x_r old), from the recorded changes
   uint64_t* ts0;          // clock at the first step
   int n, ld, B, mblocks;
   int kappa, trace_cap;
@@ -113,6 +120,8 @@ __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_mem
 
 // ---- launchers (dense.hip) --------------------------------------------------
 
+constexpr int kFlipMax = 32;
+
 struct TileCfgInfo {
   const char* name;
   int BM, BN, WM, WN, threads;  // block tile, waves along M and N
@@ -124,6 +133,10 @@ const TileCfgInfo& dense_cfg(int id);
 hipError_t launch_dense_gemm(int cfg, int prec, int epi, const TileDev* tiles, int ntiles,
                              const InstDev* insts, int parity, int grid, hipStream_t s);
 hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, hipStream_t s);
+// work[w] = (instance, first restart) of the workgroups of the incremental evaluation
+hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, int max_ld,
+                            hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
 hipError_t launch_stamp(uint64_t* ts0, hipStream_t s);
 hipError_t launch_init_state(const double* x0, int B, int n, int ld, float y0, float* X,
                              float* Y, uint8_t* Xs, int xs_prec, int8_t* Xr, hipStream_t s);

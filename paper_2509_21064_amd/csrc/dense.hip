@@ -163,13 +163,21 @@ __device__ void best_of_B(const InstDev& I, int mode, int tid, int64_t* sF, int*
     constexpr int U = 4;
     int64_t bestF = LLONG_MAX;
     int bestb = INT_MAX;
+    // A restart with at most kFlipMax recorded rounding changes takes its
+    // previous objective plus the exact difference; the others (and every
+    // restart when nflip is absent) take the full product's partials.
     for (int b0 = 0; b0 < I.B; b0 += U * NT) {
-      int64_t S[U], C[U];
+      int64_t S[U], C[U], Fp[U], dF[U];
+      int k[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int b = b0 + u * NT + tid;
-        S[u] = b < I.B ? I.Sacc[b] : 0;
-        C[u] = b < I.B ? I.Cacc[b] : 0;
+        const bool ok = b < I.B;
+        S[u] = ok ? I.Sacc[b] : 0;
+        C[u] = ok ? I.Cacc[b] : 0;
+        k[u] = (ok && I.nflip) ? I.nflip[b] : kFlipMax + 1;
+        Fp[u] = (ok && k[u] <= kFlipMax) ? I.Fall[b] : 0;
+        dF[u] = (ok && k[u] > 0 && k[u] <= kFlipMax) ? I.dF[b] : 0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -177,7 +185,9 @@ __device__ void best_of_B(const InstDev& I, int mode, int tid, int64_t* sF, int*
         if (b >= I.B) continue;
         I.Sacc[b] = 0;  // ready for the next evaluation
         I.Cacc[b] = 0;
-        const int64_t F = (I.kappa == 2 ? S[u] : S[u] / 2) + C[u];
+        if (I.nflip && mode == 1) I.nflip[b] = 0;
+        const int64_t F =
+            k[u] <= kFlipMax ? Fp[u] + dF[u] : (I.kappa == 2 ? S[u] : S[u] / 2) + C[u];
         I.Fall[b] = F;
         if (F < bestF) {
           bestF = F;
@@ -239,6 +249,34 @@ __device__ void best_of_B(const InstDev& I, int mode, int tid, int64_t* sF, int*
   if (tid == 0 && mode != 2) *I.t_dev = t;
 }
 
+// Rounding changes of coordinates i..i+3 of restart b (bytes of the old and
+// new rounded words; coordinates at or past n are padding): counted in
+// nflip[b] and marked in the restart's bitmap.  Neither atomic returns a
+// value, so nothing waits on them (a returned value would make the step wait
+// for every older memory operation, the epilogue's prefetches included).
+__device__ __forceinline__ void record_flips(const InstDev& I, int b, int i, int n, uint32_t oldw,
+                                             uint32_t neww) {
+  uint32_t chg = (oldw ^ neww) & 0x01010101u;
+  const int valid = n - i;
+  if (valid < 4) chg &= (1u << (8 * valid)) - 1u;
+  if (!chg) return;
+  atomicAdd(I.nflip + b, __builtin_popcount(chg));
+  const uint32_t bits = (chg | (chg >> 7) | (chg >> 14) | (chg >> 21)) & 0xfu;
+  atomicOr(I.fbits + (size_t)b * (I.ld / 32) + (i >> 5), bits << (i & 31));
+}
+
+// An evaluation tile is needed only if some restart of its column block asks
+// for a full product (more than kFlipMax changes, or a fresh state).
+template <int BN, int NT>
+__device__ __forceinline__ bool eval_block_needed(const InstDev& I, int n0, int tid) {
+  bool need = false;
+  for (int q = tid; q < BN; q += NT) {
+    const int b = n0 + q;
+    if (b < I.B && I.nflip[b] > kFlipMax) need = true;
+  }
+  return __syncthreads_or(need);
+}
+
 // Epilogue of one tile, shared by both main loops.  STEP/GRAD: lane holds
 // rows ibase+16*fm+r (r = 0..3) of restart column bbase+16*fn.
 template <int BM, int BN, int WM, int WN, int P, int EPI>
@@ -267,6 +305,7 @@ __device__ __forceinline__ void gemm_epilogue(
       f32x4 cs, sc;
       i32x4 off8;
       f32x4 x[FN], y[FN];
+      uint32_t xro[FN];  // rounded word before this step
     };
     auto fetch = [&](int fm, Rows& r) {
       const int ic = min(ibase + fm * 16, ld - 4);
@@ -285,6 +324,7 @@ __device__ __forceinline__ void gemm_epilogue(
           const size_t off = (size_t)min(bbase + fn * 16, B - 1) * ld + ic;
           r.x[fn] = *gptr((const f32x4*)(Xc + off));
           r.y[fn] = *gptr((const f32x4*)(Yp + off));
+          r.xro[fn] = *gptr((const uint32_t*)(I.Xr + off));
         }
       }
     };
@@ -328,6 +368,7 @@ __device__ __forceinline__ void gemm_epilogue(
                               ((uint32_t)(xo[2] > 0.5f) << 16) |
                               ((uint32_t)(xo[3] > 0.5f) << 24);
           *gptr((uint32_t*)(I.Xr + off)) = xr;
+          if (I.nflip) record_flips(I, b, i, n, r.xro[fn], xr);
           if constexpr (P == P_BF16) {
             u32x2 v;
             v.x = (uint32_t)f32_to_bf16_rne(xo[0]) | ((uint32_t)f32_to_bf16_rne(xo[1]) << 16);
@@ -490,6 +531,7 @@ __device__ __forceinline__ void gemm_epilogue_rows(
   uint8_t* Xsn = I.Xs[parity ^ 1];
   struct Vals {
     f32x4 x[PF], y[PF];
+    uint32_t xro[PF];  // rounded word before this step
   };
   // element u of group g: pass g / GPP, index e = (g mod GPP) * PF + u within the
   // thread's share of that pass
@@ -508,6 +550,7 @@ __device__ __forceinline__ void gemm_epilogue_rows(
         const size_t off = (size_t)b * ld + min(td.m0 + 4 * c, ld - 4);
         v.x[u] = *gptr((const f32x4*)(Xc + off));
         v.y[u] = *gptr((const f32x4*)(Yp + off));
+        v.xro[u] = *gptr((const uint32_t*)(I.Xr + off));
       }
     }
   };
@@ -548,6 +591,7 @@ __device__ __forceinline__ void gemm_epilogue_rows(
         const uint32_t xr = (uint32_t)(xo[0] > 0.5f) | ((uint32_t)(xo[1] > 0.5f) << 8) |
                             ((uint32_t)(xo[2] > 0.5f) << 16) | ((uint32_t)(xo[3] > 0.5f) << 24);
         *gptr((uint32_t*)(I.Xr + off)) = xr;
+        if (I.nflip) record_flips(I, b, i, n, v.xro[u], xr);
         if constexpr (P == P_BF16) {
           u32x2 w;
           w.x = (uint32_t)f32_to_bf16_rne(xo[0]) | ((uint32_t)f32_to_bf16_rne(xo[1]) << 16);
@@ -586,6 +630,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
   for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
     const TileDev td = tiles[w];
     const InstDev& I = insts[td.inst];
+    if constexpr (EPI == EPI_EVAL) {
+      if (I.nflip && !eval_block_needed<BN, 64 * WM * WN>(I, td.n0, threadIdx.x)) continue;
+    }
     const int n = I.n, ld = I.ld, B = I.B;
     const size_t rbytes = (size_t)ld * EB;
     const int nk = (int)(rbytes / 128);
@@ -725,6 +772,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
   for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
     const TileDev td = tiles[w];
     const InstDev& I = insts[td.inst];
+    if constexpr (EPI == EPI_EVAL) {
+      if (I.nflip && !eval_block_needed<BN, 64 * WM * WN>(I, td.n0, threadIdx.x)) continue;
+    }
     const int n = I.n, B = I.B;
     const size_t rbytes = (size_t)I.ld * EB;
     const int nk = (int)(rbytes / 128);
@@ -1075,6 +1125,126 @@ hipError_t launch_quantize_A(const int32_t* Ahat, int n, int ld, int prec, uint8
   const size_t tot = (size_t)n * ld;
   hipLaunchKernelGGL(quantize_A_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Ahat,
                      n, ld, prec, A, A8, rscale);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- incremental evaluation
+//
+// x_r changes from x to x' = x + delta (delta_i = +-1 on the recorded
+// coordinates D).  With F(x) = (kappa/2) x^T Ahat x + c'^T x and Ahat symmetric
+// with zero diagonal,
+//   F(x') - F(x) = sum_{i in D} delta_i (c'_i + kappa (Ahat x')_i)
+//                  - kappa sum_{i < j in D} delta_i delta_j Ahat_ij,
+// all in integers.  One workgroup per restart: the new rounded row is staged
+// in LDS, D is read off (and cleared from) the restart's bitmap, each wave
+// takes changed coordinates in turn and dots row i of Ahat with x'
+// (v_dot4_i32_i8, int32: |Ahat x'|_i <= 127 n), delta_i is +1 where x'_i = 1,
+// and the pairs are spread over the threads.  Restarts evaluated in full
+// (more than kFlipMax changes) only have their bitmap cleared.
+
+constexpr int kIncrThreads = 256;
+
+__global__ void __launch_bounds__(kIncrThreads)
+    eval_incr_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ work) {
+  constexpr int NW = kIncrThreads / 64;
+  extern __shared__ __attribute__((aligned(16))) uint8_t xr_s[];
+  __shared__ int fl[kFlipMax];
+  __shared__ int nfl;
+  __shared__ int64_t part[NW];
+  const int2 wk = work[blockIdx.x];
+  const InstDev& I = insts[wk.x];
+  const int b = wk.y;
+  const int k = I.nflip[b];
+  if (k == 0) return;  // unchanged: F carries over, the bitmap is clear
+  const int ld = I.ld, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int nw32 = ld / 32;
+  uint32_t* bits = I.fbits + (size_t)b * nw32;
+  if (k > kFlipMax) {  // evaluated in full
+    for (int w = tid; w < nw32; w += kIncrThreads) bits[w] = 0u;
+    return;
+  }
+  if (tid == 0) nfl = 0;
+  const int nv = ld / 16;
+  const u32x4* src = (const u32x4*)(I.Xr + (size_t)b * ld);
+  for (int v = tid; v < nv; v += kIncrThreads) ((u32x4*)xr_s)[v] = src[v];
+  __syncthreads();
+  for (int w = tid; w < nw32; w += kIncrThreads) {
+    uint32_t m = bits[w];
+    if (!m) continue;
+    bits[w] = 0u;
+    while (m) {
+      const int r = __builtin_ctz(m);
+      m &= m - 1u;
+      const int slot = atomicAdd(&nfl, 1);  // LDS; the order only permutes a sum
+      if (slot < kFlipMax) fl[slot] = 32 * w + r;
+    }
+  }
+  __syncthreads();
+  const int kk = min(nfl, kFlipMax);
+  int64_t acc64 = 0;
+  for (int e = wid; e < kk; e += NW) {
+    const int i = fl[e];
+    const u32x4* arow = (const u32x4*)(I.A8 + (size_t)i * ld);
+    int dot = 0;
+    for (int v = lane; v < nv; v += 64) {
+      const u32x4 a = arow[v];
+      const u32x4 x = ((const u32x4*)xr_s)[v];
+      dot = __builtin_amdgcn_sdot4((int)a.x, (int)x.x, dot, false);
+      dot = __builtin_amdgcn_sdot4((int)a.y, (int)x.y, dot, false);
+      dot = __builtin_amdgcn_sdot4((int)a.z, (int)x.z, dot, false);
+      dot = __builtin_amdgcn_sdot4((int)a.w, (int)x.w, dot, false);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
+    if (lane == 0) {
+      const int64_t d = xr_s[i] ? 1 : -1;
+      acc64 += d * (I.cp[i] + (int64_t)I.kappa * dot);
+    }
+  }
+  for (int pq = tid; pq < kk * kk; pq += kIncrThreads) {
+    const int e = pq / kk, f = pq % kk;
+    if (e < f) {
+      const int ie = fl[e], jf = fl[f];
+      const int de = xr_s[ie] ? 1 : -1, df = xr_s[jf] ? 1 : -1;
+      acc64 -= (int64_t)I.kappa * de * df * (int)I.A8[(size_t)ie * ld + jf];
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc64 += __shfl_xor(acc64, o);
+  if (lane == 0) part[wid] = acc64;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += part[w];
+    I.dF[b] = t;
+  }
+}
+
+hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, int max_ld,
+                            hipStream_t s) {
+  if (nwork == 0) return hipSuccess;
+  static int attr_ld = 0;
+  if (max_ld > attr_ld) {
+    hipError_t e = hipFuncSetAttribute((const void*)eval_incr_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_ld);
+    if (e != hipSuccess) return e;
+    attr_ld = max_ld;
+  }
+  hipLaunchKernelGGL(eval_incr_kernel, dim3(nwork), dim3(kIncrThreads), (size_t)max_ld, s, insts,
+                     work);
+  return hipGetLastError();
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t cnt) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < cnt) p[idx] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v,
+                     count);
   return hipGetLastError();
 }
 

@@ -196,3 +196,35 @@ def test_batched_grouped_equals_per_instance_and_single():
             assert r["best_obj"] == rg[i]["best_obj"] and r["best_iter"] == rg[i]["best_iter"]
             assert np.array_equal(r["best_x"], rg[i]["best_x"])
         assert rg[i]["best_obj"] == oq.objective(q, rg[i]["best_x"][None])[0]
+
+
+@pytest.mark.parametrize("tile", [0, 1, 8])
+def test_incremental_objectives_every_step(tile):
+    """The objectives the in-loop evaluation keeps (a full product first, then
+    exact differences from the recorded rounding changes, or a full product for
+    column blocks where some restart changed many coordinates) equal the
+    oracle's at every step; the run passes through both regimes."""
+    P = require_gpu()
+    n, B = 600, 300
+    q = W.random_dense_qubo(n, -50, 50, W.rng_for(7, 0, 0, n))
+    s = W.qubo_scale(q)
+    x0 = W.x0_uniform(7, 0, B, n)
+    p = W.gda_params("qubo", B=B, T=1, scale=s, precision="i8", tile=tile)
+    say(f"[incremental eval] n={n} B={B} tile={tile}")
+    ctx = P.qubo_gda_init(q, p, x0)
+    prev = None
+    few = many = 0
+    for t in range(80):
+        ctx.step(1)
+        Xg, _, _ = ctx.get_state()
+        xr = Xg > 0.5
+        assert np.array_equal(ctx.objectives(), oq.objective(q, xr)), t
+        if prev is not None:
+            k = np.sum(xr != prev, axis=1)
+            few += int(np.sum((k >= 1) & (k <= 32)))
+            many += int(np.sum(k > 32))
+        prev = xr
+    say(f"   (restart, step) pairs with 1..32 changes {few}, with more {many}")
+    assert few > 0 and many > 0
+    r = ctx.result()
+    assert r["best_obj"] == oq.objective(q, r["best_x"][None])[0]
