@@ -260,6 +260,12 @@ enum { PDBO_K_STEP = 0, PDBO_K_EVAL = 1, PDBO_K_ARGMIN = 2, PDBO_K_PERSISTENT = 
  * context, on the context's stream.  Clears the accumulated times. */
 PDBO_API pdbo_status pdbo_timing(pdbo_ctx* ctx, int32_t enable);
 
+/* Times only the launches of the kernel classes in mask (bit k = PDBO_K_k;
+ * 0 disables timing): every timed launch costs two event records on the
+ * stream, so a caller that needs one class measures the others separately.
+ * Clears the accumulated times.  PDBO_EINVAL for bits beyond PDBO_K_COUNT. */
+PDBO_API pdbo_status pdbo_timing_classes(pdbo_ctx* ctx, uint32_t mask);
+
 /* Accumulated device time (ms) and launch count of kernel class `which`
  * (PDBO_K_*) since timing was enabled.  Synchronises. */
 PDBO_API pdbo_status pdbo_kernel_time(pdbo_ctx* ctx, int32_t which, double* total_ms, int64_t* launches);

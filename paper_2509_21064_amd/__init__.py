@@ -152,8 +152,15 @@ class Context:
     def trace(self, cap=4096):
         return qubo_gda_trace(self, cap)
 
-    def timing(self, enable=True):
-        check(load().pdbo_timing(self.h, int(bool(enable))), self.h)
+    def timing(self, enable=True, classes=None):
+        """Kernel timing on (all classes, or the PDBO_K_* classes listed) or off."""
+        if classes is not None and enable:
+            mask = 0
+            for k in classes:
+                mask |= 1 << int(k)
+            check(load().pdbo_timing_classes(self.h, mask), self.h)
+        else:
+            check(load().pdbo_timing(self.h, int(bool(enable))), self.h)
 
     def kernel_time(self, which):
         ms, cnt = ctypes.c_double(), ctypes.c_int64()

@@ -7,7 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint8, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint8, c_uint32, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpdbo.so")
@@ -71,6 +71,7 @@ SIGNATURES = {
     "qubo_gda_trace": (_st, [_ctx, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                              POINTER(c_int32)]),
     "pdbo_timing": (_st, [_ctx, c_int32]),
+    "pdbo_timing_classes": (_st, [_ctx, c_uint32]),
     "pdbo_kernel_time": (_st, [_ctx, c_int32, POINTER(c_double), POINTER(c_int64)]),
     "pdbo_tile_name": (c_char_p, [_ctx]),
     "pdbo_destroy": (None, [_ctx]),

@@ -97,6 +97,7 @@ struct pdbo_ctx {
   uint64_t* ts0_d = nullptr;
   // timing
   bool timing = false;
+  uint32_t tmask = 0;  // kernel classes being timed (bit k = PDBO_K_k)
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> ev_pool;  // events already read, reused by later launches
   double ms[PDBO_K_COUNT] = {};
@@ -446,7 +447,7 @@ hipEvent_t ev_get(pdbo_ctx* c) {
 // Brackets one launch with a pair of events on the context's stream.
 void t_begin(pdbo_ctx* c, TimedLaunch& tl, int cls) {
   tl.cls = -1;
-  if (!c->timing) return;
+  if (!c->timing || !((c->tmask >> cls) & 1u)) return;
   tl.a = ev_get(c);
   if (!tl.a) return;
   tl.b = ev_get(c);
@@ -1624,16 +1625,22 @@ pdbo_status qubo_gda_trace(pdbo_ctx* c, int32_t cap, int64_t* t, int64_t* F, int
 
 // ---------------------------------------------------------------- timing
 
-pdbo_status pdbo_timing(pdbo_ctx* c, int32_t enable) {
+pdbo_status pdbo_timing_classes(pdbo_ctx* c, uint32_t mask) {
   if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
+  if (mask >> PDBO_K_COUNT) return fail(c, PDBO_EINVAL, "mask names an unknown kernel class");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   t_collect(c);
   for (int k = 0; k < PDBO_K_COUNT; ++k) {
     c->ms[k] = 0.0;
     c->cnt[k] = 0;
   }
-  c->timing = enable != 0;
+  c->tmask = mask;
+  c->timing = mask != 0;
   return PDBO_OK;
+}
+
+pdbo_status pdbo_timing(pdbo_ctx* c, int32_t enable) {
+  return pdbo_timing_classes(c, enable ? (1u << PDBO_K_COUNT) - 1u : 0u);
 }
 
 pdbo_status pdbo_kernel_time(pdbo_ctx* c, int32_t which, double* total_ms, int64_t* launches) {
