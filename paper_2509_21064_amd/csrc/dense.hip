@@ -472,7 +472,9 @@ __device__ __forceinline__ void gemm_epilogue_rows(
   constexpr int PR = rows_per_pass<BM, BN, STAGE>();
   constexpr int NP = BN / PR;                      // passes
   constexpr int EPP = PR * C4 / NT;                // elements per thread and pass
-  constexpr int PF = 2;                            // elements per prefetch group
+  // elements per prefetch group: as many as divide the thread's share of a pass
+  // (up to 5), so that enough x/y loads are in flight to cover the latency
+  constexpr int PF = EPP % 5 == 0 ? 5 : EPP % 4 == 0 ? 4 : EPP % 2 == 0 ? 2 : 1;
   constexpr int GPP = EPP / PF;                    // groups per pass
   static_assert(PR * BM * 4 <= STAGE && BN % PR == 0 && PR % 16 == 0, "pass shape");
   static_assert(C4 % 8 == 0 && (PR * C4) % NT == 0 && EPP % PF == 0, "row epilogue shape");
