@@ -75,7 +75,6 @@ struct pdbo_ctx {
   // incremental evaluation: one workgroup per (instance, restart), in instance order
   int2* incr_work_d = nullptr;
   std::vector<int> incr_off;  // first work item of each instance, plus the total
-  int incr_ld = 0;            // largest row length (bytes of one rounded row)
   int grouped = 1;
   InstDev* scratch_inst_d = nullptr;
   float* gx_scratch = nullptr;     // fp32 x for grad()
@@ -654,12 +653,10 @@ pdbo_status upload_dense_tables(pdbo_ctx* c) {
   build_tiles(c);
   std::vector<int2> work;  // alive until the stream is synchronised below
   c->incr_off.clear();
-  c->incr_ld = 0;
   for (size_t k = 0; k < c->insts_h.size(); ++k) {
     c->incr_off.push_back((int)work.size());
     if (!c->insts_h[k].nflip) continue;
     for (int b = 0; b < c->insts_h[k].B; ++b) work.push_back(make_int2((int)k, b));
-    c->incr_ld = std::max(c->incr_ld, c->insts_h[k].ld);
   }
   c->incr_off.push_back((int)work.size());
   if (!work.empty()) {
@@ -841,8 +838,7 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
       t_end(c, tl);
       if (c->incr_off.back() > 0) {
         t_begin(c, tl, PDBO_K_INCR);
-        HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d, c->incr_off.back(), c->incr_ld,
-                                   c->stream));
+        HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d, c->incr_off.back(), c->stream));
         t_end(c, tl);
       }
     }
@@ -865,7 +861,7 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
         const int w0 = c->incr_off[k], nw = c->incr_off[k + 1] - w0;
         if (nw > 0) {
           t_begin(c, tl, PDBO_K_INCR);
-          HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d + w0, nw, c->incr_ld, c->stream));
+          HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d + w0, nw, c->stream));
           t_end(c, tl);
         }
       }

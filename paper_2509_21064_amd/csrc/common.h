@@ -134,8 +134,7 @@ hipError_t launch_dense_gemm(int cfg, int prec, int epi, const TileDev* tiles, i
                              const InstDev* insts, int parity, int grid, hipStream_t s);
 hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, hipStream_t s);
 // work[w] = (instance, first restart) of the workgroups of the incremental evaluation
-hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, int max_ld,
-                            hipStream_t s);
+hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
 hipError_t launch_stamp(uint64_t* ts0, hipStream_t s);
 hipError_t launch_init_state(const double* x0, int B, int n, int ld, float y0, float* X,

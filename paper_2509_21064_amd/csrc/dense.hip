@@ -1137,21 +1137,23 @@ hipError_t launch_quantize_A(const int32_t* Ahat, int n, int ld, int prec, uint8
 // with zero diagonal,
 //   F(x') - F(x) = sum_{i in D} delta_i (c'_i + kappa (Ahat x')_i)
 //                  - kappa sum_{i < j in D} delta_i delta_j Ahat_ij,
-// all in integers.  One workgroup per restart: the new rounded row is staged
-// in LDS, D is read off (and cleared from) the restart's bitmap, each wave
-// takes changed coordinates in turn and dots row i of Ahat with x'
-// (v_dot4_i32_i8, int32: |Ahat x'|_i <= 127 n), delta_i is +1 where x'_i = 1,
-// and the pairs are spread over the threads.  Restarts evaluated in full
-// (more than kFlipMax changes) only have their bitmap cleared.
+// all in integers.  One workgroup per restart: D is read off (and cleared
+// from) the restart's bitmap; then every thread takes 16-byte chunks of the
+// new rounded row and accumulates the dot products of all rows i in D of
+// Ahat with them at once (v_dot4_i32_i8, int32: |Ahat x'|_i <= 127 n), so the
+// row is read once and all the loads of a chunk are in flight together;
+// delta_i is +1 where x'_i = 1, and the pairs are spread over the threads.
+// Restarts evaluated in full (more than kFlipMax changes) only have their
+// bitmap cleared.
 
 constexpr int kIncrThreads = 256;
 
 __global__ void __launch_bounds__(kIncrThreads)
     eval_incr_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ work) {
   constexpr int NW = kIncrThreads / 64;
-  extern __shared__ __attribute__((aligned(16))) uint8_t xr_s[];
   __shared__ int fl[kFlipMax];
   __shared__ int nfl;
+  __shared__ int red[NW][kFlipMax];
   __shared__ int64_t part[NW];
   const int2 wk = work[blockIdx.x];
   const InstDev& I = insts[wk.x];
@@ -1166,9 +1168,6 @@ __global__ void __launch_bounds__(kIncrThreads)
     return;
   }
   if (tid == 0) nfl = 0;
-  const int nv = ld / 16;
-  const u32x4* src = (const u32x4*)(I.Xr + (size_t)b * ld);
-  for (int v = tid; v < nv; v += kIncrThreads) ((u32x4*)xr_s)[v] = src[v];
   __syncthreads();
   for (int w = tid; w < nw32; w += kIncrThreads) {
     uint32_t m = bits[w];
@@ -1183,31 +1182,50 @@ __global__ void __launch_bounds__(kIncrThreads)
   }
   __syncthreads();
   const int kk = min(nfl, kFlipMax);
-  int64_t acc64 = 0;
-  for (int e = wid; e < kk; e += NW) {
-    const int i = fl[e];
-    const u32x4* arow = (const u32x4*)(I.A8 + (size_t)i * ld);
-    int dot = 0;
-    for (int v = lane; v < nv; v += 64) {
-      const u32x4 a = arow[v];
-      const u32x4 x = ((const u32x4*)xr_s)[v];
-      dot = __builtin_amdgcn_sdot4((int)a.x, (int)x.x, dot, false);
-      dot = __builtin_amdgcn_sdot4((int)a.y, (int)x.y, dot, false);
-      dot = __builtin_amdgcn_sdot4((int)a.z, (int)x.z, dot, false);
-      dot = __builtin_amdgcn_sdot4((int)a.w, (int)x.w, dot, false);
-    }
+  const int8_t* xrow = I.Xr + (size_t)b * ld;
+  const int nv = ld / 16;
+  int dot[kFlipMax];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
-    if (lane == 0) {
-      const int64_t d = xr_s[i] ? 1 : -1;
-      acc64 += d * (I.cp[i] + (int64_t)I.kappa * dot);
+  for (int e = 0; e < kFlipMax; ++e) dot[e] = 0;
+  for (int v = tid; v < nv; v += kIncrThreads) {
+    const u32x4 x = *(const u32x4*)(xrow + (size_t)v * 16);
+#pragma unroll
+    for (int e = 0; e < kFlipMax; ++e) {
+      if (e < kk) {
+        const u32x4 a = *(const u32x4*)(I.A8 + (size_t)fl[e] * ld + (size_t)v * 16);
+        int d = dot[e];
+        d = __builtin_amdgcn_sdot4((int)a.x, (int)x.x, d, false);
+        d = __builtin_amdgcn_sdot4((int)a.y, (int)x.y, d, false);
+        d = __builtin_amdgcn_sdot4((int)a.z, (int)x.z, d, false);
+        d = __builtin_amdgcn_sdot4((int)a.w, (int)x.w, d, false);
+        dot[e] = d;
+      }
     }
+  }
+#pragma unroll
+  for (int e = 0; e < kFlipMax; ++e) {
+    if (e < kk) {
+      int d = dot[e];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+      if (lane == 0) red[wid][e] = d;
+    }
+  }
+  __syncthreads();
+  int64_t acc64 = 0;
+  if (tid < kk) {
+    const int i = fl[tid];
+    int d = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) d += red[w][tid];
+    const int64_t sgn = xrow[i] ? 1 : -1;
+    acc64 = sgn * (I.cp[i] + (int64_t)I.kappa * d);
   }
   for (int pq = tid; pq < kk * kk; pq += kIncrThreads) {
     const int e = pq / kk, f = pq % kk;
     if (e < f) {
       const int ie = fl[e], jf = fl[f];
-      const int de = xr_s[ie] ? 1 : -1, df = xr_s[jf] ? 1 : -1;
+      const int de = xrow[ie] ? 1 : -1, df = xrow[jf] ? 1 : -1;
       acc64 -= (int64_t)I.kappa * de * df * (int)I.A8[(size_t)ie * ld + jf];
     }
   }
@@ -1223,18 +1241,9 @@ __global__ void __launch_bounds__(kIncrThreads)
   }
 }
 
-hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, int max_ld,
-                            hipStream_t s) {
+hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
-  static int attr_ld = 0;
-  if (max_ld > attr_ld) {
-    hipError_t e = hipFuncSetAttribute((const void*)eval_incr_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_ld);
-    if (e != hipSuccess) return e;
-    attr_ld = max_ld;
-  }
-  hipLaunchKernelGGL(eval_incr_kernel, dim3(nwork), dim3(kIncrThreads), (size_t)max_ld, s, insts,
-                     work);
+  hipLaunchKernelGGL(eval_incr_kernel, dim3(nwork), dim3(kIncrThreads), 0, s, insts, work);
   return hipGetLastError();
 }
 
