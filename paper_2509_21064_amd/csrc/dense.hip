@@ -8,7 +8,9 @@
 //   EPI_EVAL : E = Ahat . Xr in int8 x int8 -> int32, reduced on the fly to
 //              x_r^T Ahat x_r and c'^T x_r per restart with int64 atomics
 //              (integer addition is exact in any order, so the totals are
-//              bit-reproducible).
+//              bit-reproducible); a tile whose restarts all changed few
+//              rounded coordinates exits at once, their objectives come from
+//              eval_incr_kernel (the incremental evaluation below).
 //
 // Operands are both K-contiguous: row i of Ahat (Ahat is symmetric) and row b
 // of the restart-major shadow.  Every K step consumes one 128-byte chunk of

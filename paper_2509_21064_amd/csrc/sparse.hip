@@ -29,7 +29,7 @@ static size_t csr_lds_need(int n, int64_t nnz, bool packed) {
 constexpr size_t kLdsBudget = 150 * 1024;
 
 // The persistent kernel needs x of one restart in LDS and at most 32768 rows
-// (1024 threads x 32 rows in registers).  With packed entries (16-bit column,
+// (512 threads x 64 rows).  With packed entries (16-bit column,
 // 16-bit value) the whole canonical matrix is staged in LDS too when it fits;
 // otherwise the CSR arrays are read through the L2.
 bool csr_fits(int n, int64_t nnz, bool packed, size_t* lds_bytes) {
