@@ -559,12 +559,18 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
 
   const size_t sz = (size_t)B * ld;
   STCHK(dalloc(c, &I.X[0], sz));
-  STCHK(dalloc(c, &I.X[1], sz));
   STCHK(dalloc(c, &I.Y, sz));
   if (prec == PDBO_FP32) {
+    // x is the GEMM operand itself: tiles of one step read x^t while others
+    // write x^{t+1}, so the two must be distinct
+    STCHK(dalloc(c, &I.X[1], sz));
     I.Xs[0] = (uint8_t*)I.X[0];
     I.Xs[1] = (uint8_t*)I.X[1];
   } else {
+    // the GEMM reads the operand shadow; each x value is read and rewritten
+    // by the same thread of the step epilogue, so x is updated in place (one
+    // buffer less to keep in the last-level cache)
+    I.X[1] = I.X[0];
     STCHK(dalloc(c, &I.Xs[0], sz * EB));
     STCHK(dalloc(c, &I.Xs[1], sz * EB));
   }
