@@ -228,3 +228,35 @@ def test_incremental_objectives_every_step(tile):
     assert few > 0 and many > 0
     r = ctx.result()
     assert r["best_obj"] == oq.objective(q, r["best_x"][None])[0]
+
+
+def test_timing_classes_and_trace():
+    """Per-class timing counts exactly the launches of the classes asked for;
+    an unknown class is rejected; the incumbent trace improves strictly and ends
+    at the result."""
+    P = require_gpu()
+    q = W.qubo_c1(0)
+    B = 64
+    x0 = W.x0_uniform(1, 0, B, q.n)
+    p = W.gda_params("qubo", B=B, T=1, scale=W.qubo_scale(q), precision="i8")
+    ctx = P.qubo_gda_init(q, p, x0)
+    ctx.timing(True, classes=[P.PDBO_K_STEP])
+    ctx.step(7)
+    ms, cnt = ctx.kernel_time(P.PDBO_K_STEP)
+    assert cnt == 7 and ms > 0
+    for k in (P.PDBO_K_EVAL, P.PDBO_K_INCR, P.PDBO_K_ARGMIN):
+        assert ctx.kernel_time(k)[1] == 0
+    ctx.timing(True)
+    ctx.step(3)
+    for k in (P.PDBO_K_STEP, P.PDBO_K_EVAL, P.PDBO_K_INCR, P.PDBO_K_ARGMIN):
+        assert ctx.kernel_time(k)[1] == 3, k
+    with pytest.raises(P.PdboError):
+        ctx.timing(True, classes=[7])
+    ctx.timing(False)
+    ctx.step(40)
+    tr = ctx.trace()
+    r = ctx.result()
+    assert len(tr["F"]) >= 1
+    assert np.all(np.diff(tr["F"]) < 0) and np.all(np.diff(tr["t"]) > 0)
+    assert tr["F"][-1] == r["best_obj"] and tr["t"][-1] == r["best_iter"]
+    assert r["best_obj"] == oq.objective(q, r["best_x"][None])[0]

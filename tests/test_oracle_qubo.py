@@ -190,3 +190,35 @@ def test_real_weight_objective_fsum():
     exact = sum(Fraction(Q[i, j]) for i in S for j in S) + sum(Fraction(c[i]) for i in S)
     assert oq.objective_fsum(Q, c, x) == float(exact)
     assert math.isfinite(oq.objective_fsum(Q, None, x))
+
+
+@pytest.mark.parametrize("even", [False, True])
+def test_incremental_difference_identity(even):
+    """The identity behind the incremental evaluation: for x' = x + d (d = +-1 on
+    a set D of changed coordinates) and A = offdiag(Q + Q^T) = kappa Ahat,
+    F(x') - F(x) = sum_{i in D} d_i (c'_i + kappa (Ahat x')_i)
+                   - kappa sum_{i < j in D} d_i d_j Ahat_ij,
+    checked against the objective computed from scratch (Eq. 1), with an
+    asymmetric Q and a diagonal, and with all couplings even (kappa = 2)."""
+    g = np.random.default_rng(11 + even)
+    n = 40
+    Q = g.integers(-9, 10, size=(n, n)).astype(np.int64)
+    if even:
+        Q = 2 * Q
+        np.fill_diagonal(Q, g.integers(-9, 10, n))
+    q = W.Qubo(n=n, Q=Q, c=g.integers(-20, 21, n).astype(np.int64))
+    A, cp = oq.canonicalize(q)
+    kappa = 2 if np.all(A.astype(np.int64) % 2 == 0) else 1
+    assert kappa == (2 if even else 1)
+    Ah = (A / kappa).astype(np.int64)
+    for trial in range(30):
+        x = (g.random(n) < 0.5).astype(np.int64)
+        D = g.choice(n, size=int(g.integers(1, 9)), replace=False)
+        xn = x.copy()
+        xn[D] = 1 - xn[D]
+        d = xn - x
+        Ax = Ah @ xn
+        lin = sum(int(d[i]) * (int(cp[i]) + kappa * int(Ax[i])) for i in D)
+        quad = sum(int(d[i]) * int(d[j]) * int(Ah[i, j]) for i in D for j in D if i < j)
+        F = oq.objective(q, np.stack([x, xn]).astype(np.uint8))
+        assert F[1] - F[0] == lin - kappa * quad
