@@ -146,7 +146,8 @@ pdbo_status dalloc(pdbo_ctx* c, T** p, size_t count) {
 
 void free_all(pdbo_ctx* c) {
   if (!c) return;
-  if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+  // the context's stream may be the null (legacy default) stream: synchronise it either way
+  (void)hipStreamSynchronize(c->stream);
   for (auto& t : c->pending) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
