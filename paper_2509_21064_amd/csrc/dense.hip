@@ -153,102 +153,139 @@ constexpr int gemm_lds_bytes() {
 // improvement update of the incumbent, copy of the winning rounded vector.
 // mode 0: no evaluation this iteration (only the iteration counter advances);
 // mode 1: evaluation and incumbent update; mode 2: objectives only.
+//
+// The kernel is a short chain of dependent steps, so its length is set by how
+// many memory round trips it waits for: every load it needs (including the
+// incumbent and the trace length) goes out in one batch, the reduction runs in
+// registers and through LDS, and the stores are issued last, after the
+// barriers, so that no barrier waits for them.
+__device__ __forceinline__ void argmin_pair(int64_t& F, int& b, int64_t F2, int b2) {
+  if (F2 < F || (F2 == F && b2 < b)) {
+    F = F2;
+    b = b2;
+  }
+}
+
 template <int NT>
 __device__ void best_of_B(const InstDev& I, int mode, int tid, int64_t* sF, int* sb,
                           int* improved) {
-  const int64_t t = *I.t_dev + 1;
-  if (mode != 0) {
-    // Loads are batched ahead of the stores: Fall, Sacc and Cacc are distinct
-    // arrays, but the compiler cannot know it and would otherwise wait a
-    // memory round trip per restart.  Each thread visits its restarts in
-    // increasing order, so the strict comparison keeps the first minimum.
-    constexpr int U = 4;
-    int64_t bestF = LLONG_MAX;
-    int bestb = INT_MAX;
-    // A restart with at most kFlipMax recorded rounding changes takes its
-    // previous objective plus the exact difference; the others (and every
-    // restart when nflip is absent) take the full product's partials.
-    for (int b0 = 0; b0 < I.B; b0 += U * NT) {
-      int64_t S[U], C[U], Fp[U], dF[U];
-      int k[U];
+  static_assert(NT % 64 == 0 && NT / 64 <= 64, "whole waves, one per lane of the last step");
+  constexpr int NW = NT / 64, U = 4;
+  const int64_t t = *gptr(I.t_dev) + 1;
+  if (mode == 0) {
+    if (tid == 0) *I.t_dev = t;
+    return;
+  }
+  const int lane = tid & 63, wid = tid >> 6;
+  int64_t incF = 0;
+  int tlen = 0;
+  if (tid == 0 && mode == 1) {
+    incF = *gptr(&I.inc->F);
+    tlen = *gptr(I.trace_len);
+  }
+  int64_t bestF = LLONG_MAX;
+  int bestb = INT_MAX;
+  // A restart with at most kFlipMax recorded rounding changes takes its
+  // previous objective plus the exact difference; the others (and every
+  // restart when nflip is absent) take the full product's partials.  Each
+  // thread visits its restarts in increasing order, so the strict comparison
+  // keeps the first minimum.
+  int64_t F1[U];  // the objectives of the first batch, stored after the barriers
+  for (int b0 = 0; b0 < I.B; b0 += U * NT) {
+    int64_t S[U], C[U], Fp[U], dF[U];
+    int k[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int b = b0 + u * NT + tid;
-        const bool ok = b < I.B;
-        S[u] = ok ? I.Sacc[b] : 0;
-        C[u] = ok ? I.Cacc[b] : 0;
-        k[u] = (ok && I.nflip) ? I.nflip[b] : kFlipMax + 1;
-        Fp[u] = (ok && k[u] <= kFlipMax) ? I.Fall[b] : 0;
-        dF[u] = (ok && k[u] > 0 && k[u] <= kFlipMax) ? I.dF[b] : 0;
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u * NT + tid;
+      const bool ok = b < I.B;
+      S[u] = ok ? *gptr(I.Sacc + b) : 0;
+      C[u] = ok ? *gptr(I.Cacc + b) : 0;
+      k[u] = (ok && I.nflip) ? *gptr(I.nflip + b) : kFlipMax + 1;
+      Fp[u] = ok ? *gptr(I.Fall + b) : 0;
+      dF[u] = (ok && I.nflip) ? *gptr(I.dF + b) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u * NT + tid;
+      const int64_t F = k[u] == 0 ? Fp[u]
+                        : k[u] <= kFlipMax ? Fp[u] + dF[u]
+                                           : (I.kappa == 2 ? S[u] : S[u] / 2) + C[u];
+      if (b < I.B && F < bestF) {
+        bestF = F;
+        bestb = b;
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int b = b0 + u * NT + tid;
-        if (b >= I.B) continue;
-        I.Sacc[b] = 0;  // ready for the next evaluation
+      if (b0 == 0) {
+        F1[u] = F;
+      } else if (b < I.B) {  // more than U * NT restarts: store as we go
+        I.Sacc[b] = 0;
         I.Cacc[b] = 0;
         if (I.nflip && mode == 1) I.nflip[b] = 0;
-        const int64_t F =
-            k[u] <= kFlipMax ? Fp[u] + dF[u] : (I.kappa == 2 ? S[u] : S[u] / 2) + C[u];
         I.Fall[b] = F;
-        if (F < bestF) {
-          bestF = F;
-          bestb = b;
-        }
-      }
-    }
-    sF[tid] = bestF;
-    sb[tid] = bestb;
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-      if (tid < h) {
-        const int64_t f2 = sF[tid + h];
-        const int b2 = sb[tid + h];
-        if (f2 < sF[tid] || (f2 == sF[tid] && b2 < sb[tid])) {
-          sF[tid] = f2;
-          sb[tid] = b2;
-        }
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      *improved = 0;
-      if (mode == 1 && sF[0] < I.inc->F) {
-        const uint64_t ts = wall_clock();
-        I.inc->F = sF[0];
-        I.inc->t = t;
-        I.inc->b = sb[0];
-        I.inc->ts = ts;
-        const int k = *I.trace_len;
-        if (k < I.trace_cap) {
-          I.trace[k] = TraceRec{t, sF[0], (int64_t)sb[0], ts};
-          *I.trace_len = k + 1;
-        }
-        *improved = 1;
-      }
-    }
-    __syncthreads();
-    if (*improved) {
-      // whole 16-byte words of the winning row (best_x holds ld bytes)
-      const u32x4* src = (const u32x4*)(I.Xr + (size_t)sb[0] * I.ld);
-      u32x4* dst = (u32x4*)I.best_x;
-      const int nv = I.ld / 16;
-      for (int v0 = 0; v0 < nv; v0 += U * NT) {
-        u32x4 r[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int v = v0 + u * NT + tid;
-          if (v < nv) r[u] = src[v];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int v = v0 + u * NT + tid;
-          if (v < nv) dst[v] = r[u];
-        }
       }
     }
   }
-  if (tid == 0 && mode != 2) *I.t_dev = t;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+    argmin_pair(bestF, bestb, __shfl_xor(bestF, o), __shfl_xor(bestb, o));
+  if (lane == 0) {
+    sF[wid] = bestF;
+    sb[wid] = bestb;
+  }
+  __syncthreads();
+  if (wid == 0) {
+    bestF = lane < NW ? sF[lane] : LLONG_MAX;
+    bestb = lane < NW ? sb[lane] : INT_MAX;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+      argmin_pair(bestF, bestb, __shfl_xor(bestF, o), __shfl_xor(bestb, o));
+    if (lane == 0) {
+      int imp = 0;
+      if (mode == 1 && bestF < incF) {
+        const uint64_t ts = wall_clock();
+        I.inc->F = bestF;
+        I.inc->t = t;
+        I.inc->b = bestb;
+        I.inc->ts = ts;
+        if (tlen < I.trace_cap) {
+          I.trace[tlen] = TraceRec{t, bestF, (int64_t)bestb, ts};
+          *I.trace_len = tlen + 1;
+        }
+        imp = 1;
+      }
+      *improved = imp;
+      sb[0] = bestb;
+      if (mode != 2) *I.t_dev = t;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int b = u * NT + tid;
+    if (b >= I.B) continue;
+    I.Sacc[b] = 0;  // ready for the next evaluation
+    I.Cacc[b] = 0;
+    if (I.nflip && mode == 1) I.nflip[b] = 0;
+    I.Fall[b] = F1[u];
+  }
+  if (*improved) {
+    // whole 16-byte words of the winning row (best_x holds ld bytes)
+    const u32x4* src = (const u32x4*)(I.Xr + (size_t)sb[0] * I.ld);
+    u32x4* dst = (u32x4*)I.best_x;
+    const int nv = I.ld / 16;
+    for (int v0 = 0; v0 < nv; v0 += U * NT) {
+      u32x4 r[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int v = v0 + u * NT + tid;
+        if (v < nv) r[u] = src[v];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int v = v0 + u * NT + tid;
+        if (v < nv) dst[v] = r[u];
+      }
+    }
+  }
 }
 
 // Rounding changes of coordinates i..i+3 of restart b (bytes of the old and
@@ -1028,8 +1065,8 @@ constexpr int kArgThreads = 1024;
 
 __global__ void __launch_bounds__(kArgThreads)
     argmin_kernel(const InstDev* __restrict__ insts, int inst0, int mode) {
-  __shared__ int64_t sF[kArgThreads];
-  __shared__ int sb[kArgThreads];
+  __shared__ int64_t sF[kArgThreads / 64];
+  __shared__ int sb[kArgThreads / 64];
   __shared__ int improved;
   best_of_B<kArgThreads>(insts[inst0 + blockIdx.x], mode, threadIdx.x, sF, sb, &improved);
 }
@@ -1141,18 +1178,26 @@ hipError_t launch_quantize_A(const int32_t* Ahat, int n, int ld, int prec, uint8
 //                  - kappa sum_{i < j in D} delta_i delta_j Ahat_ij,
 // all in integers.  One workgroup per restart: D is read off (and cleared
 // from) the restart's bitmap; then every thread takes 16-byte chunks of the
-// new rounded row and accumulates the dot products of all rows i in D of
-// Ahat with them at once (v_dot4_i32_i8, int32: |Ahat x'|_i <= 127 n), so the
-// row is read once and all the loads of a chunk are in flight together;
-// delta_i is +1 where x'_i = 1, and the pairs are spread over the threads.
-// Restarts evaluated in full (more than kFlipMax changes) only have their
-// bitmap cleared.
+// new rounded row and accumulates the dot products of the rows i in D of Ahat
+// with them (v_dot4_i32_i8, int32: |Ahat x'|_i <= 127 n); delta_i is +1 where
+// x'_i = 1, and the pairs are spread over the threads.  Restarts evaluated in
+// full (more than kFlipMax changes) only have their bitmap cleared.
+//
+// At a few changes per restart the kernel is a chain of memory round trips,
+// so the loads are issued in as few batches as possible: the count with the
+// first bitmap words; then the row chunks of x', the chunks of up to
+// kIncrE rows of D at once (each thread holds kIncrV chunks of every row, so
+// one pass covers rows of up to kIncrThreads * kIncrV * 16 bytes), and the
+// signs, linear terms and pair entries that the last stage needs.
 
 constexpr int kIncrThreads = 256;
+constexpr int kIncrV = 3;  // 16-byte chunks of a row per thread and pass
+constexpr int kIncrE = 4;  // rows of D loaded together
 
 __global__ void __launch_bounds__(kIncrThreads)
     eval_incr_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ work) {
-  constexpr int NW = kIncrThreads / 64;
+  constexpr int NT = kIncrThreads, NW = NT / 64, V = kIncrV, E = kIncrE;
+  static_assert(kFlipMax % E == 0, "whole groups of rows");
   __shared__ int fl[kFlipMax];
   __shared__ int nfl;
   __shared__ int red[NW][kFlipMax];
@@ -1160,20 +1205,21 @@ __global__ void __launch_bounds__(kIncrThreads)
   const int2 wk = work[blockIdx.x];
   const InstDev& I = insts[wk.x];
   const int b = wk.y;
-  const int k = I.nflip[b];
-  if (k == 0) return;  // unchanged: F carries over, the bitmap is clear
   const int ld = I.ld, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int nw32 = ld / 32;
-  uint32_t* bits = I.fbits + (size_t)b * nw32;
-  if (k > kFlipMax) {  // evaluated in full
-    for (int w = tid; w < nw32; w += kIncrThreads) bits[w] = 0u;
-    return;
-  }
+  PDBO_GLOBAL uint32_t* bits = gptr(I.fbits + (size_t)b * nw32);
+  const int k = *gptr(I.nflip + b);
+  const uint32_t m0 = tid < nw32 ? bits[tid] : 0u;  // with the count, before it is known
+  if (k == 0) return;  // unchanged: F carries over, the bitmap is clear
   if (tid == 0) nfl = 0;
   __syncthreads();
-  for (int w = tid; w < nw32; w += kIncrThreads) {
-    uint32_t m = bits[w];
-    if (!m) continue;
+  if (k > kFlipMax) {  // evaluated in full
+    if (m0) bits[tid] = 0u;
+    for (int w = tid + NT; w < nw32; w += NT) bits[w] = 0u;
+    return;
+  }
+  auto take = [&](int w, uint32_t m) {
+    if (!m) return;
     bits[w] = 0u;
     while (m) {
       const int r = __builtin_ctz(m);
@@ -1181,54 +1227,83 @@ __global__ void __launch_bounds__(kIncrThreads)
       const int slot = atomicAdd(&nfl, 1);  // LDS; the order only permutes a sum
       if (slot < kFlipMax) fl[slot] = 32 * w + r;
     }
-  }
+  };
+  take(tid, m0);
+  for (int w = tid + NT; w < nw32; w += NT) take(w, bits[w]);
   __syncthreads();
   const int kk = min(nfl, kFlipMax);
-  const int8_t* xrow = I.Xr + (size_t)b * ld;
-  const int nv = ld / 16;
-  int dot[kFlipMax];
-#pragma unroll
-  for (int e = 0; e < kFlipMax; ++e) dot[e] = 0;
-  for (int v = tid; v < nv; v += kIncrThreads) {
-    const u32x4 x = *(const u32x4*)(xrow + (size_t)v * 16);
-#pragma unroll
-    for (int e = 0; e < kFlipMax; ++e) {
-      if (e < kk) {
-        const u32x4 a = *(const u32x4*)(I.A8 + (size_t)fl[e] * ld + (size_t)v * 16);
-        int d = dot[e];
-        d = __builtin_amdgcn_sdot4((int)a.x, (int)x.x, d, false);
-        d = __builtin_amdgcn_sdot4((int)a.y, (int)x.y, d, false);
-        d = __builtin_amdgcn_sdot4((int)a.z, (int)x.z, d, false);
-        d = __builtin_amdgcn_sdot4((int)a.w, (int)x.w, d, false);
-        dot[e] = d;
-      }
-    }
+  if (kk == 0) {  // a count without marks: nothing to add
+    if (tid == 0) *gptr(I.dF + b) = 0;
+    return;
   }
+  const PDBO_GLOBAL int8_t* xrow = gptr(I.Xr + (size_t)b * ld);
+  const PDBO_GLOBAL int8_t* A8 = gptr(I.A8);
+  const int nv = ld / 16;
+
+  // operands of the last stage: sign and linear term of change tid, and the
+  // first pass of pairs (e, f), e < f.  They are loaded without branches, at
+  // clamped (valid) indices, and masked where they are used, so that the loads
+  // stay in flight while the rows are read.
+  const int ci = fl[min(tid, kk - 1)];
+  const int64_t cpi = *gptr(I.cp + ci);
+  const int xi = xrow[ci];
+  const int pe = min(tid / kk, kk - 1), pf = tid - (tid / kk) * kk;
+  const int pie = fl[pe], pjf = fl[pf];
+  const int pa = A8[(size_t)pie * ld + pjf];
+  const int pxe = xrow[pie], pxf = xrow[pjf];
+  const bool pair_ok = tid < kk * kk && tid / kk < pf;
+
+  // red[w][e]: wave w's part of (Ahat x')_i for change e, summed over passes
+  if (lane < kFlipMax) red[wid][lane] = 0;
+  for (int v0 = 0; v0 < nv; v0 += NT * V) {
+    // chunks past the row end are loaded at the last chunk and x is zeroed there
+    u32x4 x[V];
 #pragma unroll
-  for (int e = 0; e < kFlipMax; ++e) {
-    if (e < kk) {
-      int d = dot[e];
+    for (int v = 0; v < V; ++v)
+      x[v] = *(const PDBO_GLOBAL u32x4*)(xrow + (size_t)min(v0 + v * NT + tid, nv - 1) * 16);
+    for (int g = 0; g < kk; g += E) {
+      // rows past the last change repeat it; their sums are dropped
+      u32x4 a[E][V];
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
-      if (lane == 0) red[wid][e] = d;
+      for (int j = 0; j < E; ++j) {
+        const PDBO_GLOBAL int8_t* arow = A8 + (size_t)fl[min(g + j, kk - 1)] * ld;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          a[j][v] = *(const PDBO_GLOBAL u32x4*)(arow + (size_t)min(v0 + v * NT + tid, nv - 1) * 16);
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (v0 + v * NT + tid >= nv) x[v] = u32x4{0, 0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        int d = 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          d = __builtin_amdgcn_sdot4((int)a[j][v].x, (int)x[v].x, d, false);
+          d = __builtin_amdgcn_sdot4((int)a[j][v].y, (int)x[v].y, d, false);
+          d = __builtin_amdgcn_sdot4((int)a[j][v].z, (int)x[v].z, d, false);
+          d = __builtin_amdgcn_sdot4((int)a[j][v].w, (int)x[v].w, d, false);
+        }
+        d = wave_sum_i32(d);
+        if (lane == 0 && g + j < kk) red[wid][g + j] += d;
+      }
     }
   }
   __syncthreads();
   int64_t acc64 = 0;
   if (tid < kk) {
-    const int i = fl[tid];
     int d = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) d += red[w][tid];
-    const int64_t sgn = xrow[i] ? 1 : -1;
-    acc64 = sgn * (I.cp[i] + (int64_t)I.kappa * d);
+    acc64 = (xi ? 1 : -1) * (cpi + (int64_t)I.kappa * d);
   }
-  for (int pq = tid; pq < kk * kk; pq += kIncrThreads) {
+  if (pair_ok) acc64 -= (int64_t)I.kappa * ((pxe ? 1 : -1) * (pxf ? 1 : -1) * pa);
+  for (int pq = tid + NT; pq < kk * kk; pq += NT) {
     const int e = pq / kk, f = pq % kk;
     if (e < f) {
       const int ie = fl[e], jf = fl[f];
       const int de = xrow[ie] ? 1 : -1, df = xrow[jf] ? 1 : -1;
-      acc64 -= (int64_t)I.kappa * de * df * (int)I.A8[(size_t)ie * ld + jf];
+      acc64 -= (int64_t)I.kappa * de * df * (int)A8[(size_t)ie * ld + jf];
     }
   }
 #pragma unroll
@@ -1239,7 +1314,7 @@ __global__ void __launch_bounds__(kIncrThreads)
     int64_t t = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) t += part[w];
-    I.dF[b] = t;
+    *gptr(I.dF + b) = t;
   }
 }
 

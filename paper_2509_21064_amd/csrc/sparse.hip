@@ -92,21 +92,6 @@ __device__ __forceinline__ void row_gather(int i, const int32_t* __restrict__ rp
   accr = r0 + r1;
 }
 
-// Sum of an int32 over the 64 lanes of a wave through DPP moves (no LDS):
-// shifts by 1, 2, 4 and 8 within each row of 16 lanes leave the row's total in
-// its lane 15; row_bcast:15 adds row 0's total into row 1 and row 2's into
-// row 3, row_bcast:31 adds lane 31 into rows 2 and 3, so lane 63 ends with
-// the wave's total.  Lanes a move does not reach add 0.
-__device__ __forceinline__ int wave_sum_i32(int v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
-  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
-  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
-  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
-  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15, rows 1 and 3
-  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31, rows 2 and 3
-  return __builtin_amdgcn_readlane(v, 63);
-}
-
 // DBUF: x is double-buffered in LDS (iteration t gathers from buffer t mod 2
 // and writes x^{t+1} into the other), so one barrier per iteration suffices;
 // otherwise x is updated in place between two barriers.
