@@ -679,9 +679,10 @@ pdbo_status upload_dense_tables(pdbo_ctx* c) {
                            hipMemcpyHostToDevice, c->stream));
   // set the dynamic LDS limit of every kernel this context launches, outside
   // of any stream capture
-  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, nullptr, 0, nullptr, 0, 0, c->stream));
-  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_GRAD, nullptr, 0, nullptr, 0, 0, c->stream));
-  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, nullptr, 0, nullptr, 0, 0, c->stream));
+  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->par.g_kind, nullptr, 0, nullptr, 0, 0,
+                              c->stream));
+  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_GRAD, 0, nullptr, 0, nullptr, 0, 0, c->stream));
+  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, nullptr, 0, nullptr, 0, 0, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return PDBO_OK;
 }
@@ -805,11 +806,11 @@ pdbo_status autotune_dense(pdbo_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(idv, c->insts_h.data(), c->insts_h.size() * sizeof(InstDev),
                              hipMemcpyHostToDevice, c->stream));
     const int nt = (int)c->tiles_h.size();
-    HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_GRAD, td, nt, idv, c->parity, 0, c->stream));
+    HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_GRAD, 0, td, nt, idv, c->parity, 0, c->stream));
     HIPCHK(c, hipEventRecord(e0, c->stream));
     constexpr int reps = 3;
     for (int r = 0; r < reps; ++r)
-      HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_GRAD, td, nt, idv, c->parity, 0, c->stream));
+      HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_GRAD, 0, td, nt, idv, c->parity, 0, c->stream));
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));
     float ms = 0.f;
@@ -833,14 +834,14 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
   TimedLaunch tl;
   if (c->grouped) {
     t_begin(c, tl, PDBO_K_STEP);
-    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->tiles_d, (int)c->tiles_h.size(),
-                                c->insts_d, c->parity, 0, c->stream));
+    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->par.g_kind, c->tiles_d,
+                                (int)c->tiles_h.size(), c->insts_d, c->parity, 0, c->stream));
     t_end(c, tl);
     if (do_eval) {
       // full products only for the column blocks that need them; then the
       // exact differences of every restart with few rounding changes
       t_begin(c, tl, PDBO_K_EVAL);
-      HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, c->tiles_d, (int)c->tiles_h.size(),
+      HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d, (int)c->tiles_h.size(),
                                   c->insts_d, c->parity, 0, c->stream));
       t_end(c, tl);
       if (c->incr_off.back() > 0) {
@@ -855,14 +856,15 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
   } else {
     for (int k = 0; k < ninst; ++k) {
       t_begin(c, tl, PDBO_K_STEP);
-      HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->tiles_d + c->tile_off[k],
-                                  c->tile_cnt[k], c->insts_d, c->parity, 0, c->stream));
+      HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->par.g_kind,
+                                  c->tiles_d + c->tile_off[k], c->tile_cnt[k], c->insts_d,
+                                  c->parity, 0, c->stream));
       t_end(c, tl);
     }
     if (do_eval)
       for (int k = 0; k < ninst; ++k) {
         t_begin(c, tl, PDBO_K_EVAL);
-        HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, c->tiles_d + c->tile_off[k],
+        HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d + c->tile_off[k],
                                     c->tile_cnt[k], c->insts_d, c->parity, 0, c->stream));
         t_end(c, tl);
         const int w0 = c->incr_off[k], nw = c->incr_off[k + 1] - w0;
@@ -1346,7 +1348,7 @@ pdbo_status qubo_gda_grad(pdbo_ctx* c, const float* x, float* G) {
     I.Xs[0] = I.Xs[1] = Xs;
     I.G = c->g_scratch;
     HIPCHK(c, hipMemcpyAsync(c->scratch_inst_d, &I, sizeof(I), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_GRAD, c->tiles_d, (int)c->tiles_h.size(),
+    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_GRAD, 0, c->tiles_d, (int)c->tiles_h.size(),
                                 c->scratch_inst_d, 0, 0, c->stream));
   } else if (c->kind == 1) {
     ld = c->csr.ld;
@@ -1387,7 +1389,7 @@ pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F
     I.B = nb;
     HIPCHK(c, hipMemcpyAsync(c->scratch_inst_d, &I, sizeof(I), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, c->tiles_d, (int)c->tiles_h.size(),
+    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d, (int)c->tiles_h.size(),
                                 c->scratch_inst_d, 0, 0, c->stream));
     HIPCHK(c, launch_argmin(c->scratch_inst_d, 0, 1, 2, c->stream));
   } else if (c->kind == 1) {

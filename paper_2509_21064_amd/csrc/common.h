@@ -145,8 +145,10 @@ struct TileCfgInfo {
 int dense_num_cfgs();
 const TileCfgInfo& dense_cfg(int id);
 
-hipError_t launch_dense_gemm(int cfg, int prec, int epi, const TileDev* tiles, int ntiles,
-                             const InstDev* insts, int parity, int grid, hipStream_t s);
+// gkind: the kind of g (GdaP::gkind) of every instance of the launch; only the
+// step epilogue uses it
+hipError_t launch_dense_gemm(int cfg, int prec, int epi, int gkind, const TileDev* tiles,
+                             int ntiles, const InstDev* insts, int parity, int grid, hipStream_t s);
 hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, hipStream_t s);
 // work[w] = (instance, first restart) of the workgroups of the incremental evaluation
 hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, hipStream_t s);

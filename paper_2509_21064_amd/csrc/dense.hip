@@ -317,8 +317,11 @@ __device__ __forceinline__ bool eval_block_needed(const InstDev& I, int n0, int 
 }
 
 // Epilogue of one tile, shared by both main loops.  STEP/GRAD: lane holds
-// rows ibase+16*fm+r (r = 0..3) of restart column bbase+16*fn.
-template <int BM, int BN, int WM, int WN, int P, int EPI>
+// rows ibase+16*fm+r (r = 0..3) of restart column bbase+16*fn.  GK is the kind
+// of g (0 quadratic, 1 entropy) as a constant: with the kind read at run time
+// the compiler evaluates both forms of g and g' for every element, and the
+// entropy's logarithms alone cost more than the rest of the update.
+template <int BM, int BN, int WM, int WN, int P, int EPI, int GK = 0>
 __device__ __forceinline__ void gemm_epilogue(
     typename PT<P>::Acc (&acc)[BM / WM / 16][BN / WN / 16], const TileDev& td, const InstDev& I,
     int parity, int lane, int wm, int wn) {
@@ -329,7 +332,8 @@ __device__ __forceinline__ void gemm_epilogue(
   const int bbase = td.n0 + wn * WTN + (lane & 15);
   if constexpr (EPI == EPI_STEP || EPI == EPI_GRAD) {
     const float kos = I.kos;
-    const GdaP gp = I.gp;
+    GdaP gp = I.gp;
+    gp.gkind = GK;
     float* Xc = I.X[parity];
     float* Xn = I.X[parity ^ 1];
     float* Yp = I.Y;
@@ -499,7 +503,7 @@ constexpr int rows_per_pass() {
   return (64 * BM * 4 <= STAGE && BN % 64 == 0) ? 64 : (32 * BM * 4 <= STAGE && BN % 32 == 0) ? 32 : 16;
 }
 
-template <int BM, int BN, int WM, int WN, int P, int EPI, int STAGE>
+template <int BM, int BN, int WM, int WN, int P, int EPI, int STAGE, int GK = 0>
 __device__ __forceinline__ void gemm_epilogue_rows(
     typename PT<P>::Acc (&acc)[BM / WM / 16][BN / WN / 16], const TileDev& td, const InstDev& I,
     int parity, int tid, int lane, int wm, int wn, uint8_t* buf0, uint8_t* buf1) {
@@ -565,7 +569,8 @@ __device__ __forceinline__ void gemm_epilogue_rows(
     }
   };
 
-  const GdaP gp = I.gp;
+  GdaP gp = I.gp;
+  gp.gkind = GK;  // a constant: only this kind's g and g' are computed
   float* Xc = I.X[parity];
   float* Xn = I.X[parity ^ 1];
   float* Yp = I.Y;
@@ -648,7 +653,7 @@ __device__ __forceinline__ void gemm_epilogue_rows(
   }
 }
 
-template <int BM, int BN, int WM, int WN, int P, int EPI>
+template <int BM, int BN, int WM, int WN, int P, int EPI, int GK>
 __global__ void __launch_bounds__(64 * WM * WN)
     dense_gemm(const TileDev* __restrict__ tiles, int ntiles, const InstDev* __restrict__ insts,
                int parity) {
@@ -753,7 +758,7 @@ __global__ void __launch_bounds__(64 * WM * WN)
       __syncthreads();
     }
 
-    gemm_epilogue<BM, BN, WM, WN, P, EPI>(acc, td, I, parity, lane, wm, wn);
+    gemm_epilogue<BM, BN, WM, WN, P, EPI, GK>(acc, td, I, parity, lane, wm, wn);
   }
 }
 
@@ -782,7 +787,7 @@ __device__ __forceinline__ void wait_vmcnt_lds() {
 
 typedef __attribute__((address_space(3))) void* lds_ptr;
 
-template <int BM, int BN, int WM, int WN, int P, int EPI>
+template <int BM, int BN, int WM, int WN, int P, int EPI, int GK>
 __global__ void __launch_bounds__(64 * WM * WN)
     dense_gemm_dma(const TileDev* __restrict__ tiles, int ntiles, const InstDev* __restrict__ insts,
                    int parity) {
@@ -970,8 +975,8 @@ __global__ void __launch_bounds__(64 * WM * WN)
       // landed and every wave is done reading the stages before G goes in
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      gemm_epilogue_rows<BM, BN, WM, WN, P, EPI, STAGE>(acc, td, I, parity, tid, lane, wm, wn, st0,
-                                                        st1);
+      gemm_epilogue_rows<BM, BN, WM, WN, P, EPI, STAGE, GK>(acc, td, I, parity, tid, lane, wm, wn,
+                                                            st0, st1);
     }
   }
   __builtin_amdgcn_s_waitcnt(0);  // no DMA into LDS may outlive the workgroup
@@ -1003,17 +1008,17 @@ static const TileCfgInfo kCfgs[] = {
 int dense_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 const TileCfgInfo& dense_cfg(int id) { return kCfgs[id]; }
 
-template <int BM, int BN, int WM, int WN, int P, int EPI, int DMA>
+template <int BM, int BN, int WM, int WN, int P, int EPI, int DMA, int GK>
 static hipError_t launch_one(const TileDev* tiles, int ntiles, const InstDev* insts, int parity,
                              int grid, hipStream_t s) {
   if (grid <= 0 || grid > ntiles) grid = ntiles;
   if constexpr (DMA) {
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((dense_gemm_dma<BM, BN, WM, WN, P, EPI>), dim3(grid), dim3(64 * WM * WN), 0,
-                       s, tiles, ntiles, insts, parity);
+    hipLaunchKernelGGL((dense_gemm_dma<BM, BN, WM, WN, P, EPI, GK>), dim3(grid), dim3(64 * WM * WN),
+                       0, s, tiles, ntiles, insts, parity);
   } else {
     constexpr int lds = gemm_lds_bytes<BM, BN>();
-    auto kern = dense_gemm<BM, BN, WM, WN, P, EPI>;
+    auto kern = dense_gemm<BM, BN, WM, WN, P, EPI, GK>;
     static bool attr_done = false;
     if (!attr_done) {
       hipError_t e =
@@ -1027,31 +1032,39 @@ static hipError_t launch_one(const TileDev* tiles, int ntiles, const InstDev* in
   return hipGetLastError();
 }
 
+// The step kernels come in one variant per kind of g (GK); the others do not
+// use g and take GK = 0.
 template <int BM, int BN, int WM, int WN, int DMA>
-static hipError_t launch_cfg(int prec, int epi, const TileDev* tiles, int ntiles,
+static hipError_t launch_cfg(int prec, int epi, int gkind, const TileDev* tiles, int ntiles,
                              const InstDev* insts, int parity, int grid, hipStream_t s) {
-#define PDBO_L(P, E) launch_one<BM, BN, WM, WN, P, E, DMA>(tiles, ntiles, insts, parity, grid, s)
-  if (epi == EPI_EVAL) return PDBO_L(P_I8, EPI_EVAL);
-  switch (prec * 2 + epi) {
-    case P_F32 * 2 + EPI_STEP: return PDBO_L(P_F32, EPI_STEP);
-    case P_F32 * 2 + EPI_GRAD: return PDBO_L(P_F32, EPI_GRAD);
-    case P_BF16 * 2 + EPI_STEP: return PDBO_L(P_BF16, EPI_STEP);
-    case P_BF16 * 2 + EPI_GRAD: return PDBO_L(P_BF16, EPI_GRAD);
-    case P_FP8 * 2 + EPI_STEP: return PDBO_L(P_FP8, EPI_STEP);
-    case P_FP8 * 2 + EPI_GRAD: return PDBO_L(P_FP8, EPI_GRAD);
-    case P_I8 * 2 + EPI_STEP: return PDBO_L(P_I8, EPI_STEP);
-    case P_I8 * 2 + EPI_GRAD: return PDBO_L(P_I8, EPI_GRAD);
+#define PDBO_L(P, E, G) \
+  launch_one<BM, BN, WM, WN, P, E, DMA, G>(tiles, ntiles, insts, parity, grid, s)
+  if (epi == EPI_EVAL) return PDBO_L(P_I8, EPI_EVAL, 0);
+  const int g = (epi == EPI_STEP && gkind != 0) ? 1 : 0;
+  switch ((prec * 2 + epi) * 2 + g) {
+    case (P_F32 * 2 + EPI_STEP) * 2: return PDBO_L(P_F32, EPI_STEP, 0);
+    case (P_F32 * 2 + EPI_STEP) * 2 + 1: return PDBO_L(P_F32, EPI_STEP, 1);
+    case (P_F32 * 2 + EPI_GRAD) * 2: return PDBO_L(P_F32, EPI_GRAD, 0);
+    case (P_BF16 * 2 + EPI_STEP) * 2: return PDBO_L(P_BF16, EPI_STEP, 0);
+    case (P_BF16 * 2 + EPI_STEP) * 2 + 1: return PDBO_L(P_BF16, EPI_STEP, 1);
+    case (P_BF16 * 2 + EPI_GRAD) * 2: return PDBO_L(P_BF16, EPI_GRAD, 0);
+    case (P_FP8 * 2 + EPI_STEP) * 2: return PDBO_L(P_FP8, EPI_STEP, 0);
+    case (P_FP8 * 2 + EPI_STEP) * 2 + 1: return PDBO_L(P_FP8, EPI_STEP, 1);
+    case (P_FP8 * 2 + EPI_GRAD) * 2: return PDBO_L(P_FP8, EPI_GRAD, 0);
+    case (P_I8 * 2 + EPI_STEP) * 2: return PDBO_L(P_I8, EPI_STEP, 0);
+    case (P_I8 * 2 + EPI_STEP) * 2 + 1: return PDBO_L(P_I8, EPI_STEP, 1);
+    case (P_I8 * 2 + EPI_GRAD) * 2: return PDBO_L(P_I8, EPI_GRAD, 0);
     default: return hipErrorInvalidValue;
   }
 #undef PDBO_L
 }
 
-hipError_t launch_dense_gemm(int cfg, int prec, int epi, const TileDev* tiles, int ntiles,
-                             const InstDev* insts, int parity, int grid, hipStream_t s) {
+hipError_t launch_dense_gemm(int cfg, int prec, int epi, int gkind, const TileDev* tiles,
+                             int ntiles, const InstDev* insts, int parity, int grid, hipStream_t s) {
   switch (cfg) {
 #define X(id, bm, bn, wm, wn, dma) \
   case id:                         \
-    return launch_cfg<bm, bn, wm, wn, dma>(prec, epi, tiles, ntiles, insts, parity, grid, s);
+    return launch_cfg<bm, bn, wm, wn, dma>(prec, epi, gkind, tiles, ntiles, insts, parity, grid, s);
     PDBO_TILE_CFGS(X)
 #undef X
     default:

@@ -103,6 +103,42 @@ def test_lockstep_iteration(name, prec):
     assert np.max(np.abs(Gg - G64)) <= gabs
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "i8"])
+@pytest.mark.parametrize("name", ["gnp_n200", "dense_u100_n700"])
+def test_lockstep_iteration_entropy_g(name, prec):
+    """The dense step with the entropy g (a separate step kernel variant):
+    one iteration against the oracle, including x at 0, 1/2 and 1, where g'
+    is taken at the clipped point."""
+    P = require_gpu()
+    q, B, s = CASES[name]
+    s = _scale(q, s)
+    say(f"[dense lockstep entropy] case={name} prec={prec}")
+    g = np.random.default_rng(12)
+    X = g.random((B, q.n)).astype(np.float32)
+    X[:, ::7] = 0.5
+    X[:, 3::11] = np.float32(0.5 + W.DELTA)
+    X[:, 5::13] = 0.0
+    X[:, 6::17] = 1.0
+    Y = g.uniform(-2.0, 6.0, (B, q.n)).astype(np.float32)
+    p = W.gda_params("qubo", B=B, T=1, scale=s, precision=prec, g="entropy")
+    ctx = P.qubo_gda_init(q, p, X.astype(np.float64))
+    ctx.set_state(X, Y, 0)
+    ctx.step(1)
+    Xg, Yg, t = ctx.get_state()
+    assert t == 1
+    G64 = oq.grad_f(*oq.canonicalize(q), X.astype(np.float64), s)
+    # float32 logarithms of g' near the clip: up to |y| * 2e-6 in dL
+    gabs = GTOL[prec] * float(np.max(np.abs(G64))) + 2e-6 * float(np.max(np.abs(Y))) + 1e-6
+    dx, dy, namb, _, _ = lockstep_compare(X.astype(np.float64), Y.astype(np.float64), G64, Xg, Yg, p, gabs)
+    say(f"   max|dX|={dx:.3e} max|dY|={dy:.3e} excluded={namb}/{X.size}")
+    assert dx <= p["alpha"] * gabs + 2e-6
+    assert dy <= 2e-6 * (1 + np.max(np.abs(Y)))
+    assert namb <= 0.2 * X.size
+    assert np.all((Xg >= 0) & (Xg <= 1))
+    F = ctx.objectives()
+    assert np.array_equal(F, oq.objective(q, Xg > 0.5))
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_eval_exact_random_vectors(name):
     P = require_gpu()
