@@ -102,7 +102,7 @@ __device__ __forceinline__ float sat3_adjoint(const SatDev& D, const float* __re
 // the variable's owner, and x^t is read back from LDS; only x^{t+1} is held in
 // registers until the barrier.  Used when many variables fall to each thread
 // and both arrays fit, so that the per-variable state does not spill.
-template <bool K3, int NT, int RMAX, bool YLDS>
+template <bool K3, int NT, int RMAX, bool YLDS, int GK>
 __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int nsteps) {
   constexpr int NW = NT / 64;
   extern __shared__ __attribute__((aligned(16))) float xs[];
@@ -133,7 +133,8 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
   int64_t bF = D.rbestF[b], bT = D.rbestT[b];
   uint64_t bTs = D.rbestTs[b];
   int64_t Flast = D.Flast[b];
-  const GdaP gp = D.gp;
+  GdaP gp = D.gp;
+  gp.gkind = GK;  // a constant: only this kind's g and g' are computed
   const float ios = D.ios;
   __syncthreads();
   for (int s = 0; s <= nsteps; ++s) {
@@ -210,9 +211,9 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
   }
 }
 
-template <bool K3, int NT, int RMAX, bool YLDS = false>
+template <bool K3, int GK, int NT, int RMAX, bool YLDS = false>
 static hipError_t launch_sat_k(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
-  auto kern = sat_persistent<K3, NT, RMAX, YLDS>;
+  auto kern = sat_persistent<K3, NT, RMAX, YLDS, GK>;
   const size_t lds = align16s((size_t)d.n * 4) * (YLDS ? 2 : 1);
   hipError_t e =
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -225,23 +226,27 @@ static hipError_t launch_sat_k(const SatDev& d, int64_t t0, int nsteps, hipStrea
 // variables per thread in registers, up to 20 with y in LDS (n <= 20000, both
 // arrays in the 160 KB); beyond that 512 threads with a larger register budget,
 // whose per-variable state partly spills to scratch memory.
-template <bool K3>
+template <bool K3, int GK>
 static hipError_t launch_sat_r(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
   const int r = (d.n + 1023) / 1024;
-  if (r <= 4) return launch_sat_k<K3, 1024, 4>(d, t0, nsteps, s);
-  if (r <= 8) return launch_sat_k<K3, 1024, 8>(d, t0, nsteps, s);
+  if (r <= 4) return launch_sat_k<K3, GK, 1024, 4>(d, t0, nsteps, s);
+  if (r <= 8) return launch_sat_k<K3, GK, 1024, 8>(d, t0, nsteps, s);
   if (r <= 20 && 2 * align16s((size_t)d.n * 4) <= kSatYldsBudget)
-    return launch_sat_k<K3, 1024, 20, true>(d, t0, nsteps, s);
+    return launch_sat_k<K3, GK, 1024, 20, true>(d, t0, nsteps, s);
   const int r2 = (d.n + 511) / 512;
-  if (r2 <= 40) return launch_sat_k<K3, 512, 40>(d, t0, nsteps, s);
-  if (r2 <= 64) return launch_sat_k<K3, 512, 64>(d, t0, nsteps, s);
+  if (r2 <= 40) return launch_sat_k<K3, GK, 512, 40>(d, t0, nsteps, s);
+  if (r2 <= 64) return launch_sat_k<K3, GK, 512, 64>(d, t0, nsteps, s);
   return hipErrorInvalidValue;
 }
 
+// One kernel variant per kind of g (GK): read at run time, the kind would make
+// the update evaluate both forms of g and g' for every coordinate.
 hipError_t launch_sat_persistent(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
   if (nsteps <= 0) return hipSuccess;
-  if (d.inc3) return launch_sat_r<true>(d, t0, nsteps, s);
-  return launch_sat_r<false>(d, t0, nsteps, s);
+  if (d.gp.gkind == 0)
+    return d.inc3 ? launch_sat_r<true, 0>(d, t0, nsteps, s)
+                  : launch_sat_r<false, 0>(d, t0, nsteps, s);
+  return d.inc3 ? launch_sat_r<true, 1>(d, t0, nsteps, s) : launch_sat_r<false, 1>(d, t0, nsteps, s);
 }
 
 // ---- adjoint at given points: gradient (mode 0) or Lagrangian backward (mode 1)

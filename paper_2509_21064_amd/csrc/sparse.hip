@@ -98,7 +98,7 @@ __device__ __forceinline__ void row_gather(int i, const int32_t* __restrict__ rp
 // SMALL: the host has bounded every wave's partial sums of x_r^T Ahat x_r and
 // c'^T x_r below 2^31, so the wave reductions run in int32 (half the shuffles
 // of int64); the sum over waves is always taken in int64.
-template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL>
+template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK>
 __global__ void __launch_bounds__(NT)
     csr_persistent(CsrDev D, int64_t t0, int nsteps) {
   constexpr int NW = NT / 64;
@@ -151,7 +151,8 @@ __global__ void __launch_bounds__(NT)
   uint64_t bTs = D.rbestTs[b];
   int64_t Flast = D.Flast[b];
   const float kos = D.kos;
-  const GdaP gp = D.gp;
+  GdaP gp = D.gp;
+  gp.gkind = GK;  // a constant: only this kind's g and g' are computed
   __syncthreads();
 
   for (int s = 0; s <= nsteps; ++s) {
@@ -259,9 +260,9 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL>
+template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK>
 static hipError_t launch_csr_k(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
-  auto kern = csr_persistent<PACKED, NT, RMAX, DBUF, SMALL>;
+  auto kern = csr_persistent<PACKED, NT, RMAX, DBUF, SMALL, GK>;
   const size_t lds = csr_lds_need(d.n, d.nnz, PACKED) + (DBUF ? align16((size_t)d.n * 4) : 0);
   hipError_t e =
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -270,38 +271,41 @@ static hipError_t launch_csr_k(const CsrDev& d, int64_t t0, int nsteps, hipStrea
   return hipGetLastError();
 }
 
-template <bool PACKED, int NT, int RMAX>
+template <bool PACKED, int NT, int RMAX, int GK>
 static hipError_t launch_csr_v(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
   const bool dbuf = csr_lds_need(d.n, d.nnz, PACKED) + align16((size_t)d.n * 4) <= kLdsBudget;
-  if (dbuf && d.small32) return launch_csr_k<PACKED, NT, RMAX, true, true>(d, t0, nsteps, s);
-  if (dbuf) return launch_csr_k<PACKED, NT, RMAX, true, false>(d, t0, nsteps, s);
-  if (d.small32) return launch_csr_k<PACKED, NT, RMAX, false, true>(d, t0, nsteps, s);
-  return launch_csr_k<PACKED, NT, RMAX, false, false>(d, t0, nsteps, s);
+  if (dbuf && d.small32) return launch_csr_k<PACKED, NT, RMAX, true, true, GK>(d, t0, nsteps, s);
+  if (dbuf) return launch_csr_k<PACKED, NT, RMAX, true, false, GK>(d, t0, nsteps, s);
+  if (d.small32) return launch_csr_k<PACKED, NT, RMAX, false, true, GK>(d, t0, nsteps, s);
+  return launch_csr_k<PACKED, NT, RMAX, false, false, GK>(d, t0, nsteps, s);
 }
 
 // 1024 threads per restart (sixteen waves keep enough LDS gathers in flight)
 // up to 8 rows per thread; beyond that (n > 8192) 512 threads with 32 or 64
 // rows per thread, whose per-row state does not fit the register budget and
 // partly lives in scratch memory.
-template <bool PACKED>
+template <bool PACKED, int GK>
 static hipError_t launch_csr_r(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
   const int r = (d.n + 1023) / 1024;
-  if (r <= 1) return launch_csr_v<PACKED, 1024, 1>(d, t0, nsteps, s);
-  if (r <= 2) return launch_csr_v<PACKED, 1024, 2>(d, t0, nsteps, s);
-  if (r <= 4) return launch_csr_v<PACKED, 1024, 4>(d, t0, nsteps, s);
-  if (r <= 8) return launch_csr_v<PACKED, 1024, 8>(d, t0, nsteps, s);
+  if (r <= 1) return launch_csr_v<PACKED, 1024, 1, GK>(d, t0, nsteps, s);
+  if (r <= 2) return launch_csr_v<PACKED, 1024, 2, GK>(d, t0, nsteps, s);
+  if (r <= 4) return launch_csr_v<PACKED, 1024, 4, GK>(d, t0, nsteps, s);
+  if (r <= 8) return launch_csr_v<PACKED, 1024, 8, GK>(d, t0, nsteps, s);
   const int r2 = (d.n + 511) / 512;
-  if (r2 <= 32) return launch_csr_k<PACKED, 512, 32, false, false>(d, t0, nsteps, s);
-  if (r2 <= 64) return launch_csr_k<PACKED, 512, 64, false, false>(d, t0, nsteps, s);
+  if (r2 <= 32) return launch_csr_k<PACKED, 512, 32, false, false, GK>(d, t0, nsteps, s);
+  if (r2 <= 64) return launch_csr_k<PACKED, 512, 64, false, false, GK>(d, t0, nsteps, s);
   return hipErrorInvalidValue;
 }
 
+// One kernel variant per kind of g (GK): read at run time, the kind would make
+// the update evaluate both forms of g and g' for every coordinate.
 hipError_t launch_csr_persistent(const CsrDev& d, bool packed, int64_t t0, int nsteps,
                                  hipStream_t s) {
   if (nsteps <= 0) return hipSuccess;
-  if (packed && csr_lds_need(d.n, d.nnz, true) <= kLdsBudget)
-    return launch_csr_r<true>(d, t0, nsteps, s);
-  return launch_csr_r<false>(d, t0, nsteps, s);
+  const bool pk = packed && csr_lds_need(d.n, d.nnz, true) <= kLdsBudget;
+  if (d.gp.gkind == 0)
+    return pk ? launch_csr_r<true, 0>(d, t0, nsteps, s) : launch_csr_r<false, 0>(d, t0, nsteps, s);
+  return pk ? launch_csr_r<true, 1>(d, t0, nsteps, s) : launch_csr_r<false, 1>(d, t0, nsteps, s);
 }
 
 // ---- gradient and exact evaluation at given points (tests, qubo_gda_grad/eval)
