@@ -56,6 +56,34 @@ def test_gradient_lockstep_eval(name):
     assert np.array_equal(ctx.eval(xr), om.objective(f, xr))
 
 
+@pytest.mark.parametrize("name", ["3sat_n500", "3sat_n6000", "3sat_n12345", "4sat_n9001"])
+def test_lockstep_quadratic_g(name):
+    """The persistent kernel's variant for the quadratic g (the MaxSAT workloads
+    use the entropy one): one iteration against the oracle."""
+    P = require_gpu()
+    mk, B = CASES[name]
+    f = mk()
+    s = W.maxsat_scale(f)
+    say(f"[sat lockstep quad] case={name} n={f.n} m={f.m} k={f.k} B={B}")
+    g = np.random.default_rng(9)
+    X = g.random((B, f.n)).astype(np.float32)
+    X[:, ::11] = 0.5
+    Y = g.uniform(-1.0, 2.0, (B, f.n)).astype(np.float32)
+    p = W.gda_params("maxsat", B=B, T=1, scale=s, g="quad")
+    ctx = P.maxsat_gda_init(f, p, X.astype(np.float64))
+    ctx.set_state(X, Y, 0)
+    ctx.step(1)
+    Xg, Yg, _ = ctx.get_state()
+    G64 = om.grad_f(f, X.astype(np.float64), s)
+    gabs = 1e-5 * float(np.max(np.abs(G64))) + 1e-6
+    dx, dy, namb, _, _ = lockstep_compare(X.astype(np.float64), Y.astype(np.float64), G64, Xg, Yg, p, gabs)
+    say(f"   max|dX|={dx:.3e} max|dY|={dy:.3e} excluded={namb}/{X.size}")
+    assert dx <= p["alpha"] * gabs + 2e-6
+    assert dy <= 1e-5
+    assert namb <= 0.2 * X.size
+    assert np.array_equal(ctx.objectives(), om.objective(f, Xg > 0.5))
+
+
 def test_autograd_function_against_oracle():
     P = require_gpu()
     import torch

@@ -85,6 +85,39 @@ def test_gradient_and_lockstep(name):
     assert np.array_equal(ctx.objectives(), oq.objective(q, Xg > 0.5))
 
 
+@pytest.mark.parametrize("name", ["maxcut_n2000", "maxcut_n301_ragged", "maxcut_n8000_inplace",
+                                  "maxcut_n12000_rows32"])
+def test_lockstep_entropy_g(name):
+    """The persistent kernel's variant for the entropy g (the Max-Cut workloads
+    use the quadratic one): one iteration against the oracle, with x at 0, 1/2
+    and 1."""
+    P = require_gpu()
+    mk, B, s = CASES[name]
+    q = mk()
+    s = W.qubo_scale(q) if s is None else s
+    say(f"[csr lockstep entropy] case={name} n={q.n} B={B}")
+    g = np.random.default_rng(8)
+    X = g.random((B, q.n)).astype(np.float32)
+    X[:, ::9] = 0.5
+    X[:, 4::13] = 0.0
+    X[:, 7::17] = 1.0
+    Y = g.uniform(-2.0, 6.0, (B, q.n)).astype(np.float32)
+    p = W.gda_params("maxcut", B=B, T=1, scale=s, g="entropy")
+    ctx = P.qubo_gda_init(q, p, X.astype(np.float64))
+    ctx.set_state(X, Y, 0)
+    ctx.step(1)
+    Xg, Yg, t = ctx.get_state()
+    assert t == 1
+    G64 = oq.grad_f(*oq.canonicalize(q), X.astype(np.float64), s)
+    # float32 logarithms of g' near the clip: up to |y| * 2e-6 in dL
+    gabs = 1e-5 * float(np.max(np.abs(G64))) + 2e-6 * float(np.max(np.abs(Y))) + 1e-6
+    dx, dy, namb, _, _ = lockstep_compare(X.astype(np.float64), Y.astype(np.float64), G64, Xg, Yg, p, gabs)
+    say(f"   max|dX|={dx:.3e} max|dY|={dy:.3e} excluded={namb}/{X.size}")
+    assert dx <= p["alpha"] * gabs + 2e-6 and dy <= 2e-6 * 7
+    assert namb <= 0.2 * X.size
+    assert np.array_equal(ctx.objectives(), oq.objective(q, Xg > 0.5))
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_eval_exact(name):
     P = require_gpu()
