@@ -109,10 +109,12 @@ def run_form(P, q, s, x0, form, args):
                step_kernel_ms=k_step[0] / max(k_step[1], 1),
                eval_kernel_ms=k_eval[0] / max(k_eval[1], 1),
                eval_incr_kernel_ms=k_inc[0] / max(k_inc[1], 1),
-               argmin_kernel_ms=k_arg[0] / max(k_arg[1], 1), launches=k_step[1])
+               argmin_kernel_ms=k_arg[0] / max(k_arg[1], 1), argmin_launches=k_arg[1],
+               breakdown_steps=args.breakdown_steps, launches=k_step[1])
     log(f"{form}: {out['value']:.4g} restart-it/s, {out['ms_per_step']:.3f} ms/step "
         f"(step {out['step_kernel_ms']:.3f} ms, eval {out['eval_kernel_ms']:.3f} ms, "
-        f"incremental eval {out['eval_incr_kernel_ms']:.3f} ms, argmin {out['argmin_kernel_ms']:.3f} ms)")
+        f"incremental eval {out['eval_incr_kernel_ms']:.3f} ms, argmin {out['argmin_kernel_ms']:.3f} ms "
+        f"x {out['argmin_launches']} launches in {args.breakdown_steps} steps)")
     if not args.no_quality:
         ctx = P.qubo_gda_init(q, p, x0)
         torch.cuda.synchronize()

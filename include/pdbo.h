@@ -243,7 +243,11 @@ PDBO_API pdbo_status qubo_gda_trace(pdbo_ctx* ctx, int32_t cap, int64_t* t, int6
  *   PDBO_K_EVAL        dense int8 GEMM of the exact objectives (Eq. 1); a column
  *                      block of restarts is skipped when none of them needs a
  *                      full product
- *   PDBO_K_ARGMIN      best of B and incumbent update
+ *   PDBO_K_ARGMIN      best of B and incumbent update, when it has a launch of its
+ *                      own: with incremental evaluation (eval_every = 1) an
+ *                      iteration's best of B runs in extra workgroups of the
+ *                      next step launch, and only the last iteration of each
+ *                      qubo_gda_step call (or graph of iterations) launches it
  *   PDBO_K_PERSISTENT  the CSR and MaxSAT persistent kernels (one per step call)
  *   PDBO_K_INCR        exact objective differences from the recorded rounding
  *                      changes: when at most 32 coordinates of a restart's
@@ -252,7 +256,8 @@ PDBO_API pdbo_status qubo_gda_trace(pdbo_ctx* ctx, int32_t cap, int64_t* t, int6
  *                                     - kappa sum_{i<j} d_i d_j Ahat_ij
  *                      (d = x' - x, all in integers) replaces the full product;
  *                      the first evaluation after init or set_state, and any
- *                      restart with more changes, take the full product. */
+ *                      restart with more changes, take the full product.  This
+ *                      kernel also finalises every restart's objective. */
 enum { PDBO_K_STEP = 0, PDBO_K_EVAL = 1, PDBO_K_ARGMIN = 2, PDBO_K_PERSISTENT = 3,
        PDBO_K_INCR = 4, PDBO_K_COUNT = 5 };
 

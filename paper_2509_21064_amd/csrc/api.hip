@@ -87,6 +87,8 @@ struct pdbo_ctx {
   hipGraph_t graph = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream used only to record the graph
   int graph_parity0 = -1;
+  // the best of B of the last iteration has not run yet (incremental evaluation)
+  bool argmin_pending = false;
   // CSR / MaxSAT persistent
   CsrDev csr{};
   bool compact = false;
@@ -581,13 +583,13 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
   STCHK(dalloc(c, &I.Fall, (size_t)B));
   I.nflip = nullptr;
   I.fbits = nullptr;
-  I.dF = nullptr;
+  I.cand = nullptr;
   if (p->eval_every == 1) {
     // the first evaluation is a full product (nflip above kFlipMax); the
     // bitmap starts clear (dalloc zeroes)
     STCHK(dalloc(c, &I.nflip, (size_t)B));
     STCHK(dalloc(c, &I.fbits, (size_t)B * (ld / 32)));
-    STCHK(dalloc(c, &I.dF, (size_t)B));
+    STCHK(dalloc(c, &I.cand, (size_t)B * ld));
     HIPCHK(c, launch_fill_i32(I.nflip, kFlipMax + 1, B, c->stream));
   }
   STCHK(dalloc(c, &I.inc, 1));
@@ -828,14 +830,19 @@ pdbo_status autotune_dense(pdbo_ctx* c) {
   return PDBO_OK;
 }
 
+// With incremental evaluation an iteration's best of B is left pending: it
+// runs in extra workgroups of the next step launch (on CUs the tiles leave
+// free), or in a launch of its own when the steps stop (flush_argmin).
 pdbo_status dense_one_step(pdbo_ctx* c) {
   const bool do_eval = ((c->t_host + 1) % c->eval_every) == 0;
   const int ninst = (int)c->insts_h.size();
+  const bool incr = c->incr_off.back() > 0;  // every instance, eval_every = 1
   TimedLaunch tl;
   if (c->grouped) {
     t_begin(c, tl, PDBO_K_STEP);
     HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->par.g_kind, c->tiles_d,
-                                (int)c->tiles_h.size(), c->insts_d, c->parity, 0, c->stream));
+                                (int)c->tiles_h.size(), c->insts_d, c->parity, 0, c->stream, 0,
+                                c->argmin_pending ? ninst : 0));
     t_end(c, tl);
     if (do_eval) {
       // full products only for the column blocks that need them; then the
@@ -850,15 +857,17 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
         t_end(c, tl);
       }
     }
-    t_begin(c, tl, PDBO_K_ARGMIN);
-    HIPCHK(c, launch_argmin(c->insts_d, 0, ninst, do_eval ? 1 : 0, c->stream));
-    t_end(c, tl);
+    if (!incr) {
+      t_begin(c, tl, PDBO_K_ARGMIN);
+      HIPCHK(c, launch_argmin(c->insts_d, 0, ninst, do_eval ? 1 : 0, c->stream));
+      t_end(c, tl);
+    }
   } else {
     for (int k = 0; k < ninst; ++k) {
       t_begin(c, tl, PDBO_K_STEP);
       HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->par.g_kind,
                                   c->tiles_d + c->tile_off[k], c->tile_cnt[k], c->insts_d,
-                                  c->parity, 0, c->stream));
+                                  c->parity, 0, c->stream, k, c->argmin_pending ? 1 : 0));
       t_end(c, tl);
     }
     if (do_eval)
@@ -874,14 +883,26 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
           t_end(c, tl);
         }
       }
-    for (int k = 0; k < ninst; ++k) {
-      t_begin(c, tl, PDBO_K_ARGMIN);
-      HIPCHK(c, launch_argmin(c->insts_d, k, 1, do_eval ? 1 : 0, c->stream));
-      t_end(c, tl);
-    }
+    if (!incr)
+      for (int k = 0; k < ninst; ++k) {
+        t_begin(c, tl, PDBO_K_ARGMIN);
+        HIPCHK(c, launch_argmin(c->insts_d, k, 1, do_eval ? 1 : 0, c->stream));
+        t_end(c, tl);
+      }
   }
+  c->argmin_pending = incr;
   c->parity ^= 1;
   c->t_host += 1;
+  return PDBO_OK;
+}
+
+pdbo_status flush_argmin(pdbo_ctx* c) {
+  if (!c->argmin_pending) return PDBO_OK;
+  TimedLaunch tl;
+  t_begin(c, tl, PDBO_K_ARGMIN);
+  HIPCHK(c, launch_argmin(c->insts_d, 0, (int)c->insts_h.size(), 1, c->stream));
+  t_end(c, tl);
+  c->argmin_pending = false;
   return PDBO_OK;
 }
 
@@ -897,6 +918,7 @@ pdbo_status dense_steps(pdbo_ctx* c, int nsteps) {
         // executes there) and launch the graph on the caller's stream.
         if (!c->cap_stream)
           HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        STCHK(flush_argmin(c));  // a graph starts and ends with nothing pending
         HIPCHK(c, hipStreamSynchronize(c->stream));
         const int64_t t_save = c->t_host;
         const int par_save = c->parity;
@@ -909,11 +931,13 @@ pdbo_status dense_steps(pdbo_ctx* c, int nsteps) {
         }
         pdbo_status st = PDBO_OK;
         for (int s = 0; s < K && st == PDBO_OK; ++s) st = dense_one_step(c);
+        if (st == PDBO_OK) st = flush_argmin(c);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(c->stream, &g);
         c->stream = user;
         c->t_host = t_save;
         c->parity = par_save;
+        c->argmin_pending = false;
         if (st != PDBO_OK) {
           if (g) (void)hipGraphDestroy(g);
           return st;
@@ -928,6 +952,7 @@ pdbo_status dense_steps(pdbo_ctx* c, int nsteps) {
         --left;
         continue;
       }
+      STCHK(flush_argmin(c));
       HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
       c->t_host += K;
       left -= K;
@@ -936,7 +961,7 @@ pdbo_status dense_steps(pdbo_ctx* c, int nsteps) {
       --left;
     }
   }
-  return PDBO_OK;
+  return flush_argmin(c);
 }
 
 double clock_rate_hz() {

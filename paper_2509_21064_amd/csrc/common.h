@@ -69,9 +69,12 @@ struct InstDev {
   // The step epilogue records the coordinates whose rounding changed; an
   // evaluation then updates F_b exactly from them unless more than kFlipMax
   // changed (or nflip[b] was set above kFlipMax to ask for a full product).
+  // The incremental kernel finalises every F_b (Fall) and keeps the rounded
+  // row of each restart that beats the incumbent (cand), so that the best of
+  // B can run while the next step already rewrites x_r.
   int32_t* nflip;         // [B] rounding changes since the last evaluation
   uint32_t* fbits;        // [B][ld / 32] bitmap of the changed coordinates
-  int64_t* dF;            // [B] F(x_r new) - F(x_r old), from the recorded changes
+  uint8_t* cand;          // [B][ld] rounded rows that beat the incumbent when evaluated
   uint64_t* ts0;          // clock at the first step
   int n, ld, B, mblocks;
   int kappa, trace_cap;
@@ -147,8 +150,12 @@ const TileCfgInfo& dense_cfg(int id);
 
 // gkind: the kind of g (GdaP::gkind) of every instance of the launch; only the
 // step epilogue uses it
+// A step launch may also run the best of B of the previous iteration for
+// instances am0 .. am0 + amn - 1 (incremental evaluation only), in amn extra
+// workgroups after the tiles.
 hipError_t launch_dense_gemm(int cfg, int prec, int epi, int gkind, const TileDev* tiles,
-                             int ntiles, const InstDev* insts, int parity, int grid, hipStream_t s);
+                             int ntiles, const InstDev* insts, int parity, int grid, hipStream_t s,
+                             int am0 = 0, int amn = 0);
 hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, hipStream_t s);
 // work[w] = (instance, first restart) of the workgroups of the incremental evaluation
 hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, hipStream_t s);

@@ -147,12 +147,17 @@ constexpr int gemm_lds_bytes() {
   return 2 * (BM + BN) * kRow;
 }
 
-// Best of B for one instance, by one workgroup of NT threads:
-// F_b = (kappa * S_b) / 2 + C_b from the evaluation's integer partials (which
-// are reset to zero for the next evaluation), first argmin over b, strict-
-// improvement update of the incumbent, copy of the winning rounded vector.
+// Best of B for one instance, by one workgroup of NT threads: the objectives
+// F_b, first argmin over b, strict-improvement update of the incumbent, copy
+// of the winning rounded vector.
 // mode 0: no evaluation this iteration (only the iteration counter advances);
 // mode 1: evaluation and incumbent update; mode 2: objectives only.
+// Without incremental evaluation (nflip absent), F_b = (kappa * S_b) / 2 + C_b
+// from the evaluation's integer partials, which are reset to zero for the next
+// evaluation, and the winner is copied from x_r.  With it, the incremental
+// kernel has already finalised F_b in Fall, reset the partials and kept the
+// rows that beat the incumbent in cand: only Fall is read and the winner is
+// copied from cand, so this can run while the next step rewrites x_r.
 //
 // The kernel is a short chain of dependent steps, so its length is set by how
 // many memory round trips it waits for: every load it needs (including the
@@ -183,43 +188,35 @@ __device__ void best_of_B(const InstDev& I, int mode, int tid, int64_t* sF, int*
     incF = *gptr(&I.inc->F);
     tlen = *gptr(I.trace_len);
   }
+  const bool fin = I.nflip != nullptr;  // objectives finalised by the incremental kernel
   int64_t bestF = LLONG_MAX;
   int bestb = INT_MAX;
-  // A restart with at most kFlipMax recorded rounding changes takes its
-  // previous objective plus the exact difference; the others (and every
-  // restart when nflip is absent) take the full product's partials.  Each
-  // thread visits its restarts in increasing order, so the strict comparison
-  // keeps the first minimum.
+  // Each thread visits its restarts in increasing order, so the strict
+  // comparison keeps the first minimum.
   int64_t F1[U];  // the objectives of the first batch, stored after the barriers
   for (int b0 = 0; b0 < I.B; b0 += U * NT) {
-    int64_t S[U], C[U], Fp[U], dF[U];
-    int k[U];
+    int64_t S[U], C[U], Fp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int b = b0 + u * NT + tid;
       const bool ok = b < I.B;
-      S[u] = ok ? *gptr(I.Sacc + b) : 0;
-      C[u] = ok ? *gptr(I.Cacc + b) : 0;
-      k[u] = (ok && I.nflip) ? *gptr(I.nflip + b) : kFlipMax + 1;
-      Fp[u] = ok ? *gptr(I.Fall + b) : 0;
-      dF[u] = (ok && I.nflip) ? *gptr(I.dF + b) : 0;
+      S[u] = (ok && !fin) ? *gptr(I.Sacc + b) : 0;
+      C[u] = (ok && !fin) ? *gptr(I.Cacc + b) : 0;
+      Fp[u] = (ok && fin) ? *gptr(I.Fall + b) : 0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int b = b0 + u * NT + tid;
-      const int64_t F = k[u] == 0 ? Fp[u]
-                        : k[u] <= kFlipMax ? Fp[u] + dF[u]
-                                           : (I.kappa == 2 ? S[u] : S[u] / 2) + C[u];
+      const int64_t F = fin ? Fp[u] : (I.kappa == 2 ? S[u] : S[u] / 2) + C[u];
       if (b < I.B && F < bestF) {
         bestF = F;
         bestb = b;
       }
       if (b0 == 0) {
         F1[u] = F;
-      } else if (b < I.B) {  // more than U * NT restarts: store as we go
+      } else if (b < I.B && !fin) {  // more than U * NT restarts: store as we go
         I.Sacc[b] = 0;
         I.Cacc[b] = 0;
-        if (I.nflip && mode == 1) I.nflip[b] = 0;
         I.Fall[b] = F;
       }
     }
@@ -258,18 +255,19 @@ __device__ void best_of_B(const InstDev& I, int mode, int tid, int64_t* sF, int*
     }
   }
   __syncthreads();
+  if (!fin) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int b = u * NT + tid;
-    if (b >= I.B) continue;
-    I.Sacc[b] = 0;  // ready for the next evaluation
-    I.Cacc[b] = 0;
-    if (I.nflip && mode == 1) I.nflip[b] = 0;
-    I.Fall[b] = F1[u];
+    for (int u = 0; u < U; ++u) {
+      const int b = u * NT + tid;
+      if (b >= I.B) continue;
+      I.Sacc[b] = 0;  // ready for the next evaluation
+      I.Cacc[b] = 0;
+      I.Fall[b] = F1[u];
+    }
   }
   if (*improved) {
     // whole 16-byte words of the winning row (best_x holds ld bytes)
-    const u32x4* src = (const u32x4*)(I.Xr + (size_t)sb[0] * I.ld);
+    const u32x4* src = (const u32x4*)((fin ? I.cand : (const uint8_t*)I.Xr) + (size_t)sb[0] * I.ld);
     u32x4* dst = (u32x4*)I.best_x;
     const int nv = I.ld / 16;
     for (int v0 = 0; v0 < nv; v0 += U * NT) {
@@ -314,6 +312,17 @@ __device__ __forceinline__ bool eval_block_needed(const InstDev& I, int n0, int 
     if (b < I.B && I.nflip[b] > kFlipMax) need = true;
   }
   return __syncthreads_or(need);
+}
+
+// Workgroups of a step launch past its tiles run the best of B of the
+// previous iteration, one instance each (incremental evaluation only: it reads
+// the finalised objectives and the kept rows, nothing the step writes).
+template <int NT>
+__device__ __forceinline__ void best_of_B_extra(const InstDev& I) {
+  __shared__ int64_t sF[NT / 64];
+  __shared__ int sb[NT / 64];
+  __shared__ int improved;
+  best_of_B<NT>(I, 1, threadIdx.x, sF, sb, &improved);
 }
 
 // Epilogue of one tile, shared by both main loops.  STEP/GRAD: lane holds
@@ -656,7 +665,11 @@ __device__ __forceinline__ void gemm_epilogue_rows(
 template <int BM, int BN, int WM, int WN, int P, int EPI, int GK>
 __global__ void __launch_bounds__(64 * WM * WN)
     dense_gemm(const TileDev* __restrict__ tiles, int ntiles, const InstDev* __restrict__ insts,
-               int parity) {
+               int parity, int am0) {
+  if (blockIdx.x >= ntiles) {
+    if constexpr (EPI == EPI_STEP) best_of_B_extra<64 * WM * WN>(insts[am0 + blockIdx.x - ntiles]);
+    return;
+  }
   constexpr int NT = 64 * WM * WN;
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
@@ -790,7 +803,11 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 template <int BM, int BN, int WM, int WN, int P, int EPI, int GK>
 __global__ void __launch_bounds__(64 * WM * WN)
     dense_gemm_dma(const TileDev* __restrict__ tiles, int ntiles, const InstDev* __restrict__ insts,
-                   int parity) {
+                   int parity, int am0) {
+  if (blockIdx.x >= ntiles) {
+    if constexpr (EPI == EPI_STEP) best_of_B_extra<64 * WM * WN>(insts[am0 + blockIdx.x - ntiles]);
+    return;
+  }
   constexpr int NW = WM * WN;
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
@@ -1010,12 +1027,13 @@ const TileCfgInfo& dense_cfg(int id) { return kCfgs[id]; }
 
 template <int BM, int BN, int WM, int WN, int P, int EPI, int DMA, int GK>
 static hipError_t launch_one(const TileDev* tiles, int ntiles, const InstDev* insts, int parity,
-                             int grid, hipStream_t s) {
+                             int grid, hipStream_t s, int am0, int amn) {
   if (grid <= 0 || grid > ntiles) grid = ntiles;
+  if (EPI == EPI_STEP && amn > 0 && ntiles > 0) grid = ntiles + amn;  // one tile per workgroup
   if constexpr (DMA) {
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL((dense_gemm_dma<BM, BN, WM, WN, P, EPI, GK>), dim3(grid), dim3(64 * WM * WN),
-                       0, s, tiles, ntiles, insts, parity);
+                       0, s, tiles, ntiles, insts, parity, am0);
   } else {
     constexpr int lds = gemm_lds_bytes<BM, BN>();
     auto kern = dense_gemm<BM, BN, WM, WN, P, EPI, GK>;
@@ -1027,7 +1045,8 @@ static hipError_t launch_one(const TileDev* tiles, int ntiles, const InstDev* in
       attr_done = true;
     }
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds, s, tiles, ntiles, insts, parity);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WM * WN), lds, s, tiles, ntiles, insts, parity,
+                       am0);
   }
   return hipGetLastError();
 }
@@ -1036,9 +1055,10 @@ static hipError_t launch_one(const TileDev* tiles, int ntiles, const InstDev* in
 // use g and take GK = 0.
 template <int BM, int BN, int WM, int WN, int DMA>
 static hipError_t launch_cfg(int prec, int epi, int gkind, const TileDev* tiles, int ntiles,
-                             const InstDev* insts, int parity, int grid, hipStream_t s) {
+                             const InstDev* insts, int parity, int grid, hipStream_t s, int am0,
+                             int amn) {
 #define PDBO_L(P, E, G) \
-  launch_one<BM, BN, WM, WN, P, E, DMA, G>(tiles, ntiles, insts, parity, grid, s)
+  launch_one<BM, BN, WM, WN, P, E, DMA, G>(tiles, ntiles, insts, parity, grid, s, am0, amn)
   if (epi == EPI_EVAL) return PDBO_L(P_I8, EPI_EVAL, 0);
   const int g = (epi == EPI_STEP && gkind != 0) ? 1 : 0;
   switch ((prec * 2 + epi) * 2 + g) {
@@ -1060,11 +1080,13 @@ static hipError_t launch_cfg(int prec, int epi, int gkind, const TileDev* tiles,
 }
 
 hipError_t launch_dense_gemm(int cfg, int prec, int epi, int gkind, const TileDev* tiles,
-                             int ntiles, const InstDev* insts, int parity, int grid, hipStream_t s) {
+                             int ntiles, const InstDev* insts, int parity, int grid, hipStream_t s,
+                             int am0, int amn) {
   switch (cfg) {
-#define X(id, bm, bn, wm, wn, dma) \
-  case id:                         \
-    return launch_cfg<bm, bn, wm, wn, dma>(prec, epi, gkind, tiles, ntiles, insts, parity, grid, s);
+#define X(id, bm, bn, wm, wn, dma)                                                            \
+  case id:                                                                                    \
+    return launch_cfg<bm, bn, wm, wn, dma>(prec, epi, gkind, tiles, ntiles, insts, parity, grid, \
+                                           s, am0, amn);
     PDBO_TILE_CFGS(X)
 #undef X
     default:
@@ -1194,7 +1216,9 @@ hipError_t launch_quantize_A(const int32_t* Ahat, int n, int ld, int prec, uint8
 // new rounded row and accumulates the dot products of the rows i in D of Ahat
 // with them (v_dot4_i32_i8, int32: |Ahat x'|_i <= 127 n); delta_i is +1 where
 // x'_i = 1, and the pairs are spread over the threads.  Restarts evaluated in
-// full (more than kFlipMax changes) only have their bitmap cleared.
+// full (more than kFlipMax changes) take the product's partials.  Either way
+// the kernel finalises the restart's objective and resets its counters, and
+// keeps its rounded row when it beats the incumbent, for the best of B.
 //
 // At a few changes per restart the kernel is a chain of memory round trips,
 // so the loads are issued in as few batches as possible: the count with the
@@ -1223,12 +1247,43 @@ __global__ void __launch_bounds__(kIncrThreads)
   PDBO_GLOBAL uint32_t* bits = gptr(I.fbits + (size_t)b * nw32);
   const int k = *gptr(I.nflip + b);
   const uint32_t m0 = tid < nw32 ? bits[tid] : 0u;  // with the count, before it is known
-  if (k == 0) return;  // unchanged: F carries over, the bitmap is clear
+  const int64_t Fp = *gptr(I.Fall + b);
+  const int64_t incF = *gptr(&I.inc->F);
+  const PDBO_GLOBAL int8_t* xrow = gptr(I.Xr + (size_t)b * ld);
+  const int nv = ld / 16;
+  // Only thread 0 reads and resets the restart's partials, count and
+  // objective.  The new objective F is the same in every thread; the rounded
+  // row is kept when it beats the incumbent of the earlier iterations, whose
+  // best of B has run by now.
+  auto finish = [&](int64_t F) {
+    if (tid == 0) {
+      *gptr(I.Fall + b) = F;
+      *gptr(I.nflip + b) = 0;
+      *gptr(I.Sacc + b) = 0;  // ready for the next evaluation
+      *gptr(I.Cacc + b) = 0;
+    }
+    if (F < incF) {
+      PDBO_GLOBAL u32x4* dst = (PDBO_GLOBAL u32x4*)gptr(I.cand + (size_t)b * ld);
+      for (int v = tid; v < nv; v += NT) dst[v] = ((const PDBO_GLOBAL u32x4*)xrow)[v];
+    }
+  };
+  if (k == 0) {  // unchanged: F carries over, the bitmap is clear
+    if (tid == 0) {  // partials of a column block that was evaluated in full
+      *gptr(I.Sacc + b) = 0;
+      *gptr(I.Cacc + b) = 0;
+    }
+    return;
+  }
   if (tid == 0) nfl = 0;
+  if (k > kFlipMax && tid == 0) {  // evaluated in full: the product's partials
+    const int64_t S = *gptr(I.Sacc + b), C = *gptr(I.Cacc + b);
+    part[0] = (I.kappa == 2 ? S : S / 2) + C;
+  }
   __syncthreads();
-  if (k > kFlipMax) {  // evaluated in full
+  if (k > kFlipMax) {
     if (m0) bits[tid] = 0u;
     for (int w = tid + NT; w < nw32; w += NT) bits[w] = 0u;
+    finish(part[0]);
     return;
   }
   auto take = [&](int w, uint32_t m) {
@@ -1246,12 +1301,10 @@ __global__ void __launch_bounds__(kIncrThreads)
   __syncthreads();
   const int kk = min(nfl, kFlipMax);
   if (kk == 0) {  // a count without marks: nothing to add
-    if (tid == 0) *gptr(I.dF + b) = 0;
+    finish(Fp);
     return;
   }
-  const PDBO_GLOBAL int8_t* xrow = gptr(I.Xr + (size_t)b * ld);
   const PDBO_GLOBAL int8_t* A8 = gptr(I.A8);
-  const int nv = ld / 16;
 
   // operands of the last stage: sign and linear term of change tid, and the
   // first pass of pairs (e, f), e < f.  They are loaded without branches, at
@@ -1323,12 +1376,10 @@ __global__ void __launch_bounds__(kIncrThreads)
   for (int o = 32; o > 0; o >>= 1) acc64 += __shfl_xor(acc64, o);
   if (lane == 0) part[wid] = acc64;
   __syncthreads();
-  if (tid == 0) {
-    int64_t t = 0;
+  int64_t dF = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) t += part[w];
-    *gptr(I.dF + b) = t;
-  }
+  for (int w = 0; w < NW; ++w) dF += part[w];
+  finish(Fp + dF);
 }
 
 hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, hipStream_t s) {

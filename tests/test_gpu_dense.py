@@ -284,8 +284,11 @@ def test_timing_classes_and_trace():
         assert ctx.kernel_time(k)[1] == 0
     ctx.timing(True)
     ctx.step(3)
-    for k in (P.PDBO_K_STEP, P.PDBO_K_EVAL, P.PDBO_K_INCR, P.PDBO_K_ARGMIN):
+    for k in (P.PDBO_K_STEP, P.PDBO_K_EVAL, P.PDBO_K_INCR):
         assert ctx.kernel_time(k)[1] == 3, k
+    # the best of B of the first two iterations runs inside the next step
+    # launch; only the last one has a launch of its own
+    assert ctx.kernel_time(P.PDBO_K_ARGMIN)[1] == 1
     with pytest.raises(P.PdboError):
         ctx.timing(True, classes=[7])
     ctx.timing(False)
