@@ -397,9 +397,14 @@ def main():
                 avg_launch_ms=h["step_kernel_ms"], launches=h["launches"],
                 note="int8 multiply-adds count as 2 operations against the 5.0 POP/s int8 peak"
                      if head == "i8" else "")
-    ev = dict(kernel="dense_gemm<i8, EVAL>", achieved=flops / (h["eval_kernel_ms"] * 1e-3) / 1e12,
-              peak=PEAK_TFLOPS["i8"], unit="TOP/s")
-    ev["frac"] = ev["achieved"] / ev["peak"]
+    # In the steady state every tile of the evaluation GEMM finds no restart of
+    # its column block that needs a full product and exits, so a roofline
+    # fraction does not apply; its launch time and that of the incremental
+    # kernel are reported as they are.
+    ev = dict(kernel="dense_gemm<i8, EVAL>", avg_launch_ms=h["eval_kernel_ms"],
+              incremental_kernel_ms=h["eval_incr_kernel_ms"],
+              note="steady state: every evaluation tile skips its column block (at most 32 rounding "
+                   "changes per restart); the incremental kernel evaluates exactly")
     line = dict(metric=METRIC, value=h["value"], unit=UNIT, n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=h["ms_per_step"], higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype=head, data="synthetic",
@@ -407,7 +412,7 @@ def main():
                                      f"B={args.B}, quality run T={args.T}",
                             n=q.n, B=args.B, T=args.T, scale=s, precision=head,
                             g="x^2-x", y0=6.0, alpha=0.025, beta=0.025, delta=2 ** -7),
-                forms=res, roofline=roof, eval_roofline=ev)
+                forms=res, roofline=roof, evaluation=ev)
     if "fp32" in res and head != "fp32":
         f32 = res["fp32"]
         line["speedup_vs_fp32"] = h["value"] / f32["value"]
