@@ -89,6 +89,10 @@ struct pdbo_ctx {
   int graph_parity0 = -1;
   // the best of B of the last iteration has not run yet (incremental evaluation)
   bool argmin_pending = false;
+  // with incremental evaluation, the evaluation GEMM runs in iterations before
+  // this one (the transient after init or set_state, when many rounded
+  // coordinates change); later iterations evaluate such restarts by rows
+  int64_t full_until = 0;
   // CSR / MaxSAT persistent
   CsrDev csr{};
   bool compact = false;
@@ -830,6 +834,20 @@ pdbo_status autotune_dense(pdbo_ctx* c) {
   return PDBO_OK;
 }
 
+// Iterations after init or set_state in which the evaluation GEMM runs:
+// PDBO_FULL_EVAL_ITERS, default 64.  Afterwards a restart whose rounded
+// iterate changed in more than kFlipMax coordinates is evaluated by rows in
+// the incremental kernel, which is exact but slow; on the workloads here no
+// restart does after about 20 iterations.
+int64_t full_eval_iters() {
+  const char* e = std::getenv("PDBO_FULL_EVAL_ITERS");
+  if (e && *e) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 0) return v;
+  }
+  return 64;
+}
+
 // With incremental evaluation an iteration's best of B is left pending: it
 // runs in extra workgroups of the next step launch (on CUs the tiles leave
 // free), or in a launch of its own when the steps stop (flush_argmin).
@@ -837,6 +855,7 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
   const bool do_eval = ((c->t_host + 1) % c->eval_every) == 0;
   const int ninst = (int)c->insts_h.size();
   const bool incr = c->incr_off.back() > 0;  // every instance, eval_every = 1
+  const bool full = do_eval && (!incr || c->t_host < c->full_until);
   TimedLaunch tl;
   if (c->grouped) {
     t_begin(c, tl, PDBO_K_STEP);
@@ -847,13 +866,16 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
     if (do_eval) {
       // full products only for the column blocks that need them; then the
       // exact differences of every restart with few rounding changes
-      t_begin(c, tl, PDBO_K_EVAL);
-      HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d, (int)c->tiles_h.size(),
-                                  c->insts_d, c->parity, 0, c->stream));
-      t_end(c, tl);
-      if (c->incr_off.back() > 0) {
+      if (full) {
+        t_begin(c, tl, PDBO_K_EVAL);
+        HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d,
+                                    (int)c->tiles_h.size(), c->insts_d, c->parity, 0, c->stream));
+        t_end(c, tl);
+      }
+      if (incr) {
         t_begin(c, tl, PDBO_K_INCR);
-        HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d, c->incr_off.back(), c->stream));
+        HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d, c->incr_off.back(), full ? 1 : 0,
+                                   c->stream));
         t_end(c, tl);
       }
     }
@@ -872,14 +894,16 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
     }
     if (do_eval)
       for (int k = 0; k < ninst; ++k) {
-        t_begin(c, tl, PDBO_K_EVAL);
-        HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d + c->tile_off[k],
-                                    c->tile_cnt[k], c->insts_d, c->parity, 0, c->stream));
-        t_end(c, tl);
+        if (full) {
+          t_begin(c, tl, PDBO_K_EVAL);
+          HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d + c->tile_off[k],
+                                      c->tile_cnt[k], c->insts_d, c->parity, 0, c->stream));
+          t_end(c, tl);
+        }
         const int w0 = c->incr_off[k], nw = c->incr_off[k + 1] - w0;
         if (nw > 0) {
           t_begin(c, tl, PDBO_K_INCR);
-          HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d + w0, nw, c->stream));
+          HIPCHK(c, launch_eval_incr(c->insts_d, c->incr_work_d + w0, nw, full ? 1 : 0, c->stream));
           t_end(c, tl);
         }
       }
@@ -911,7 +935,8 @@ pdbo_status dense_steps(pdbo_ctx* c, int nsteps) {
   const bool use_graph = K > 0 && c->eval_every == 1 && !c->timing;
   int left = nsteps;
   while (left > 0) {
-    if (use_graph && left >= K) {
+    // graphs hold iterations past the transient (no evaluation GEMM)
+    if (use_graph && left >= K && c->t_host >= c->full_until) {
       if (!c->gexec) {
         // The caller's stream may be the legacy default stream, which cannot
         // be captured: record the K iterations on a private stream (nothing
@@ -1055,6 +1080,7 @@ static pdbo_status dense_init(int k, const pdbo_qubo* probs, const pdbo_params* 
   pdbo_ctx* c = new pdbo_ctx();
   c->kind = 0;
   c->grouped = grouped ? 1 : 0;
+  c->full_until = full_eval_iters();
   pdbo_status st = begin_ctx(c, stream, &pars[0]);
   if (st == PDBO_OK) {
     if (pars[0].tile > 0) {
@@ -1310,6 +1336,7 @@ pdbo_status qubo_gda_set_state(pdbo_ctx* c, const float* x, const float* y, int6
   HIPCHK(c, launch_set_state((const float*)tx.p, (const float*)ty.p, c->B, n, ld, X, Y, Xs, c->prec,
                              c->stream));
   c->t_host = t;
+  c->full_until = t + full_eval_iters();
   if (c->kind == 0) {
     HIPCHK(c, hipMemcpyAsync(c->insts_h[0].t_dev, &t, sizeof(t), hipMemcpyHostToDevice, c->stream));
     // the rounded iterate no longer follows the recorded changes

@@ -158,7 +158,10 @@ hipError_t launch_dense_gemm(int cfg, int prec, int epi, int gkind, const TileDe
                              int am0 = 0, int amn = 0);
 hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, hipStream_t s);
 // work[w] = (instance, first restart) of the workgroups of the incremental evaluation
-hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, hipStream_t s);
+// full_done: the evaluation GEMM ran in this iteration (its partials hold the
+// full products); otherwise restarts that need one are evaluated by rows
+hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, int full_done,
+                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
 hipError_t launch_stamp(uint64_t* ts0, hipStream_t s);
 hipError_t launch_init_state(const double* x0, int B, int n, int ld, float y0, float* X,

@@ -1231,10 +1231,95 @@ constexpr int kIncrThreads = 256;
 constexpr int kIncrV = 3;  // 16-byte chunks of a row per thread and pass
 constexpr int kIncrE = 4;  // rows of D loaded together
 
+// Objective of a rounded row from scratch, by rows of Ahat: with S the sum of
+// (Ahat x')_i and C the sum of c'_i over the coordinates i where x'_i = 1,
+// F = (kappa / 2) S + C.  The incremental kernel takes this path for a restart
+// with more than kFlipMax changes (or a first evaluation after init or
+// set_state) when the evaluation GEMM did not run in this iteration.  It reads
+// n bytes of Ahat per set coordinate: slow, and meant to be rare.  The set
+// coordinates are collected 4 * NT at a time into lst.
+template <int NT, int V, int E>
+__device__ int64_t objective_by_rows(const InstDev& I, const PDBO_GLOBAL int8_t* xrow, int ld,
+                                     int nv, int tid, int* lst, int* cnt, int64_t* part) {
+  const int lane = tid & 63, wid = tid >> 6;
+  constexpr int NW = NT / 64;
+  const PDBO_GLOBAL int8_t* A8 = gptr(I.A8);
+  const int nw = ld / 4;  // 32-bit words of the row, four 0/1 bytes each
+  int64_t accS = 0, accC = 0;
+  for (int v0 = 0; v0 < nv; v0 += NT * V) {
+    u32x4 x[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int idx = v0 + v * NT + tid;
+      x[v] = *(const PDBO_GLOBAL u32x4*)(xrow + (size_t)min(idx, nv - 1) * 16);
+      if (idx >= nv) x[v] = u32x4{0, 0, 0, 0};
+    }
+    for (int s0 = 0; s0 < nw; s0 += NT) {
+      if (tid == 0) *cnt = 0;
+      __syncthreads();
+      const int w = s0 + tid;
+      const uint32_t word = w < nw ? ((const PDBO_GLOBAL uint32_t*)xrow)[w] : 0u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)  // padding coordinates (>= n) are zero; never indexed
+        if (((word >> (8 * q)) & 1u) && 4 * w + q < I.n) lst[atomicAdd(cnt, 1)] = 4 * w + q;
+      __syncthreads();
+      const int m = *cnt;  // at most 4 * NT
+      if (v0 == 0)
+        for (int e = tid; e < m; e += NT) accC += *gptr(I.cp + lst[e]);
+      for (int g = 0; g < m; g += E) {
+        u32x4 a[E][V];
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const PDBO_GLOBAL int8_t* arow = A8 + (size_t)lst[min(g + j, m - 1)] * ld;
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            a[j][v] =
+                *(const PDBO_GLOBAL u32x4*)(arow + (size_t)min(v0 + v * NT + tid, nv - 1) * 16);
+        }
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          if (g + j >= m) break;
+          int d = 0;
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            d = __builtin_amdgcn_sdot4((int)a[j][v].x, (int)x[v].x, d, false);
+            d = __builtin_amdgcn_sdot4((int)a[j][v].y, (int)x[v].y, d, false);
+            d = __builtin_amdgcn_sdot4((int)a[j][v].z, (int)x[v].z, d, false);
+            d = __builtin_amdgcn_sdot4((int)a[j][v].w, (int)x[v].w, d, false);
+          }
+          accS += d;
+        }
+      }
+      __syncthreads();  // every thread is done with lst
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    accS += __shfl_xor(accS, o);
+    accC += __shfl_xor(accC, o);
+  }
+  if (lane == 0) part[wid] = accS;
+  __syncthreads();
+  int64_t S = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) S += part[w];
+  __syncthreads();
+  if (lane == 0) part[wid] = accC;
+  __syncthreads();
+  int64_t C = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) C += part[w];
+  __syncthreads();
+  return (I.kappa == 2 ? S : S / 2) + C;
+}
+
 __global__ void __launch_bounds__(kIncrThreads)
-    eval_incr_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ work) {
+    eval_incr_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ work,
+                     int full_done) {
   constexpr int NT = kIncrThreads, NW = NT / 64, V = kIncrV, E = kIncrE;
   static_assert(kFlipMax % E == 0, "whole groups of rows");
+  __shared__ int lst[4 * NT];
+  __shared__ int lcnt;
   __shared__ int fl[kFlipMax];
   __shared__ int nfl;
   __shared__ int red[NW][kFlipMax];
@@ -1283,7 +1368,8 @@ __global__ void __launch_bounds__(kIncrThreads)
   if (k > kFlipMax) {
     if (m0) bits[tid] = 0u;
     for (int w = tid + NT; w < nw32; w += NT) bits[w] = 0u;
-    finish(part[0]);
+    const int64_t F = part[0];  // the partials are zero when the GEMM did not run
+    finish(full_done ? F : objective_by_rows<NT, V, E>(I, xrow, ld, nv, tid, lst, &lcnt, part));
     return;
   }
   auto take = [&](int w, uint32_t m) {
@@ -1382,9 +1468,11 @@ __global__ void __launch_bounds__(kIncrThreads)
   finish(Fp + dF);
 }
 
-hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, hipStream_t s) {
+hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, int full_done,
+                            hipStream_t s) {
   if (nwork == 0) return hipSuccess;
-  hipLaunchKernelGGL(eval_incr_kernel, dim3(nwork), dim3(kIncrThreads), 0, s, insts, work);
+  hipLaunchKernelGGL(eval_incr_kernel, dim3(nwork), dim3(kIncrThreads), 0, s, insts, work,
+                     full_done);
   return hipGetLastError();
 }
 

@@ -190,6 +190,10 @@ def test_twin_reaches_brute_force_optimum(rep):
 
 
 def test_determinism_resume_graph():
+    """Bit-identical iterates and incumbents with and without hipGraph replays
+    (graphs start after the evaluation GEMM's transient of 64 iterations), and
+    through get/set_state into a fresh context, whose transient restarts at
+    the resumed iteration."""
     P = require_gpu()
     q = W.random_dense_qubo(300, -100, 100, W.rng_for(3, 2, 0, 300))
     s = W.qubo_scale(q)
@@ -198,23 +202,65 @@ def test_determinism_resume_graph():
     say("[dense determinism/resume/graph]")
     outs = []
     for gc in (0, 0, 8):
-        ctx = P.qubo_gda_init(q, W.gda_params("qubo", B=B, T=40, scale=s, precision="bf16", graph_chunk=gc), x0)
+        ctx = P.qubo_gda_init(q, W.gda_params("qubo", B=B, T=100, scale=s, precision="bf16", graph_chunk=gc), x0)
         ctx.step(17)
         ctx.step(23)
+        ctx.step(60)
         X, Y, t = ctx.get_state()
         outs.append((X, Y, ctx.result()))
     for X, Y, r in outs[1:]:
         assert np.array_equal(X, outs[0][0]) and np.array_equal(Y, outs[0][1])
         assert r["best_obj"] == outs[0][2]["best_obj"] and r["best_iter"] == outs[0][2]["best_iter"]
     # resume through get/set_state into a fresh context
-    ctx = P.qubo_gda_init(q, W.gda_params("qubo", B=B, T=40, scale=s, precision="bf16"), x0)
+    ctx = P.qubo_gda_init(q, W.gda_params("qubo", B=B, T=100, scale=s, precision="bf16"), x0)
     ctx.step(17)
     X17, Y17, _ = ctx.get_state()
-    ctx2 = P.qubo_gda_init(q, W.gda_params("qubo", B=B, T=40, scale=s, precision="bf16"), x0)
+    ctx2 = P.qubo_gda_init(q, W.gda_params("qubo", B=B, T=100, scale=s, precision="bf16", graph_chunk=8), x0)
     ctx2.set_state(X17, Y17, 17)
-    ctx2.step(23)
+    ctx2.step(83)
     X, Y, t = ctx2.get_state()
-    assert t == 40 and np.array_equal(X, outs[0][0]) and np.array_equal(Y, outs[0][1])
+    assert t == 100 and np.array_equal(X, outs[0][0]) and np.array_equal(Y, outs[0][1])
+    F = ctx2.objectives()
+    assert np.array_equal(F, oq.objective(q, X > 0.5))
+
+
+@pytest.mark.parametrize("full_iters", ["0", "2"])
+def test_objectives_by_rows_after_transient(full_iters, monkeypatch):
+    """Past the transient (PDBO_FULL_EVAL_ITERS iterations after init) the
+    evaluation GEMM no longer runs: restarts with more than 32 rounding changes,
+    and with 0 the first evaluation, are evaluated by rows of Ahat in the
+    incremental kernel.  The objectives equal the oracle's at every step, and
+    the incumbent equals that of a context that runs the GEMM throughout."""
+    P = require_gpu()
+    monkeypatch.setenv("PDBO_FULL_EVAL_ITERS", full_iters)
+    n, B = 517, 96
+    q = W.random_dense_qubo(n, -50, 50, W.rng_for(7, 1, 0, n))
+    s = W.qubo_scale(q)
+    x0 = W.x0_uniform(7, 1, B, n)
+    p = W.gda_params("qubo", B=B, T=30, scale=s, precision="i8")
+    say(f"[objectives by rows] n={n} B={B} transient={full_iters}")
+    ctx = P.qubo_gda_init(q, p, x0)
+    prev = None
+    many = 0
+    for t in range(30):
+        ctx.step(1)
+        Xg, _, _ = ctx.get_state()
+        xr = Xg > 0.5
+        assert np.array_equal(ctx.objectives(), oq.objective(q, xr)), t
+        if prev is not None and t >= int(full_iters):
+            many += int(np.sum(np.sum(xr != prev, axis=1) > 32))
+        prev = xr
+    say(f"   restarts evaluated by rows after the transient: {many}")
+    assert many > 0
+    r = ctx.result()
+    assert r["best_obj"] == oq.objective(q, r["best_x"][None])[0]
+    monkeypatch.setenv("PDBO_FULL_EVAL_ITERS", "1000")
+    ref = P.qubo_gda_init(q, p, x0)
+    ref.step(30)
+    r2 = ref.result()
+    assert (r["best_obj"], r["best_iter"], r["best_restart"]) == \
+        (r2["best_obj"], r2["best_iter"], r2["best_restart"])
+    assert np.array_equal(r["best_x"], r2["best_x"])
 
 
 def test_batched_grouped_equals_per_instance_and_single():
