@@ -15,7 +15,7 @@ Prints one JSON line: restart-iterations/s of the fastest mixed-precision form
 whose best objective after T iterations is within 0.1% of the plain FP32
 form's as `value` (every form is listed under `forms`), the best objective
 found by 1 s of device time for each form, the roofline of the dominant kernel
-(HIP-event times of its launches in the timed region) and the CPU oracle
+(HIP-event times of every fifth of its launches in the timed region) and the CPU oracle
 baseline.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -89,8 +89,9 @@ def run_form(P, q, s, x0, form, args):
     ctx.step(args.warmup)
     torch.cuda.synchronize()
     # timed region: only the step kernel (the roofline's) is bracketed by events,
-    # since every timed launch adds two event records to the stream
-    ctx.timing(True, classes=[P.PDBO_K_STEP])
+    # and only every time_stride-th launch of it, since every timed launch adds
+    # two event records to the stream
+    ctx.timing(True, classes=[P.PDBO_K_STEP], stride=args.time_stride)
     torch.cuda.synchronize()
     ts = time.perf_counter()
     ctx.step(args.steps)
@@ -326,6 +327,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--breakdown-steps", type=int, default=20,
                     help="steps after the timed region that time the evaluation and argmin kernels")
+    ap.add_argument("--time-stride", type=int, default=5,
+                    help="in the timed region, bracket every time-stride-th step launch with HIP events")
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--B", type=int, default=1024)
     ap.add_argument("--T", type=int, default=2000, help="iterations of the quality run")
@@ -399,6 +402,7 @@ def main():
                 peak=PEAK_TFLOPS[head], unit="TFLOP/s", frac=achieved / PEAK_TFLOPS[head],
                 traffic=traffic, flop_per_launch=flops,
                 avg_launch_ms=h["step_kernel_ms"], launches=h["launches"],
+                launches_timed_every=args.time_stride,
                 note="int8 multiply-adds count as 2 operations against the 5.0 POP/s int8 peak"
                      if head == "i8" else "")
     # Past the transient after init (64 iterations) the evaluation GEMM does

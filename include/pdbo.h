@@ -271,6 +271,12 @@ PDBO_API pdbo_status pdbo_timing(pdbo_ctx* ctx, int32_t enable);
  * Clears the accumulated times.  PDBO_EINVAL for bits beyond PDBO_K_COUNT. */
 PDBO_API pdbo_status pdbo_timing_classes(pdbo_ctx* ctx, uint32_t mask);
 
+/* Times only every stride-th launch of each timed class, counting from the
+ * first launch after this call or pdbo_timing / pdbo_timing_classes (1, the
+ * default, times every launch), so that a long timed run carries fewer event
+ * records.  Clears the accumulated times.  PDBO_EINVAL for stride < 1. */
+PDBO_API pdbo_status pdbo_timing_stride(pdbo_ctx* ctx, int32_t stride);
+
 /* Accumulated device time (ms) and launch count of kernel class `which`
  * (PDBO_K_*) since timing was enabled.  Synchronises. */
 PDBO_API pdbo_status pdbo_kernel_time(pdbo_ctx* ctx, int32_t which, double* total_ms, int64_t* launches);

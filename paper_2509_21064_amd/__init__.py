@@ -152,8 +152,9 @@ class Context:
     def trace(self, cap=4096):
         return qubo_gda_trace(self, cap)
 
-    def timing(self, enable=True, classes=None):
-        """Kernel timing on (all classes, or the PDBO_K_* classes listed) or off."""
+    def timing(self, enable=True, classes=None, stride=1):
+        """Kernel timing on (all classes, or the PDBO_K_* classes listed) or off;
+        with stride > 1 only every stride-th launch of a class is timed."""
         if classes is not None and enable:
             mask = 0
             for k in classes:
@@ -161,6 +162,7 @@ class Context:
             check(load().pdbo_timing_classes(self.h, mask), self.h)
         else:
             check(load().pdbo_timing(self.h, int(bool(enable))), self.h)
+        check(load().pdbo_timing_stride(self.h, int(stride)), self.h)
 
     def kernel_time(self, which):
         ms, cnt = ctypes.c_double(), ctypes.c_int64()

@@ -72,6 +72,7 @@ SIGNATURES = {
                              POINTER(c_int32)]),
     "pdbo_timing": (_st, [_ctx, c_int32]),
     "pdbo_timing_classes": (_st, [_ctx, c_uint32]),
+    "pdbo_timing_stride": (_st, [_ctx, c_int32]),
     "pdbo_kernel_time": (_st, [_ctx, c_int32, POINTER(c_double), POINTER(c_int64)]),
     "pdbo_tile_name": (c_char_p, [_ctx]),
     "pdbo_destroy": (None, [_ctx]),

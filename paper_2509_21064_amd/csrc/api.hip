@@ -103,6 +103,8 @@ struct pdbo_ctx {
   // timing
   bool timing = false;
   uint32_t tmask = 0;  // kernel classes being timed (bit k = PDBO_K_k)
+  int tstride = 1;     // time every tstride-th launch of a timed class
+  int64_t tseen[PDBO_K_COUNT] = {};  // launches of each class since timing was set
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> ev_pool;  // events already read, reused by later launches
   double ms[PDBO_K_COUNT] = {};
@@ -454,6 +456,7 @@ hipEvent_t ev_get(pdbo_ctx* c) {
 void t_begin(pdbo_ctx* c, TimedLaunch& tl, int cls) {
   tl.cls = -1;
   if (!c->timing || !((c->tmask >> cls) & 1u)) return;
+  if (c->tseen[cls]++ % c->tstride != 0) return;
   tl.a = ev_get(c);
   if (!tl.a) return;
   tl.b = ev_get(c);
@@ -1690,9 +1693,24 @@ pdbo_status pdbo_timing_classes(pdbo_ctx* c, uint32_t mask) {
   for (int k = 0; k < PDBO_K_COUNT; ++k) {
     c->ms[k] = 0.0;
     c->cnt[k] = 0;
+    c->tseen[k] = 0;
   }
   c->tmask = mask;
   c->timing = mask != 0;
+  return PDBO_OK;
+}
+
+pdbo_status pdbo_timing_stride(pdbo_ctx* c, int32_t stride) {
+  if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
+  if (stride < 1) return fail(c, PDBO_EINVAL, "stride must be >= 1");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  t_collect(c);
+  for (int k = 0; k < PDBO_K_COUNT; ++k) {
+    c->ms[k] = 0.0;
+    c->cnt[k] = 0;
+    c->tseen[k] = 0;
+  }
+  c->tstride = stride;
   return PDBO_OK;
 }
 

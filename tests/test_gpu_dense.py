@@ -341,6 +341,12 @@ def test_timing_classes_and_trace():
     assert ctx.kernel_time(P.PDBO_K_ARGMIN)[1] == 1
     with pytest.raises(P.PdboError):
         ctx.timing(True, classes=[7])
+    # every third launch: launches 0, 3 and 6 of seven
+    ctx.timing(True, classes=[P.PDBO_K_STEP], stride=3)
+    ctx.step(7)
+    assert ctx.kernel_time(P.PDBO_K_STEP)[1] == 3
+    with pytest.raises(P.PdboError):
+        ctx.timing(True, classes=[P.PDBO_K_STEP], stride=0)
     ctx.timing(False)
     ctx.step(40)
     tr = ctx.trace()
