@@ -95,3 +95,38 @@ def test_c4_batch_64_instances():
         assert (rg[i]["best_obj"], rg[i]["best_iter"], rg[i]["best_restart"]) == \
             (ri[i]["best_obj"], ri[i]["best_iter"], ri[i]["best_restart"])
         assert rg[i]["best_obj"] == oq.objective(q, rg[i]["best_x"][None])[0]
+
+
+@pytest.mark.parametrize("full_iters", ["0", "64"])
+def test_dense_n13000_objectives_multi_pass(full_iters, monkeypatch):
+    """Rows longer than one pass of the incremental kernel (n = 13,000: each
+    thread holds three 16-byte chunks of a row, 12,288 bytes per pass): with
+    the evaluation GEMM kept (64) the incremental differences run over two
+    passes once few coordinates change; with 0 every restart is evaluated by
+    rows over two passes.  Objectives of every step against the oracle."""
+    P = require_gpu()
+    monkeypatch.setenv("PDBO_FULL_EVAL_ITERS", full_iters)
+    n, B = 13000, 8
+    q = W.random_dense_qubo(n, -50, 50, W.rng_for(8, 0, 0, n))
+    s = W.qubo_scale(q)
+    x0 = W.x0_uniform(8, 0, B, n)
+    p = W.gda_params("qubo", B=B, T=40, scale=s, precision="i8")
+    steps = 40 if full_iters == "64" else 3
+    say(f"[fullsize multi-pass] n={n} B={B} transient={full_iters} steps={steps}")
+    ctx = P.qubo_gda_init(q, p, x0)
+    xs, Fs = [], []
+    for _ in range(steps):
+        ctx.step(1)
+        Xg, _, _ = ctx.get_state()
+        xs.append(Xg > 0.5)
+        Fs.append(ctx.objectives())
+    X = np.concatenate(xs)
+    assert np.array_equal(np.concatenate(Fs), oq.objective(q, X))
+    if full_iters == "64":
+        k = np.sum(xs[-1] != xs[-2], axis=1)
+        few = sum(int(np.sum((np.sum(a != b, axis=1) >= 1) & (np.sum(a != b, axis=1) <= 32)))
+                  for a, b in zip(xs[1:], xs[:-1]))
+        say(f"   (restart, step) pairs with 1..32 changes {few}; last step {k.tolist()}")
+        assert few > 0
+    r = ctx.result()
+    assert r["best_obj"] == oq.objective(q, r["best_x"][None])[0]
