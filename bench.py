@@ -11,12 +11,15 @@ after init the int8 GEMM for column blocks that need a full product, later a
 by-rows evaluation for such restarts) and the best-of-B / incumbent update,
 which runs inside the next step launch.
 
-Prints one JSON line: restart-iterations/s of the fastest mixed-precision form
-whose best objective after T iterations is within 0.1% of the plain FP32
-form's as `value` (every form is listed under `forms`), the best objective
-found by 1 s of device time for each form, the roofline of the dominant kernel
-(HIP-event times of every fifth of its launches in the timed region) and the CPU oracle
-baseline.
+Prints one JSON line.  `value` is the restart-iterations/s of the fastest
+mixed-precision form whose best objective after T iterations is within 0.1% of
+the plain FP32 form's on every seed: B*T/t_loop with t_loop from HIP events
+around a whole run of T = 2000 iterations (transient included), the median over
+5 seeds after one untimed warm-up run.  Every form is listed under `forms` with
+its per-seed runs, the best objective found by 1 s, a steady-state window past
+the transient (--steps/--warmup) and kernel times.  The roofline is that of the
+dominant kernel, the step GEMM, from HIP events around every fifth of its
+launches in one whole run.  The CPU oracle baseline closes the line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -74,78 +77,102 @@ def read_traffic(form, n, B):
         return None
 
 
-def run_form(P, q, s, x0, form, args):
-    import numpy as np
+def run_form(P, q, s, x0s, form, args):
+    """One operand form: an untimed warm-up run, then one whole run of T
+    iterations per seed (fresh starting points, incumbent cleared), each timed
+    with HIP events on the library's stream from before the first step to
+    after the last; a run with the step kernel's launches timed (every
+    time_stride-th) for the roofline; a steady-state window past the
+    transient."""
+    import statistics
+
     import torch
 
     import workloads as W
 
-    B, n = args.B, q.n
-    p = W.gda_params("qubo", B=B, T=args.T, scale=s, precision=form, tile=args.tile,
+    B, n, T = args.B, q.n, args.T
+    p = W.gda_params("qubo", B=B, T=T, scale=s, precision=form, tile=args.tile,
                      graph_chunk=args.graph_chunk)
     t0 = time.time()
-    ctx = P.qubo_gda_init(q, p, x0)
-    log(f"{form}: init {time.time() - t0:.1f}s (tile {ctx.tile_name})")
-    ctx.step(args.warmup)
+    ctx = P.qubo_gda_init(q, p, x0s[0])
+    init_s = time.time() - t0
+    log(f"{form}: init {init_s:.1f}s (tile {ctx.tile_name})")
+    ctx.step(T)  # warm-up run: first launch of every kernel, caches
     torch.cuda.synchronize()
-    # timed region: only the step kernel (the roofline's) is bracketed by events,
-    # and only every time_stride-th launch of it, since every timed launch adds
-    # two event records to the stream
+    runs = []
+    for seed, x0 in enumerate(x0s):
+        ctx.restart(x0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record()
+        ctx.step(T)
+        e1.record()
+        torch.cuda.synchronize()
+        t_loop = e0.elapsed_time(e1) * 1e-3
+        rec = dict(seed=seed, t_loop_s=t_loop, restart_it_per_s=B * T / t_loop)
+        if seed == 0:
+            # the same run goes on until it has lasted 1 s, so that the best
+            # objective at 1 s is read off a run that got there
+            total = T
+            while time.perf_counter() - w0 < 1.02:
+                ctx.step(250)
+                torch.cuda.synchronize()
+                total += 250
+            tr = ctx.trace()
+            at1 = [int(F) for F, sec in zip(tr["F"], tr["sec"]) if sec <= 1.0]
+            atT = [int(F) for F, t in zip(tr["F"], tr["t"]) if t <= T]
+            r = ctx.result()
+            rec.update(best_at_T=(atT[-1] if atT else None), best_at_1s=(at1[-1] if at1 else None),
+                       iterations_in_1s_run=total, best_at_end=int(r["best_obj"]),
+                       time_to_best_s=float(r["time_to_best_s"]), iter_of_best=int(r["best_iter"]))
+        else:
+            rec.update(best_at_T=int(ctx.result()["best_obj"]))
+        runs.append(rec)
+        log(f"{form}: seed {seed} T={T} in {t_loop:.4f}s = {B * T / t_loop:.4g} restart-it/s, "
+            f"best@T {rec['best_at_T']}")
+    rates = [r["restart_it_per_s"] for r in runs]
+    t_med = statistics.median(r["t_loop_s"] for r in runs)
+    # roofline run: every time_stride-th step launch bracketed by events
+    ctx.restart(x0s[0])
     ctx.timing(True, classes=[P.PDBO_K_STEP], stride=args.time_stride)
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    ctx.step(args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - ts
+    ctx.step(T)
     k_step = ctx.kernel_time(P.PDBO_K_STEP)
-    # the other kernels of the iteration, in a short pass of their own
+    # the other kernels of the iteration past the transient, timed on their own
     ctx.timing(True, classes=[P.PDBO_K_EVAL, P.PDBO_K_INCR, P.PDBO_K_ARGMIN])
     ctx.step(args.breakdown_steps)
     k_eval = ctx.kernel_time(P.PDBO_K_EVAL)
     k_arg = ctx.kernel_time(P.PDBO_K_ARGMIN)
     k_inc = ctx.kernel_time(P.PDBO_K_INCR)
     ctx.timing(False)
+    # steady-state window: W untimed, then K timed iterations, all past the
+    # evaluation transient whatever W is
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.step(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_win = e0.elapsed_time(e1) * 1e-3
     ctx.destroy()
-    # per-iteration averages over the timed steps; per-launch averages of the
-    # other kernels (past the transient the evaluation GEMM is not launched)
-    out = dict(value=B * args.steps / el, ms_per_step=1e3 * el / args.steps,
-               step_kernel_ms=k_step[0] / max(k_step[1], 1),
-               eval_kernel_ms=k_eval[0] / max(k_eval[1], 1),
+    out = dict(value=statistics.median(rates), ms_per_step=1e3 * t_med / T, T=T,
+               runs=runs, init_s=init_s,
+               step_kernel_ms=k_step[0] / max(k_step[1], 1), step_launches_timed=k_step[1],
+               eval_kernel_ms=k_eval[0] / max(k_eval[1], 1), eval_launches=k_eval[1],
                eval_incr_kernel_ms=k_inc[0] / max(k_inc[1], 1),
-               eval_launches=k_eval[1],
                argmin_kernel_ms=k_arg[0] / max(k_arg[1], 1), argmin_launches=k_arg[1],
-               breakdown_steps=args.breakdown_steps, launches=k_step[1])
-    log(f"{form}: {out['value']:.4g} restart-it/s, {out['ms_per_step']:.3f} ms/step "
-        f"(step {out['step_kernel_ms']:.3f} ms, eval {out['eval_kernel_ms']:.3f} ms "
-        f"x {out['eval_launches']} launches, "
-        f"incremental eval {out['eval_incr_kernel_ms']:.3f} ms, argmin {out['argmin_kernel_ms']:.3f} ms "
-        f"x {out['argmin_launches']} launches in {args.breakdown_steps} steps)")
-    if not args.no_quality:
-        ctx = P.qubo_gda_init(q, p, x0)
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        ctx.step(args.T)
-        torch.cuda.synchronize()
-        tq = time.perf_counter() - t_start
-        out.update(quality_run_s=tq, quality_run_restart_it_per_s=B * args.T / tq)
-        # a fast form finishes T iterations well inside 1 s: the run goes on until
-        # it has lasted 1 s, so that the best objective at 1 s is read off a run
-        # that got there
-        total = args.T
-        while time.perf_counter() - t_start < 1.02:
-            ctx.step(250)
-            torch.cuda.synchronize()
-            total += 250
-        r = ctx.result()
-        tr = ctx.trace()
-        ctx.destroy()
-        at1 = [int(F) for F, sec in zip(tr["F"], tr["sec"]) if sec <= 1.0]
-        atT = [int(F) for F, t in zip(tr["F"], tr["t"]) if t <= args.T]
-        out.update(best_at_1s=(at1[-1] if at1 else None), best_at_T=(atT[-1] if atT else None),
-                   T=args.T, iterations_run=total, best_at_end=int(r["best_obj"]),
-                   time_to_best_s=float(r["time_to_best_s"]), iter_of_best=int(r["best_iter"]))
-        log(f"{form}: best@T={args.T} {out['best_at_T']} ({tq:.3f}s)  best@1s {out['best_at_1s']}  "
-            f"best after {total} it {out['best_at_end']} (t={r['best_iter']}, {r['time_to_best_s']:.3f}s)")
+               breakdown_steps=args.breakdown_steps,
+               steady_state=dict(restart_it_per_s=B * args.steps / t_win,
+                                 ms_per_step=1e3 * t_win / args.steps, steps=args.steps,
+                                 warmup=args.warmup, first_iteration=T + args.breakdown_steps
+                                 + args.warmup + 1))
+    r0 = runs[0]
+    out.update(best_at_T=r0["best_at_T"], best_at_1s=r0["best_at_1s"])
+    log(f"{form}: median {out['value']:.4g} restart-it/s ({out['ms_per_step']:.4f} ms/it over T={T}), "
+        f"step kernel {out['step_kernel_ms']:.4f} ms avg over the run, steady state "
+        f"{out['steady_state']['ms_per_step']:.4f} ms/it; incr eval {out['eval_incr_kernel_ms']:.4f} ms, "
+        f"best@1s {r0['best_at_1s']}")
     return out
 
 
@@ -319,23 +346,24 @@ def workload_c4(args, P):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    # the first ~20 iterations change many rounded coordinates and evaluate with
-    # full products; the default warm-up puts the timed steps in the steady state
-    # that makes up almost all of a 1 s run (the whole-run rate, transient
-    # included, is reported as quality_run_restart_it_per_s)
-    ap.add_argument("--warmup", type=int, default=200)
+    # --steps / --warmup set the steady-state window (reported beside the
+    # headline); the headline is the whole-run rate B*T/t_loop over T iterations
+    ap.add_argument("--steps", type=int, default=50, help="iterations of the steady-state window")
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed iterations before the steady-state window (which starts past "
+                         "the evaluation transient whatever this is)")
+    ap.add_argument("--seeds", type=int, default=5,
+                    help="timed whole runs per form (starting points of seeds 0..seeds-1)")
     ap.add_argument("--breakdown-steps", type=int, default=20,
-                    help="steps after the timed region that time the evaluation and argmin kernels")
+                    help="steps after the roofline run that time the evaluation and argmin kernels")
     ap.add_argument("--time-stride", type=int, default=5,
-                    help="in the timed region, bracket every time-stride-th step launch with HIP events")
+                    help="in the roofline run, bracket every time-stride-th step launch with HIP events")
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--B", type=int, default=1024)
-    ap.add_argument("--T", type=int, default=2000, help="iterations of the quality run")
-    ap.add_argument("--forms", default="bf16,i8,fp32,fp8")
+    ap.add_argument("--T", type=int, default=2000, help="iterations of one whole run")
+    ap.add_argument("--forms", default="i8,fp8,bf16,fp32")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--graph-chunk", type=int, default=0)
-    ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-restarts", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -352,7 +380,6 @@ def main():
               "across GPUs but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2509_21064_amd as P
@@ -379,55 +406,66 @@ def main():
     t0 = time.time()
     q = W.qubo_c3(0, n=args.n)
     s = W.qubo_scale(q)
-    x0 = W.x0_uniform(3, 0, args.B, q.n)
+    x0s = [W.x0_uniform(3, seed, args.B, q.n) for seed in range(args.seeds)]
     log(f"instance n={q.n} B={args.B} s={s:.2f} generated in {time.time() - t0:.1f}s")
 
     forms = [f for f in args.forms.split(",") if f]
-    res = {f: run_form(P, q, s, x0, f, args) for f in forms}
+    res = {f: run_form(P, q, s, x0s, f, args) for f in forms}
     flops = 2.0 * q.n * q.n * args.B
     for f, r in res.items():
         r["step_kernel_frac_of_peak"] = flops / (r["step_kernel_ms"] * 1e-3) / 1e12 / PEAK_TFLOPS[f]
-    # headline: the fastest mixed-precision form whose best objective stays within
-    # 0.1% of the plain FP32 form's (all forms are reported)
+    # quality: per seed, the mixed form's best objective after T iterations
+    # against the plain FP32 form's on the same instance and starting points
+    if "fp32" in res:
+        for f, r in res.items():
+            gaps = [(a["best_at_T"] - b["best_at_T"]) / abs(b["best_at_T"])
+                    for a, b in zip(r["runs"], res["fp32"]["runs"])]
+            r["rel_gap_best_at_T_vs_fp32"] = gaps
+            r["within_0.1pct_all_seeds"] = bool(all(g <= 1e-3 for g in gaps))
+    # headline: the fastest mixed-precision form within 0.1% of FP32 on every
+    # seed (all forms are reported)
     mixed = [f for f in forms if f != "fp32"] or forms
-    ok = mixed
-    if "fp32" in res and not args.no_quality:
-        ref = res["fp32"]["best_at_T"]
-        ok = [f for f in mixed if (res[f]["best_at_T"] - ref) / abs(ref) <= 1e-3] or mixed
+    ok = [f for f in mixed if res[f].get("within_0.1pct_all_seeds", True)] or mixed
     head = max(ok, key=lambda f: res[f]["value"])
     h = res[head]
     achieved = flops / (h["step_kernel_ms"] * 1e-3) / 1e12
     traffic = read_traffic(head, q.n, args.B)
-    roof = dict(bound="mfma", kernel=f"dense_gemm<{head}, STEP>", achieved=achieved,
+    roof = dict(bound="mfma", kernel=f"dense_gemm_dma<{head}, STEP>", achieved=achieved,
                 peak=PEAK_TFLOPS[head], unit="TFLOP/s", frac=achieved / PEAK_TFLOPS[head],
                 traffic=traffic, flop_per_launch=flops,
-                avg_launch_ms=h["step_kernel_ms"], launches=h["launches"],
+                avg_launch_ms=h["step_kernel_ms"], launches_timed=h["step_launches_timed"],
                 launches_timed_every=args.time_stride,
+                window=f"one whole run of T={args.T} iterations from x0 (transient included)",
                 note="int8 multiply-adds count as 2 operations against the 5.0 POP/s int8 peak"
                      if head == "i8" else "")
-    # Past the transient after init (64 iterations) the evaluation GEMM does
-    # not run; the incremental kernel evaluates every restart exactly.  No
-    # roofline fraction applies to either; their launch times are reported.
+    # Past the transient (64 iterations) the evaluation GEMM does not run; the
+    # incremental kernel evaluates every restart exactly.  No roofline fraction
+    # applies to either; their launch times are reported.
     ev = dict(kernel="eval_incr_kernel", incremental_kernel_ms=h["eval_incr_kernel_ms"],
               eval_gemm_launches=h["eval_launches"], eval_gemm_ms=h["eval_kernel_ms"],
-              note="steady state: exact objectives from the recorded rounding changes; the int8 "
-                   "evaluation GEMM runs only in the first 64 iterations after init")
-    line = dict(metric=METRIC, value=h["value"], unit=UNIT, n_gpus=1, steps=args.steps,
-                warmup=args.warmup, ms_per_step=h["ms_per_step"], higher_is_better=True,
+              note="past the transient: exact objectives from the recorded rounding changes; the "
+                   "int8 evaluation GEMM runs only in the first 64 iterations after init")
+    line = dict(metric=METRIC, value=h["value"], unit=UNIT, n_gpus=1, steps=args.T,
+                warmup=args.T, ms_per_step=h["ms_per_step"], higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype=head, data="synthetic",
                 config=dict(workload=f"dense QUBO n={q.n}, Q sym U{{-100..100}}, c U{{-100..100}}, "
-                                     f"B={args.B}, quality run T={args.T}",
+                                     f"B={args.B}, T={args.T}",
                             n=q.n, B=args.B, T=args.T, scale=s, precision=head,
                             g="x^2-x", y0=6.0, alpha=0.025, beta=0.025, delta=2 ** -7),
+                timing=(f"value = median over {args.seeds} seeds of B*T/t_loop, t_loop from HIP events "
+                        f"around a whole run of T={args.T} iterations (after one untimed warm-up run); "
+                        f"ms_per_step = median t_loop / T; steps and warmup are the timed run's T and "
+                        f"the warm-up run's T; the --steps/--warmup window is steady_state"),
+                steady_state=h["steady_state"],
                 forms=res, roofline=roof, evaluation=ev)
     if "fp32" in res and head != "fp32":
         f32 = res["fp32"]
         line["speedup_vs_fp32"] = h["value"] / f32["value"]
-        if not args.no_quality and f32.get("best_at_1s") is not None and h.get("best_at_1s") is not None:
+        line["rel_gap_best_at_T_vs_fp32"] = h["rel_gap_best_at_T_vs_fp32"]
+        if f32.get("best_at_1s") is not None and h.get("best_at_1s") is not None:
             line["rel_gap_best_at_1s_vs_fp32"] = (h["best_at_1s"] - f32["best_at_1s"]) / abs(f32["best_at_1s"])
-            line["rel_gap_best_at_T_vs_fp32"] = (h["best_at_T"] - f32["best_at_T"]) / abs(f32["best_at_T"])
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(q, s, x0, args)
+        line["cpu_baseline"] = cpu_baseline(q, s, x0s[0], args)
     print(json.dumps(line), flush=True)
 
 

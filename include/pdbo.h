@@ -5,9 +5,9 @@
  * (Eq. 1) by running Algorithm 1 - simultaneous projected gradient
  * descent-ascent on the Lagrangian L(x,y) = f(x) + sum_i y_i g(x_i), with a
  * perturbation away from 1/2 - from B independent starting points at once, and
- * keeping the best rounded solution over all restarts (Sec. 5.2, Model
+ * keeping the best rounded solution over all restarts (Sec. 4.2, Model
  * Settings).  f is the multilinear extension of F (Def. 2.2; closed form by
- * Prop. 2.2) and g a binarity constraint function (Sec. 3.1).
+ * Prop. 2.4) and g a binarity constraint function (Sec. 3.1).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -61,7 +61,7 @@ enum { PDBO_FP32 = 0, PDBO_BF16 = 1, PDBO_FP8 = 2, PDBO_I8 = 3 };
  * QUBO instance (Eq. 1 with quadratic F): minimise F(x) = x^T Q x + c^T x over
  * x in {0,1}^n.  Q may be asymmetric and may have a diagonal; the library works
  * on the multilinear extension f(x) = 1/2 x^T A x + c'^T x with
- * A = offdiag(Q + Q^T), c' = c + diag(Q) (Prop. 2.2), which equals F on {0,1}^n.
+ * A = offdiag(Q + Q^T), c' = c + diag(Q) (Prop. 2.4), which equals F on {0,1}^n.
  *   format == PDBO_DENSE: q points to n*n int32, row-major (Q_ij at q[i*n+j]).
  *   format == PDBO_CSR:   row_ptr[n+1], col_idx[nnz], q = values[nnz] (int32),
  *                         rows sorted by column, no duplicate (i,j) in a row.
@@ -79,7 +79,7 @@ typedef struct {
 } pdbo_qubo;
 
 /*
- * Weighted Max-k-SAT (Sec. 5.1, Max-k-SAT): minimise the total weight of the
+ * Weighted Max-k-SAT (Sec. 4.1, Max-k-SAT): minimise the total weight of the
  * unsatisfied clauses.  lits holds m*k int32 literals, clause j in
  * lits[j*k .. j*k+k), DIMACS convention: +v is x_v, -v is not x_v, v in 1..n;
  * the k variables of a clause must be distinct.  w: m clause weights in
@@ -147,7 +147,7 @@ typedef struct {
 
 /* ---- QUBO (dense MFMA path or CSR persistent path) ------------------------ */
 
-/* Validates, canonicalises (Prop. 2.2) and uploads the instance, sets
+/* Validates, canonicalises (Prop. 2.4) and uploads the instance, sets
  * X^0 = x0 and Y^0 = y0 (Alg. 1 input), and returns a context.  EINVAL for any
  * contract violation (checked before any HIP call); ERANGE when the exact
  * int64 evaluation cannot be guaranteed (|Q_ij| >= 2^30, or a row of |A| or
@@ -172,6 +172,13 @@ PDBO_API pdbo_status qubo_gda_get_state(pdbo_ctx* ctx, float* x, float* y, int64
 /* Replaces the iterate (host (B, n) float32, x in [0,1]) and the iteration
  * count t >= 0; the incumbent is kept.  Synchronises. */
 PDBO_API pdbo_status qubo_gda_set_state(pdbo_ctx* ctx, const float* x, const float* y, int64_t t);
+
+/* Starts the run over on the same instance and parameters: X^0 = x0 (HOST
+ * (B, n) float64 in [0,1]), Y^0 = y0, t = 0, incumbent, trace and time origin
+ * cleared (Alg. 1 input), without uploading the instance again.  Not for
+ * batched contexts (ESTATE).  EINVAL when x0 is NULL or outside [0,1].
+ * Synchronises. */
+PDBO_API pdbo_status qubo_gda_restart(pdbo_ctx* ctx, const double* x0);
 
 /* Exact objectives (host int64[B]) of the rounded iterate evaluated last. */
 PDBO_API pdbo_status qubo_gda_objectives(pdbo_ctx* ctx, int64_t* F);
@@ -214,7 +221,7 @@ PDBO_API pdbo_status maxsat_gda_solve(const pdbo_maxsat* prob, const pdbo_params
                              void* stream, pdbo_result* result);
 
 /* Lagrangian of a MaxSAT context for nb restarts given as DEVICE arrays:
- * L[b] = f(x_b)/s + sum_i y_bi g(x_bi)  (Sec. 3.1; f as in Sec. 5.1).
+ * L[b] = f(x_b)/s + sum_i y_bi g(x_bi)  (Sec. 3.1; f as in Sec. 4.1).
  * x, y: device (nb, n) float32 (x in [0,1]); L: device float32[nb].
  * Enqueued on `stream` (hipStream_t); asynchronous. */
 PDBO_API pdbo_status maxsat_lagrangian_fwd(pdbo_ctx* ctx, const float* x, const float* y, int32_t nb,
@@ -280,6 +287,18 @@ PDBO_API pdbo_status pdbo_timing_stride(pdbo_ctx* ctx, int32_t stride);
 /* Accumulated device time (ms) and launch count of kernel class `which`
  * (PDBO_K_*) since timing was enabled.  Synchronises. */
 PDBO_API pdbo_status pdbo_kernel_time(pdbo_ctx* ctx, int32_t which, double* total_ms, int64_t* launches);
+
+/* The dense tile autotuner's cache, a JSON object of "key": cfg lines in
+ * $PDBO_AUTOTUNE_CACHE (default $HOME/.cache/pdbo_autotune.json).  A context
+ * whose tile is chosen automatically looks its key up there and, when absent,
+ * times every configuration and stores the fastest.  pdbo_autotune_store sets
+ * `key` to tile configuration `cfg` (0-based; the params' `tile` is cfg + 1),
+ * creating missing directories of the path; pdbo_autotune_lookup writes the
+ * cached configuration to *cfg, or -1 when there is none.  Keys are at most
+ * 399 printable bytes without '"' or '\'.  EINVAL for a bad key or
+ * configuration, or when the cache cannot be written.  No device work. */
+PDBO_API pdbo_status pdbo_autotune_store(const char* key, int32_t cfg);
+PDBO_API pdbo_status pdbo_autotune_lookup(const char* key, int32_t* cfg);
 
 /* Name of the tile configuration the dense path uses (static string). */
 PDBO_API const char* pdbo_tile_name(const pdbo_ctx* ctx);

@@ -10,19 +10,23 @@ pre/post-processing); the only common inputs come from the seeded generators in
 Modules
 -------
 ``qubo``       exact QUBO objective, canonical multilinear extension and its
-               gradient (Eq. 1, Def. 2.2, Prop. 2.2)
+               gradient (Eq. 1, Def. 2.2, Prop. 2.4)
 ``maxsat``     weighted Max-k-SAT objective, multilinear extension and gradient
-               (Sec. 5.1 Max-k-SAT)
+               (Sec. 4.1 Max-k-SAT)
 ``binarity``   the constraint functions g and their derivatives (Sec. 3.1)
 ``gda``        Algorithm 1 (PDBO) over B independent restarts, keeping the best
-               rounded solution (Sec. 5.2 Model Settings)
+               rounded solution (Sec. 4.2 Model Settings)
 ``enumerate``  brute force over {0,1}^n and the multilinear extension by its
                definition (Def. 2.2), for small n
-``bounds``     the dual lower bound of Prop. 4.1 and the telescoping identity in
-               the proof of Thm. 4.2
+``bounds``     the dual lower bound of Prop. 3.3 and the telescoping identity in
+               the proof of Thm. 3.7
 
 Every function works in float64 (objectives of integer instances in int64).
-Parity is pinned for every function by the CPU tests under ``tests/`` (see
-``test_oracle_*.py``); none is "parity unpinned".
+Each function is pinned by a CPU test under ``tests/`` against something other
+than itself: plain-loop and brute-force definitions, the paper's worked
+examples and identities, hand-worked golden values under ``tests/golden/``,
+closed forms, exact finite or complex-step differences, and library routines
+(numpy.polynomial, numpy's Philox).  Which test pins which function is listed
+in the design notes; no function here is "parity unpinned".
 """
 from . import binarity, bounds, enumerate, gda, maxsat, qubo  # noqa: F401

@@ -2,8 +2,8 @@
 
 The paper requires g to be convex and continuous on [0,1] with g(0)=g(1)=0,
 differentiable on (0,1) with g'(x)=0 only at x=1/2, and symmetric about 1/2.
-It names three choices: the quadratic x^2 - x (its default, Sec. 5.2 Model
-Settings, and the Max-Cut example of Sec. 4.1), the entropy
+It names three choices: the quadratic x^2 - x (its default, Sec. 4.2 Model
+Settings, and the Max-Cut example of Sec. 3.2.1), the entropy
 x log x + (1-x) log(1-x) extended continuously to the end points (used for
 Max-k-SAT), and the even-degree polynomial (2x-1)^(2d) - 1.
 

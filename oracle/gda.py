@@ -1,14 +1,14 @@
 """Algorithm 1 (PDBO): simultaneous projected gradient descent-ascent on
 L(x, y) = f(x) + sum_i y_i g(x_i), with the perturbation away from 1/2.
 
-For every coordinate i, from (x^t, y^t) (Alg. 1; Eq. 5):
+For every coordinate i, from (x^t, y^t) (Alg. 1; Eq. 6):
   * if |x_i - 1/2| <= delta and |dL/dx_i| <= 2 delta and y_i <= 0, x_i moves to
     1/2 - delta when x_i <= 1/2 and to 1/2 + delta otherwise;
   * else x_i takes the projected gradient step clip(x_i - alpha dL/dx_i, 0, 1);
   * in both cases y_i gains beta g(x_i^t), evaluated at the OLD x (the update is
     simultaneous).
 B independent restarts run side by side and the best rounded solution over all
-restarts is retained (Sec. 5.2 Model Settings).
+restarts is retained (Sec. 4.2 Model Settings).
 
 Readings where the paper is silent:
   * rounding: x_r = [x > 1/2] (ties go to 0, like the x <= 1/2 branch);

@@ -1,4 +1,4 @@
-"""Weighted Max-k-SAT as binary optimisation (Sec. 5.1, Max-k-SAT).
+"""Weighted Max-k-SAT as binary optimisation (Sec. 4.1, Max-k-SAT).
 
 A clause C_j is a set of literals; x_v = 1 means variable v is true.  With
 p(x) = x for a negated literal and p(x) = 1 - x for a plain one, the product
@@ -8,7 +8,7 @@ of unsatisfied clauses; this build weights clause j by w_j (reading), so
 
     F(x) = sum_j w_j [C_j unsatisfied],   f(x) = sum_j w_j prod_{l in C_j} p(x_l),
 
-and by Prop. 2.2 this f is already the multilinear extension of F (the k
+and by Prop. 2.4 this f is already the multilinear extension of F (the k
 variables of a clause are distinct).
 
 Literals use the DIMACS convention: +v is x_v, -v is not x_v, v is 1-based.

@@ -3,7 +3,7 @@
 Problem (Eq. 1 with a quadratic F): minimise F(x) = sum_ij Q_ij x_i x_j +
 sum_i c_i x_i over x in {0,1}^n.  Q may be asymmetric and may carry a diagonal.
 
-Canonical form (Prop. 2.2): on binary points x_i^2 = x_i, so the multilinear
+Canonical form (Prop. 2.4): on binary points x_i^2 = x_i, so the multilinear
 extension drops the exponent of every diagonal term:
     f(x) = sum_{i != j} Q_ij x_i x_j + sum_i (c_i + Q_ii) x_i
          = 1/2 x^T A x + c'^T x,   A = offdiag(Q + Q^T),  c' = c + diag(Q).
@@ -44,7 +44,7 @@ def _c(q) -> np.ndarray:
 
 
 def canonicalize(q):
-    """(A, c') of Prop. 2.2: A = offdiag(Q + Q^T) (dense ndarray or scipy CSR,
+    """(A, c') of Prop. 2.4: A = offdiag(Q + Q^T) (dense ndarray or scipy CSR,
     float64) and c' = c + diag(Q) (float64)."""
     if q.Q is not None:
         Qf = q.Q.astype(np.float64)
@@ -98,7 +98,7 @@ def objective_fsum(Q, c, x) -> float:
 
 
 def f_multilinear(A, cp, X) -> np.ndarray:
-    """f(x) = 1/2 x^T A x + c'^T x for each row of X (Prop. 2.2)."""
+    """f(x) = 1/2 x^T A x + c'^T x for each row of X (Prop. 2.4)."""
     X = np.atleast_2d(np.asarray(X, dtype=np.float64))
     AX = (A @ X.T).T
     return 0.5 * np.sum(AX * X, axis=1) + X @ cp
@@ -129,7 +129,7 @@ class QuboProblem:
         return f_multilinear(self.A, self.cp, X) / self.s
 
     def theta_upper(self) -> float:
-        """Upper bound on max over the box of ||grad(f/s)||_1 (used by Prop. 4.1)."""
+        """Upper bound on max over the box of ||grad(f/s)||_1 (used by Prop. 3.3)."""
         absA = abs(self.A)
         rows = np.asarray(absA.sum(axis=1)).ravel()
         return float(np.sum(rows + np.abs(self.cp)) / self.s)

@@ -25,7 +25,7 @@ from ._abi import (PDBO_BF16, PDBO_CSR, PDBO_DENSE, PDBO_FP8, PDBO_FP32, PDBO_G_
 
 __all__ = [
     "load", "PdboError", "Context", "qubo_gda_init", "qubo_gda_step", "qubo_gda_result",
-    "qubo_gda_get_state", "qubo_gda_set_state", "qubo_gda_objectives", "qubo_gda_grad",
+    "qubo_gda_get_state", "qubo_gda_set_state", "qubo_gda_restart", "qubo_gda_objectives", "qubo_gda_grad",
     "qubo_gda_eval", "qubo_gda_trace", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
     "qubo_gda_batch_solve", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
     "maxsat_gda_solve", "maxsat_lagrangian_fwd", "maxsat_lagrangian_bwd", "MaxSATLagrangian",
@@ -143,6 +143,9 @@ class Context:
     def objectives(self):
         return qubo_gda_objectives(self)
 
+    def restart(self, x0):
+        return qubo_gda_restart(self, x0)
+
     def grad(self, x):
         return qubo_gda_grad(self, x)
 
@@ -209,6 +212,13 @@ def qubo_gda_set_state(ctx: Context, x=None, y=None, t=0):
     xa = None if x is None else np.ascontiguousarray(x, dtype=np.float32)
     ya = None if y is None else np.ascontiguousarray(y, dtype=np.float32)
     check(load().qubo_gda_set_state(ctx.h, _ptr(xa), _ptr(ya), int(t)), ctx.h)
+
+
+def qubo_gda_restart(ctx: Context, x0):
+    xa = np.ascontiguousarray(x0, dtype=np.float64)
+    if xa.shape != (ctx.B, ctx.n):
+        raise ValueError(f"x0 must have shape {(ctx.B, ctx.n)}")
+    check(load().qubo_gda_restart(ctx.h, _ptr(xa)), ctx.h)
 
 
 def qubo_gda_objectives(ctx: Context) -> np.ndarray:

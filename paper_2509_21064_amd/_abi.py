@@ -50,6 +50,7 @@ SIGNATURES = {
     "qubo_gda_result": (_st, [_ctx, POINTER(pdbo_result)]),
     "qubo_gda_get_state": (_st, [_ctx, c_void_p, c_void_p, POINTER(c_int64)]),
     "qubo_gda_set_state": (_st, [_ctx, c_void_p, c_void_p, c_int64]),
+    "qubo_gda_restart": (_st, [_ctx, c_void_p]),
     "qubo_gda_objectives": (_st, [_ctx, c_void_p]),
     "qubo_gda_grad": (_st, [_ctx, c_void_p, c_void_p]),
     "qubo_gda_eval": (_st, [_ctx, c_void_p, c_int32, c_void_p]),
@@ -75,6 +76,8 @@ SIGNATURES = {
     "pdbo_timing_stride": (_st, [_ctx, c_int32]),
     "pdbo_kernel_time": (_st, [_ctx, c_int32, POINTER(c_double), POINTER(c_int64)]),
     "pdbo_tile_name": (c_char_p, [_ctx]),
+    "pdbo_autotune_store": (_st, [c_char_p, c_int32]),
+    "pdbo_autotune_lookup": (_st, [c_char_p, POINTER(c_int32)]),
     "pdbo_destroy": (None, [_ctx]),
     "pdbo_status_str": (c_char_p, [c_int32]),
     "pdbo_last_error": (c_char_p, [_ctx]),

@@ -1,7 +1,7 @@
 // Host side of libpdbo: the extern "C" entry points declared in pdbo.h.
 //
 // Validation happens before any HIP call, so contract violations return
-// PDBO_EINVAL on any machine.  Canonicalisation follows Prop. 2.2: on binary
+// PDBO_EINVAL on any machine.  Canonicalisation follows Prop. 2.4: on binary
 // points x_i^2 = x_i, so the multilinear extension of x^T Q x + c^T x is
 // 1/2 x^T A x + c'^T x with A = offdiag(Q + Q^T) and c' = c + diag(Q).  A is
 // stored as Ahat = A / kappa with kappa = 2 when every entry of A is even (always
@@ -9,6 +9,9 @@
 // is F = (kappa/2) x^T Ahat x + c'^T x and the gradient of f/s is
 // (kappa/s) Ahat x + c'/s.
 #include <algorithm>
+#include <sys/stat.h>
+
+#include <cerrno>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -698,13 +701,16 @@ pdbo_status upload_dense_tables(pdbo_ctx* c) {
 
 // ---------------------------------------------------------------- autotuner
 //
-// Times the GRAD variant of the dense GEMM (the same main loop as the step)
-// for every tile configuration on the context's own operands and keeps the
-// fastest.  Every output element is accumulated along K in the same order
-// whatever the tile shape, so the choice never changes results.  Choices are
-// cached as a flat JSON object {"key": cfg, ...} in $PDBO_AUTOTUNE_CACHE
-// (default $HOME/.cache/pdbo_autotune.json), keyed by architecture, operand
-// type, B, instance count and the instance sizes.
+// Times the STEP variant of the dense GEMM (main loop and the Alg. 1
+// epilogue, as the iterations launch it) for every tile configuration on
+// scratch copies of the context's iterate, so the timing launches leave the
+// state untouched, and keeps the fastest.  Every output element is accumulated
+// along K in the same order whatever the tile shape, so the choice never
+// changes results.  Choices are cached as a flat JSON object {"key": cfg, ...}
+// in $PDBO_AUTOTUNE_CACHE (default $HOME/.cache/pdbo_autotune.json), keyed by
+// architecture, operand type, B, instance count and the instance sizes.  The
+// cache directory is created with mkdir(2), one path component at a time; the
+// library starts no child process.
 
 std::string autotune_key(const pdbo_ctx* c) {
   int dev = 0;
@@ -721,8 +727,9 @@ std::string autotune_key(const pdbo_ctx* c) {
     nmax = std::max(nmax, I.n);
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s/p%d/B%d/k%zu/nmax%d/nsum%lld", arch.c_str(), c->prec, c->B,
-                c->insts_h.size(), (nmax + 63) / 64 * 64, (nsum + 1023) / 1024 * 1024);
+  std::snprintf(buf, sizeof(buf), "%s/p%d/g%d/B%d/k%zu/nmax%d/nsum%lld", arch.c_str(), c->prec,
+                c->par.g_kind, c->B, c->insts_h.size(), (nmax + 63) / 64 * 64,
+                (nsum + 1023) / 1024 * 1024);
   return buf;
 }
 
@@ -733,51 +740,94 @@ std::string autotune_path() {
   return std::string(h ? h : "/tmp") + "/.cache/pdbo_autotune.json";
 }
 
-std::mutex g_tune_mu;
-
-int autotune_lookup(const std::string& key) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  FILE* f = std::fopen(autotune_path().c_str(), "r");
-  if (!f) return -1;
-  char line[512];
-  int found = -1;
-  while (std::fgets(line, sizeof(line), f)) {
-    char k[400];
-    int v;
-    if (std::sscanf(line, " \"%399[^\"]\" : %d", k, &v) == 2 && key == k) found = v;
-  }
-  std::fclose(f);
-  return found;
+// Keys are written between double quotes, one entry per line.
+bool autotune_key_ok(const std::string& k) {
+  if (k.empty() || k.size() >= 400) return false;
+  for (char ch : k)
+    if (ch == '"' || ch == '\\' || (unsigned char)ch < 0x20) return false;
+  return true;
 }
 
-void autotune_store(const std::string& key, int cfg) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  const std::string path = autotune_path();
+// mkdir -p without a shell: every prefix of `dir` ending before a '/'.
+bool make_dirs(const std::string& dir) {
+  for (size_t pos = 1; pos <= dir.size(); ++pos) {
+    if (pos < dir.size() && dir[pos] != '/') continue;
+    const std::string part = dir.substr(0, pos);
+    struct stat sb;
+    if (::stat(part.c_str(), &sb) == 0) {
+      if (!S_ISDIR(sb.st_mode)) return false;
+      continue;
+    }
+    if (::mkdir(part.c_str(), 0755) != 0 && errno != EEXIST) return false;
+  }
+  return true;
+}
+
+std::mutex g_tune_mu;
+
+std::vector<std::pair<std::string, int>> autotune_read(const std::string& path) {
   std::vector<std::pair<std::string, int>> ent;
   if (FILE* f = std::fopen(path.c_str(), "r")) {
     char line[512];
     while (std::fgets(line, sizeof(line), f)) {
       char k[400];
       int v;
-      if (std::sscanf(line, " \"%399[^\"]\" : %d", k, &v) == 2 && key != k) ent.emplace_back(k, v);
+      if (std::sscanf(line, " \"%399[^\"]\" : %d", k, &v) == 2) ent.emplace_back(k, v);
     }
     std::fclose(f);
   }
+  return ent;
+}
+
+int autotune_lookup(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int found = -1;
+  for (const auto& e : autotune_read(autotune_path()))
+    if (e.first == key) found = e.second;
+  return found;
+}
+
+// Rewrites the cache with `key` set to `cfg` (through a temporary file renamed
+// over the old one).  Returns false when the file cannot be written.
+bool autotune_store(const std::string& key, int cfg) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const std::string path = autotune_path();
+  std::vector<std::pair<std::string, int>> ent;
+  for (const auto& e : autotune_read(path))
+    if (e.first != key) ent.push_back(e);
   ent.emplace_back(key, cfg);
   const size_t slash = path.rfind('/');
-  if (slash != std::string::npos) {
-    const std::string dir = path.substr(0, slash);
-    (void)std::system(("mkdir -p '" + dir + "' 2>/dev/null").c_str());
-  }
-  if (FILE* f = std::fopen(path.c_str(), "w")) {
-    std::fprintf(f, "{\n");
-    for (size_t i = 0; i < ent.size(); ++i)
-      std::fprintf(f, "  \"%s\": %d%s\n", ent[i].first.c_str(), ent[i].second,
-                   i + 1 < ent.size() ? "," : "");
-    std::fprintf(f, "}\n");
-    std::fclose(f);
-  }
+  if (slash != std::string::npos && slash > 0 && !make_dirs(path.substr(0, slash))) return false;
+  const std::string tmp = path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < ent.size(); ++i)
+    std::fprintf(f, "  \"%s\": %d%s\n", ent[i].first.c_str(), ent[i].second,
+                 i + 1 < ent.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path.c_str()) == 0;
 }
+
+// Device buffers and events of the timing runs, released on every exit path.
+struct TuneScratch {
+  std::vector<void*> bufs;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~TuneScratch() {
+    for (void* p : bufs) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 16));
+    if (e == hipSuccess) bufs.push_back(q);
+    *p = (T*)q;
+    return e;
+  }
+};
 
 pdbo_status upload_dense_tables(pdbo_ctx* c);
 
@@ -788,52 +838,83 @@ pdbo_status autotune_dense(pdbo_ctx* c) {
     c->cfg = cached;
     return PDBO_OK;
   }
-  // gradient outputs for the timing launches, freed on return
-  std::vector<TempDev> gbuf(c->insts_h.size());
-  for (size_t k = 0; k < c->insts_h.size(); ++k) {
-    InstDev& I = c->insts_h[k];
-    HIPCHK(c, hipMalloc(&gbuf[k].p, (size_t)I.B * I.ld * sizeof(float)));
-    I.G = (float*)gbuf[k].p;
+  // Scratch copies of everything the step writes: x (both buffers for FP32,
+  // whose operand is x itself), y, the operand shadows and x_r.  The rounding
+  // changes are not recorded (nflip = nullptr) and no best of B runs.
+  TuneScratch ts;
+  std::vector<InstDev> tune = c->insts_h;
+  const int EB = element_bytes(c->prec);
+  for (InstDev& I : tune) {
+    const size_t sz = (size_t)I.B * I.ld;
+    float *x0 = nullptr, *x1 = nullptr, *y = nullptr;
+    uint8_t *s0 = nullptr, *s1 = nullptr;
+    int8_t* xr = nullptr;
+    HIPCHK(c, ts.alloc(&x0, sz));
+    HIPCHK(c, ts.alloc(&y, sz));
+    HIPCHK(c, ts.alloc(&xr, sz));
+    HIPCHK(c, hipMemcpyAsync(x0, I.X[c->parity], sz * 4, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(y, I.Y, sz * 4, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(xr, I.Xr, sz, hipMemcpyDeviceToDevice, c->stream));
+    if (c->prec == PDBO_FP32) {
+      HIPCHK(c, ts.alloc(&x1, sz));
+      HIPCHK(c, hipMemcpyAsync(x1, x0, sz * 4, hipMemcpyDeviceToDevice, c->stream));
+      I.X[c->parity] = x0;
+      I.X[c->parity ^ 1] = x1;
+      I.Xs[c->parity] = (uint8_t*)x0;
+      I.Xs[c->parity ^ 1] = (uint8_t*)x1;
+    } else {
+      HIPCHK(c, ts.alloc(&s0, sz * EB));
+      HIPCHK(c, ts.alloc(&s1, sz * EB));
+      HIPCHK(c, hipMemcpyAsync(s0, I.Xs[c->parity], sz * EB, hipMemcpyDeviceToDevice, c->stream));
+      I.X[0] = I.X[1] = x0;
+      I.Xs[c->parity] = s0;
+      I.Xs[c->parity ^ 1] = s1;
+    }
+    I.Y = y;
+    I.Xr = xr;
+    I.nflip = nullptr;
+    I.fbits = nullptr;
   }
-  hipEvent_t e0, e1;
-  HIPCHK(c, hipEventCreate(&e0));
-  HIPCHK(c, hipEventCreate(&e1));
-  int best = c->cfg;
+  InstDev* idv = nullptr;
+  HIPCHK(c, ts.alloc(&idv, tune.size()));
+  HIPCHK(c, hipEventCreate(&ts.e0));
+  HIPCHK(c, hipEventCreate(&ts.e1));
+  const int cfg0 = c->cfg;
+  int best = cfg0;
   float best_ms = 1e30f;
   for (int id = 0; id < dense_num_cfgs(); ++id) {
     c->cfg = id;
     build_tiles(c);
+    for (size_t k = 0; k < tune.size(); ++k) tune[k].mblocks = c->insts_h[k].mblocks;
     TileDev* td = nullptr;
-    InstDev* idv = nullptr;
-    TempDev ttd, tid;
-    HIPCHK(c, hipMalloc(&ttd.p, c->tiles_h.size() * sizeof(TileDev)));
-    HIPCHK(c, hipMalloc(&tid.p, c->insts_h.size() * sizeof(InstDev)));
-    td = (TileDev*)ttd.p;
-    idv = (InstDev*)tid.p;
+    HIPCHK(c, ts.alloc(&td, c->tiles_h.size()));
     HIPCHK(c, hipMemcpyAsync(td, c->tiles_h.data(), c->tiles_h.size() * sizeof(TileDev),
                              hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(idv, c->insts_h.data(), c->insts_h.size() * sizeof(InstDev),
-                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(idv, tune.data(), tune.size() * sizeof(InstDev), hipMemcpyHostToDevice,
+                             c->stream));
     const int nt = (int)c->tiles_h.size();
-    HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_GRAD, 0, td, nt, idv, c->parity, 0, c->stream));
-    HIPCHK(c, hipEventRecord(e0, c->stream));
+    // one untimed launch (first use of the kernel), then three timed ones; the
+    // scratch iterate advances from launch to launch as in a run
+    int par = c->parity;
+    HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_STEP, c->par.g_kind, td, nt, idv, par, 0, c->stream));
+    par ^= 1;
+    HIPCHK(c, hipEventRecord(ts.e0, c->stream));
     constexpr int reps = 3;
-    for (int r = 0; r < reps; ++r)
-      HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_GRAD, 0, td, nt, idv, c->parity, 0, c->stream));
-    HIPCHK(c, hipEventRecord(e1, c->stream));
-    HIPCHK(c, hipEventSynchronize(e1));
+    for (int r = 0; r < reps; ++r, par ^= 1)
+      HIPCHK(c, launch_dense_gemm(id, c->prec, EPI_STEP, c->par.g_kind, td, nt, idv, par, 0,
+                                  c->stream));
+    HIPCHK(c, hipEventRecord(ts.e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(ts.e1));
     float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    HIPCHK(c, hipEventElapsedTime(&ms, ts.e0, ts.e1));
     if (ms < best_ms) {
       best_ms = ms;
       best = id;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  for (InstDev& I : c->insts_h) I.G = nullptr;
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // before the scratch buffers are freed
   c->cfg = best;
-  autotune_store(key, best);
+  (void)autotune_store(key, best);  // an unwritable cache only costs a re-tune next time
   return PDBO_OK;
 }
 
@@ -1350,6 +1431,57 @@ pdbo_status qubo_gda_set_state(pdbo_ctx* c, const float* x, const float* y, int6
   return PDBO_OK;
 }
 
+pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
+  if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
+  if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (!x0) return fail(c, PDBO_EINVAL, "x0 is NULL");
+  const int n = c->n_of[0], B = c->B;
+  const size_t tot = (size_t)B * n;
+  for (size_t i = 0; i < tot; ++i)
+    if (!(x0[i] >= 0.0 && x0[i] <= 1.0)) return fail(c, PDBO_EINVAL, "x0 must lie in [0,1]");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  TempDev t;
+  STCHK(temp_upload(c, t, x0, tot * sizeof(double)));
+  const float y0 = (float)c->par.y0;
+  Incumbent init{kI64Max, -1, -1, 0};
+  if (c->kind == 0) {
+    InstDev& I = c->insts_h[0];
+    c->parity = 0;
+    HIPCHK(c, launch_init_state((const double*)t.p, B, n, I.ld, y0, I.X[0], I.Y,
+                                c->prec == PDBO_FP32 ? nullptr : I.Xs[0], c->prec, I.Xr, c->stream));
+    const int64_t zero = 0;
+    HIPCHK(c, hipMemcpyAsync(I.t_dev, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(I.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_fill_i32(I.trace_len, 0, 1, c->stream));
+    HIPCHK(c, launch_fill_i64(I.Sacc, 0, (size_t)B, c->stream));
+    HIPCHK(c, launch_fill_i64(I.Cacc, 0, (size_t)B, c->stream));
+    if (I.nflip) {
+      // the first evaluation is a full product; the change bitmap starts clear
+      HIPCHK(c, launch_fill_i32(I.nflip, kFlipMax + 1, B, c->stream));
+      HIPCHK(c, launch_fill_i32((int32_t*)I.fbits, 0, (int64_t)B * (I.ld / 32), c->stream));
+    }
+    c->argmin_pending = false;
+  } else {
+    float* X = c->kind == 1 ? c->csr.X : c->sat.X;
+    float* Y = c->kind == 1 ? c->csr.Y : c->sat.Y;
+    const int ld = c->kind == 1 ? c->csr.ld : c->sat.ld;
+    int64_t* rbF = c->kind == 1 ? c->csr.rbestF : c->sat.rbestF;
+    int64_t* rbT = c->kind == 1 ? c->csr.rbestT : c->sat.rbestT;
+    HIPCHK(c, launch_init_state((const double*)t.p, B, n, ld, y0, X, Y, nullptr, P_F32, nullptr,
+                                c->stream));
+    HIPCHK(c, launch_fill_i64(rbF, kI64Max, B, c->stream));
+    HIPCHK(c, launch_fill_i64(rbT, kI64Max, B, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->inc_d, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+  }
+  // the time origin is the first step after the restart
+  HIPCHK(c, launch_fill_i64((int64_t*)c->ts0_d, 0, 1, c->stream));
+  c->stamped = false;
+  c->t_host = 0;
+  c->full_until = full_eval_iters();
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PDBO_OK;
+}
+
 pdbo_status qubo_gda_objectives(pdbo_ctx* c, int64_t* F) {
   if (!c || !F) return fail(c, PDBO_EINVAL, "NULL argument");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
@@ -1711,6 +1843,20 @@ pdbo_status pdbo_timing_stride(pdbo_ctx* c, int32_t stride) {
     c->tseen[k] = 0;
   }
   c->tstride = stride;
+  return PDBO_OK;
+}
+
+pdbo_status pdbo_autotune_store(const char* key, int32_t cfg) {
+  if (!key || !autotune_key_ok(key)) return fail(nullptr, PDBO_EINVAL, "bad autotune key");
+  if (cfg < 0 || cfg >= dense_num_cfgs()) return fail(nullptr, PDBO_EINVAL, "unknown tile configuration");
+  if (!autotune_store(key, cfg))
+    return fail(nullptr, PDBO_EINVAL, "cannot write the autotune cache " + autotune_path());
+  return PDBO_OK;
+}
+
+pdbo_status pdbo_autotune_lookup(const char* key, int32_t* cfg) {
+  if (!key || !cfg || !autotune_key_ok(key)) return fail(nullptr, PDBO_EINVAL, "bad autotune key");
+  *cfg = autotune_lookup(key);
   return PDBO_OK;
 }
 

@@ -102,7 +102,7 @@ __device__ __forceinline__ float g_deriv(float x, int gkind) {
 }
 
 // One coordinate of Alg. 1: perturbation test, projected primal step and dual
-// ascent with g evaluated at the old x (simultaneous update, Eq. 5).
+// ascent with g evaluated at the old x (simultaneous update, Eq. 6).
 __device__ __forceinline__ void gda_update(float x, float y, float G, const GdaP& p,
                                            float& xn, float& yn) {
   float dL = fmaf(y, g_deriv(x, p.gkind), G);

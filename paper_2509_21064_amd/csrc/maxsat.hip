@@ -1,4 +1,4 @@
-// Weighted Max-k-SAT path (Sec. 5.1, Max-k-SAT; weighted clauses).
+// Weighted Max-k-SAT path (Sec. 4.1, Max-k-SAT; weighted clauses).
 //
 // f(x) = sum_j w_j prod_{l in C_j} p(x_l), p = x for a negated literal and
 // 1 - x otherwise; its partial derivative in x_i sums, over the occurrences of

@@ -1,6 +1,6 @@
 // Sparse QUBO path: a persistent, restart-resident kernel for CSR couplings.
 //
-// Restarts are independent (Sec. 5.2, Model Settings), so one workgroup owns
+// Restarts are independent (Sec. 4.2, Model Settings), so one workgroup owns
 // one restart for the whole launch: x of that restart lives in LDS (every row's
 // neighbours are gathered from there), y and the thread's own x in registers,
 // and when it fits the canonical CSR matrix Ahat = offdiag(Q + Q^T)/kappa is

@@ -41,3 +41,14 @@ def lockstep_compare(X, Y, G64, Xg, Yg, p, gtol_abs):
     dx = float(np.max(np.abs(Xg - Xn)[ok])) if ok.any() else 0.0
     dy = float(np.max(np.abs(Yg - Yn)))
     return dx, dy, int(amb.sum()), Xn, Yn
+
+
+# Coordinates excluded from a lockstep comparison are those whose branch of
+# Alg. 1 the gradient tolerance could flip; the count follows from the oracle
+# alone.  Measured on the lockstep cases: none for fp32, at most 0.31% for bf16
+# and i8, 2.6% for fp8 (3 mantissa bits), and 2 of 21 on the smallest case.
+AMB_FRAC = {"fp32": 0.001, "bf16": 0.005, "i8": 0.005, "fp8": 0.03}
+
+
+def amb_limit(prec, size):
+    return max(2, AMB_FRAC[prec] * size)

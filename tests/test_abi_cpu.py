@@ -179,3 +179,38 @@ def test_valid_input_without_gpu_reports_device_error(lib):
         pytest.skip("a GPU is visible")
     q, p, x0 = _base()
     assert _init(lib, q, p, x0) in (_abi.PDBO_EDEVICE, _abi.PDBO_ENOMEM)
+
+
+def test_autotune_cache_fresh_nested_directory(lib, tmp_path, monkeypatch):
+    """The autotuner's cache is written into directories that do not exist yet
+    (created with mkdir(2), no shell), and read back."""
+    path = tmp_path / "a" / "b c" / "d'e" / "tune.json"
+    monkeypatch.setenv("PDBO_AUTOTUNE_CACHE", str(path))
+    cfg = ctypes.c_int32(7)
+    assert lib.pdbo_autotune_lookup(b"gfx950/p3/B8/k1/nmax64/nsum1024", ctypes.byref(cfg)) == 0
+    assert cfg.value == -1
+    assert lib.pdbo_autotune_store(b"gfx950/p3/B8/k1/nmax64/nsum1024", 5) == 0
+    assert lib.pdbo_autotune_store(b"gfx950/p1/B8/k1/nmax64/nsum1024", 2) == 0
+    assert lib.pdbo_autotune_store(b"gfx950/p3/B8/k1/nmax64/nsum1024", 6) == 0
+    assert path.is_file()
+    import json
+    assert json.loads(path.read_text()) == {"gfx950/p1/B8/k1/nmax64/nsum1024": 2,
+                                            "gfx950/p3/B8/k1/nmax64/nsum1024": 6}
+    assert lib.pdbo_autotune_lookup(b"gfx950/p3/B8/k1/nmax64/nsum1024", ctypes.byref(cfg)) == 0
+    assert cfg.value == 6
+    # keys that would break the file format, and unknown configurations
+    assert lib.pdbo_autotune_store(b'bad"key', 1) == _abi.PDBO_EINVAL
+    assert lib.pdbo_autotune_store(b"ok", 99) == _abi.PDBO_EINVAL
+    # a path through a regular file cannot be created
+    monkeypatch.setenv("PDBO_AUTOTUNE_CACHE", str(tmp_path / "a" / "b c" / "d'e" / "tune.json" / "x.json"))
+    assert lib.pdbo_autotune_store(b"k", 1) == _abi.PDBO_EINVAL
+
+
+def test_library_starts_no_processes():
+    """The library builds no shell command lines and spawns nothing."""
+    csrc = os.path.join(ROOT, "paper_2509_21064_amd", "csrc")
+    for f in os.listdir(csrc):
+        txt = open(os.path.join(csrc, f)).read()
+        for pat in (r"\bsystem\s*\(", r"\bpopen\s*\(", r"\bfork\s*\(", r"\bexec[lv]p?e?\s*\(",
+                    r"posix_spawn"):
+            assert not re.search(pat, txt), (f, pat)

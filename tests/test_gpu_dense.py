@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import lockstep_compare, normwise, require_gpu, say
+from gpu_util import amb_limit, lockstep_compare, normwise, require_gpu, say
 from oracle import enumerate as en
 from oracle import gda
 from oracle import qubo as oq
@@ -95,7 +95,7 @@ def test_lockstep_iteration(name, prec):
     say(f"   max|dX|={dx:.3e} max|dY|={dy:.3e} excluded={namb}/{X.size}")
     assert dx <= p["alpha"] * gabs + 2e-6
     assert dy <= 2e-6 * (1 + np.max(np.abs(Y)))
-    assert namb <= 0.2 * X.size
+    assert namb <= amb_limit(prec, X.size)
     assert np.all((Xg >= 0) & (Xg <= 1))
     # P1: objectives of the rounded iterate, bit-exact
     F = ctx.objectives()
@@ -133,7 +133,7 @@ def test_lockstep_iteration_entropy_g(name, prec):
     say(f"   max|dX|={dx:.3e} max|dY|={dy:.3e} excluded={namb}/{X.size}")
     assert dx <= p["alpha"] * gabs + 2e-6
     assert dy <= 2e-6 * (1 + np.max(np.abs(Y)))
-    assert namb <= 0.2 * X.size
+    assert namb <= amb_limit(prec, X.size)
     assert np.all((Xg >= 0) & (Xg <= 1))
     F = ctx.objectives()
     assert np.array_equal(F, oq.objective(q, Xg > 0.5))

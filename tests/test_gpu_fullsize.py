@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import lockstep_compare, require_gpu, say
+from gpu_util import amb_limit, lockstep_compare, require_gpu, say
 from oracle import maxsat as om
 from oracle import qubo as oq
 
@@ -25,7 +25,7 @@ def c3():
     return q, s, x0, A, cp
 
 
-@pytest.mark.parametrize("prec", ["i8", "bf16", "fp32"])
+@pytest.mark.parametrize("prec", ["i8", "fp8", "bf16", "fp32"])
 def test_c3_dense_n10000_B1024(c3, prec):
     P = require_gpu()
     q, s, x0, A, cp = c3
@@ -55,6 +55,20 @@ def test_c3_dense_n10000_B1024(c3, prec):
     r = ctx.result()
     assert r["best_obj"] == F.min() and r["best_iter"] == 1 and r["best_restart"] == int(np.argmin(F))
     assert r["best_obj"] == oq.objective(q, r["best_x"][None])[0]
+    # two more iterations from the GPU's own iterate: these gradient products
+    # read the operand shadow the step epilogue wrote
+    for step in (2, 3):
+        Xs, Ys = Xg[SAMPLE].astype(np.float64), Yg[SAMPLE].astype(np.float64)
+        ctx.step(1)
+        Xg, Yg, t = ctx.get_state()
+        assert t == step
+        G64 = (Xs @ A + cp[None, :]) / s
+        gabs = GTOL[prec] * float(np.max(np.abs(G64))) + 1e-6
+        dx, dy, namb, _, _ = lockstep_compare(Xs, Ys, G64, Xg[SAMPLE], Yg[SAMPLE], p, gabs)
+        say(f"   t={step} lockstep max|dX|={dx:.3e} max|dY|={dy:.3e} excluded={namb}")
+        assert dx <= p["alpha"] * gabs + 2e-6 and dy <= 1e-5
+        assert namb <= amb_limit(prec, Xs.size)
+        assert np.array_equal(ctx.objectives(), oq.objective(q, Xg > 0.5))
 
 
 def test_c5_maxsat_n20000_m84000_B256():

@@ -50,6 +50,36 @@ def test_quadratic_derivative_central_difference_exact():
     assert np.array_equal((Quadratic.value(x + h) - Quadratic.value(x - h)) / (2 * h), Quadratic.deriv(x))
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_polynomial_derivative_complex_step_and_expanded(d):
+    """g(x) = (2x-1)^(2d) - 1 (Sec. 3.1): the derivative agrees with the complex
+    step Im g(x + ih)/h, which has no cancellation and is exact to rounding for
+    a polynomial, and with numpy.polynomial's derivative of the expanded
+    coefficients; d = 1 is four times the quadratic g."""
+    from numpy.polynomial import polynomial as npp
+    g = Polynomial(d)
+    x = np.linspace(0.0, 1.0, 129)
+    h = 1e-30
+    cs = np.imag(g.value(x + 1j * h)) / h
+    assert np.allclose(g.deriv(x), cs, rtol=1e-13, atol=1e-13)
+    coef = npp.polysub(npp.polypow([-1.0, 2.0], 2 * d), [1.0])
+    assert np.allclose(g.value(x), npp.polyval(x, coef), rtol=0, atol=1e-12)
+    assert np.allclose(g.deriv(x), npp.polyval(x, npp.polyder(coef)), rtol=1e-12, atol=1e-12)
+    if d == 1:
+        assert np.array_equal(g.deriv(x), 4.0 * Quadratic.deriv(x))
+
+
+def test_prop33_lower_bound_golden():
+    """Prop. 3.3 bound b on hand-worked values (tests/golden/prop33_lower_bound.json)."""
+    with open(os.path.join(GOLDEN, "prop33_lower_bound.json")) as fh:
+        gold = json.load(fh)
+    kinds = {"quad": Quadratic(), "entropy": Entropy(), "poly2": Polynomial(2)}
+    for case in gold["cases"]:
+        b = ob.prop33_lower_bound(case["theta"], case["alpha"], case["beta"], case["delta"],
+                                  kinds[case["g"]])
+        assert b == pytest.approx(case["b"], rel=1e-12, abs=1e-9), case["name"]
+
+
 def _one_var(c, s):
     return oq.QuboProblem(W.Qubo(n=1, Q=np.zeros((1, 1), np.int32), c=None), s), c
 
@@ -68,7 +98,7 @@ def test_alg1_worked_examples():
 
 
 def test_maxcut_example_step_at_half():
-    # Sec. 4.1 example: at x = 1/2 the gradient vanishes; with y <= 0 every
+    # Sec. 3.2.1 example: at x = 1/2 the gradient vanishes; with y <= 0 every
     # coordinate is perturbed to 1/2 - delta, with y > 0 it stays at 1/2
     q = W.maxcut_c2(rep=2, n=50, M=120)
     P = oq.QuboProblem(q, 1.0)
@@ -116,18 +146,18 @@ def _invariants(problem, x0, p, T, Fstar=None):
     res = gda.run(problem, x0, p, T=T, record=True)
     # box (Alg. 1 projection) after the run
     assert np.all((res.X >= 0) & (res.X <= 1))
-    # y non-increasing: each increment beta*g(x) <= 0 (Sec. 4.1)
+    # y non-increasing: each increment beta*g(x) <= 0 (Sec. 3.2.1)
     Y0 = np.full_like(x0, p["y0"])
     assert np.all(res.Y <= Y0)
-    # telescoping identity (proof of Thm. 4.2)
+    # telescoping identity (proof of Thm. 3.7)
     gap = ob.telescoping_gap(Y0, res.Y, res.sum_g, p["beta"])
     scale = np.sum(np.abs(Y0 - res.Y), axis=1) + 1.0
     assert np.all(np.abs(gap) <= 1e-12 * scale)
-    # Prop. 4.1 lower bound with an upper bound on Theta
-    b = ob.prop41_lower_bound(problem.theta_upper(), p["alpha"], p["beta"], p["delta"], g)
+    # Prop. 3.3 lower bound with an upper bound on Theta
+    b = ob.prop33_lower_bound(problem.theta_upper(), p["alpha"], p["beta"], p["delta"], g)
     assert min(res.y_min) >= b and res.Y.min() >= b
     if Fstar is not None:
-        # Lemma 2.1: f(x) >= min F on the box (f is the multilinear extension)
+        # Lemma 2.3: f(x) >= min F on the box (f is the multilinear extension)
         assert min(float(np.min(v)) for v in res.f_values) * problem.s >= Fstar - 1e-9
         assert res.inc.F >= Fstar
     # incumbent is consistent with its own vector
@@ -176,7 +206,7 @@ def test_incumbent_tie_rules():
 
 
 def test_binarity_of_long_run():
-    # Cor. 4.1 / Def. 4.1: -sum g(x) shrinks towards 0 as y decreases
+    # Cor. 3.5 / Def. 3.6: -sum g(x) shrinks towards 0 as y decreases
     q = W.qubo_c1(0, n=60)
     P = oq.QuboProblem(q, 1.0)
     x0 = W.x0_uniform(1, 0, 4, q.n, 60)

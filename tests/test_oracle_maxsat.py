@@ -25,7 +25,7 @@ def _loop_unsat(lits, w, x):
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_clause_product_is_unsat_indicator(k):
-    # Sec. 5.1 Max-k-SAT: prod_l p(x_l) = 1 iff the clause is unsatisfied
+    # Sec. 4.1 Max-k-SAT: prod_l p(x_l) = 1 iff the clause is unsatisfied
     for signs in itertools.product((1, -1), repeat=k):
         lits = np.array([[s * (i + 1) for i, s in enumerate(signs)]], dtype=np.int32)
         inst = W.MaxSat(n=k, lits=lits, w=np.array([1], np.int32))

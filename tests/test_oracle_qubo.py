@@ -37,7 +37,7 @@ def _loop_F(Q, c, x):
 
 
 def test_maxcut_edge_identity():
-    # Sec. 5.1 Max-Cut: x_i + x_j - 2 x_i x_j equals 1 iff x_i != x_j on {0,1}^2
+    # Sec. 4.1 Max-Cut: x_i + x_j - 2 x_i x_j equals 1 iff x_i != x_j on {0,1}^2
     for xi, xj in itertools.product((0, 1), repeat=2):
         assert xi + xj - 2 * xi * xj == int(xi != xj)
 
@@ -59,7 +59,7 @@ def test_objective_csr_equals_dense_and_minus_cut():
     qd = W.Qubo(n=q.n, Q=q.dense().astype(np.int32), c=q.c)
     F_dense = oq.objective(qd, X)
     assert np.array_equal(F_csr, F_dense)
-    # cut(x) = sum over edges i<j of W_ij [x_i != x_j]; F = -cut (Sec. 5.1, Sec. 4.1 example)
+    # cut(x) = sum over edges i<j of W_ij [x_i != x_j]; F = -cut (Sec. 4.1, Sec. 3.2.1 example)
     Wd = q.dense()
     for b in range(12):
         cut = 0
@@ -103,7 +103,7 @@ def test_brute_force_gray_code_n18_twin():
 
 
 def test_canonical_f_equals_definition_bit_exact():
-    # Def. 2.2 enumeration vs the Prop. 2.2 closed form, at dyadic points k/8
+    # Def. 2.2 enumeration vs the Prop. 2.4 closed form, at dyadic points k/8
     q = _rand_qubo(8, 7)
     F_all = oq.objective(q, en.all_binary(q.n))
     A, cp = oq.canonicalize(q)
@@ -148,7 +148,7 @@ def test_gradient_forward_difference_exact():
 
 
 def test_maxcut_example_gradient_vanishes_at_half():
-    # Sec. 4.1 Max-Cut example: f = x^T W x - 1^T W x, g = x^2 - x, x = 1/2 gives
+    # Sec. 3.2.1 Max-Cut example: f = x^T W x - 1^T W x, g = x^2 - x, x = 1/2 gives
     # grad_x L = 0 for every y
     q = W.maxcut_c2(rep=1, n=40, M=90)
     P = oq.QuboProblem(q, 1.0)

@@ -4,7 +4,7 @@ Every draw comes from ``numpy.random.default_rng([cfg_id, rep, stream, ...])``
 with stream 0 the instance and stream 1 the starting points, so the oracle and
 the HIP path see bit-identical inputs.  The shapes and distributions stand in
 for the paper's benchmarks (Gset graphs for Max-Cut, random k-CNF formulas for
-Max-k-SAT, Sec. 5.2), which are not reproduced here.
+Max-k-SAT, Sec. 4.2), which are not reproduced here.
 
 Conventions
 -----------
@@ -132,7 +132,7 @@ def maxcut_c2(rep: int = 0, n: int = 2000, M: int = 6000) -> Qubo:
     """Max-Cut on G(n, M) (M distinct edges, mean degree 2M/n) with +-1 weights.
 
     As a QUBO: Q = W (symmetric CSR, both directions stored) and c = -W 1, so that
-    F(x) = x^T W x - 1^T W x equals minus the cut weight (Sec. 5.1 Max-Cut)."""
+    F(x) = x^T W x - 1^T W x equals minus the cut weight (Sec. 4.1 Max-Cut)."""
     g = rng_for(2, rep, 0, n, M)
     lin = g.choice(n * (n - 1) // 2, size=M, replace=False)
     i, j = _pairs_from_linear(n, np.sort(lin))
