@@ -192,6 +192,23 @@ PDBO_API pdbo_status qubo_gda_grad(pdbo_ctx* ctx, const float* x, float* G);
  * bytes in {0,1}, nb <= B, through the step's evaluation kernels. */
 PDBO_API pdbo_status qubo_gda_eval(pdbo_ctx* ctx, const uint8_t* xr, int32_t nb, int64_t* F);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the exact
+ * objectives of qubo_gda_eval with DEVICE arguments, enqueued on `stream`
+ * (hipStream_t, NULL = the null stream), asynchronous, with no allocation,
+ * free, memset or synchronisation.
+ *   xr: device (nb, n) bytes, a nonzero byte counts as 1; F: device int64[nb];
+ *   1 <= nb <= B.
+ * The dense path stages xr and keeps the evaluation's integer partial sums in
+ * a 16 MiB device array that the library holds on each GPU it runs on until
+ * the process ends; PDBO_EUNSUPPORTED when nb * ld + 16 nb + 256 bytes exceed
+ * it (ld = n rounded up to 128; nb <= 1656 at n = 10^4).  All calls on one GPU
+ * share that array: calls that overlap on one GPU (other streams, threads or
+ * contexts) race, calls ordered on one stream do not.  The CSR and MaxSAT
+ * paths read xr in place and use no scratch.  ESTATE for batched contexts. */
+PDBO_API pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* ctx, const uint8_t* xr, int32_t nb, int64_t* F,
+                                           void* stream);
+
 /* init + step(T) + result + destroy. */
 PDBO_API pdbo_status qubo_gda_solve(const pdbo_qubo* prob, const pdbo_params* par, int32_t T,
                            void* stream, pdbo_result* result);

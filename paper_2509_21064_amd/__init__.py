@@ -26,7 +26,7 @@ from ._abi import (PDBO_BF16, PDBO_CSR, PDBO_DENSE, PDBO_FP8, PDBO_FP32, PDBO_G_
 __all__ = [
     "load", "PdboError", "Context", "qubo_gda_init", "qubo_gda_step", "qubo_gda_result",
     "qubo_gda_get_state", "qubo_gda_set_state", "qubo_gda_restart", "qubo_gda_objectives", "qubo_gda_grad",
-    "qubo_gda_eval", "qubo_gda_trace", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
+    "qubo_gda_eval", "qubo_gda_eval_noalloc", "qubo_gda_trace", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
     "qubo_gda_batch_solve", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
     "maxsat_gda_solve", "maxsat_lagrangian_fwd", "maxsat_lagrangian_bwd", "MaxSATLagrangian",
     "PDBO_FP32", "PDBO_BF16", "PDBO_FP8", "PDBO_I8", "PDBO_K_STEP", "PDBO_K_EVAL", "PDBO_K_ARGMIN",
@@ -239,6 +239,18 @@ def qubo_gda_eval(ctx: Context, xr) -> np.ndarray:
     xa = xa.reshape(-1, ctx.n)
     F = np.zeros(xa.shape[0], dtype=np.int64)
     check(load().qubo_gda_eval(ctx.h, _ptr(xa), int(xa.shape[0]), _ptr(F)), ctx.h)
+    return F
+
+
+def qubo_gda_eval_noalloc(ctx: Context, xr, F, stream=None):
+    """Exact objectives of the rounded rows of the device uint8 tensor xr (nb, n)
+    into the device int64 tensor F (nb,), enqueued on the current torch stream
+    (or `stream`), with no device allocation by the library."""
+    assert xr.is_cuda and F.is_cuda and xr.is_contiguous() and F.is_contiguous()
+    assert xr.dim() == 2 and xr.shape[1] == ctx.n and F.shape == (xr.shape[0],)
+    s = _current_stream() if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    check(load().qubo_gda_eval_noalloc(ctx.h, ctypes.c_void_p(xr.data_ptr()), int(xr.shape[0]),
+                                       ctypes.c_void_p(F.data_ptr()), s), ctx.h)
     return F
 
 

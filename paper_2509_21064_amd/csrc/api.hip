@@ -1115,6 +1115,60 @@ pdbo_status begin_ctx(pdbo_ctx* c, void* stream, const pdbo_params* p) {
   return PDBO_OK;
 }
 
+
+// ------------------------------------------------ evaluation without allocation
+//
+// qubo_gda_eval_noalloc stages the caller's rounded vectors and keeps the
+// integer partial sums of the dense evaluation in this file-scope array, so
+// that it calls no allocator.  Each GPU the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device address).
+constexpr size_t kNoallocScratchBytes = size_t(16) << 20;
+constexpr size_t kNoallocDescBytes = 256;  // room for one InstDev, 256-byte aligned
+static_assert(sizeof(InstDev) <= kNoallocDescBytes, "descriptor slot");
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[kMaxDevices] = {};
+
+pdbo_status scratch_for_current_device(pdbo_ctx* c, uint8_t** out) {
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, PDBO_EUNSUPPORTED, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = (uint8_t*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PDBO_OK;
+}
+
+// xs[b][j] = [xr[b][j] != 0] for j < n, 0 for n <= j < ld (the padding the
+// 128-byte K chunks of the evaluation GEMM read).
+__global__ void stage_rounded_kernel(const uint8_t* __restrict__ xr, int nb, int n, int ld,
+                                     int8_t* __restrict__ xs) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nb * ld) return;
+  const int b = (int)(idx / ld), j = (int)(idx % ld);
+  xs[idx] = j < n ? (int8_t)(xr[(size_t)b * n + j] != 0) : (int8_t)0;
+}
+
+// Writes the instance descriptor of the evaluation into the scratch array and
+// clears the integer partial sums S, C that the evaluation GEMM accumulates
+// into (the last call on this GPU may have left anything there).
+__global__ void put_eval_desc_kernel(InstDev* dst, InstDev v, int64_t* S, int64_t* C, int nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *dst = v;
+  if (i < nb) {
+    S[i] = 0;
+    C[i] = 0;
+  }
+}
+
 }  // namespace
 
 // =================================================================== ABI
@@ -1586,6 +1640,59 @@ pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(F, c->f_scratch, nb * sizeof(int64_t), hipMemcpyDeviceToHost));
+  return PDBO_OK;
+}
+
+pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F,
+                                  void* stream) {
+  if (!c || !xr || !F) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (nb < 1 || nb > c->B) return fail(c, PDBO_EINVAL, "nb must be in [1, B]");
+  const hipStream_t s = (hipStream_t)stream;
+  const int n = c->n_of[0];
+  if (c->kind != 0) {
+    // the CSR and MaxSAT evaluation kernels read the caller's rows directly
+    // (row stride n, nonzero bytes are 1) and need no scratch
+    if (c->kind == 1) {
+      CsrDev d = c->csr;
+      d.ld = n;
+      HIPCHK(c, launch_csr_eval(d, (const int8_t*)xr, nb, F, s));
+    } else {
+      SatDev d = c->sat;
+      d.ld = n;
+      HIPCHK(c, launch_sat_eval(d, (const int8_t*)xr, nb, F, s));
+    }
+    return PDBO_OK;
+  }
+  const InstDev& I0 = c->insts_h[0];
+  const size_t need = kNoallocDescBytes + 2 * sizeof(int64_t) * (size_t)nb + (size_t)nb * I0.ld;
+  if (need > kNoallocScratchBytes)
+    return fail(c, PDBO_EUNSUPPORTED,
+                "nb * ld + 16 nb + 256 = " + std::to_string(need) + " bytes exceeds the " +
+                    std::to_string(kNoallocScratchBytes) + "-byte scratch of qubo_gda_eval_noalloc");
+  uint8_t* base = nullptr;
+  STCHK(scratch_for_current_device(c, &base));
+  InstDev* desc = (InstDev*)base;
+  int64_t* S = (int64_t*)(base + kNoallocDescBytes);
+  int64_t* C = S + nb;
+  int8_t* xs = (int8_t*)(C + nb);  // 256 + 16 nb bytes in: 16-byte aligned
+  InstDev I = I0;
+  I.Xr = xs;
+  I.Sacc = S;
+  I.Cacc = C;
+  I.Fall = F;
+  I.nflip = nullptr;  // full product for every vector
+  I.B = nb;
+  const size_t tot = (size_t)nb * I0.ld;
+  hipLaunchKernelGGL(stage_rounded_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, xr,
+                     nb, n, I0.ld, xs);
+  HIPCHK(c, hipGetLastError());
+  hipLaunchKernelGGL(put_eval_desc_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, desc,
+                     I, S, C, nb);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d, (int)c->tiles_h.size(), desc,
+                              0, 0, s));
+  HIPCHK(c, launch_argmin(desc, 0, 1, 2, s));
   return PDBO_OK;
 }
 
