@@ -54,7 +54,8 @@ typedef enum {
 typedef struct pdbo_ctx pdbo_ctx;
 
 enum { PDBO_DENSE = 0, PDBO_CSR = 1 };
-enum { PDBO_G_QUAD = 0, PDBO_G_ENTROPY = 1 };
+enum { PDBO_G_QUAD = 0, PDBO_G_ENTROPY = 1, PDBO_G_POLY = 2 };
+enum { PDBO_DUAL_VECTOR = 0, PDBO_DUAL_SCALAR = 1 };
 enum { PDBO_FP32 = 0, PDBO_BF16 = 1, PDBO_FP8 = 2, PDBO_I8 = 3 };
 
 /*
@@ -101,14 +102,18 @@ typedef struct {
  *   delta      perturbation tolerance, in (0, 1/2).
  *   scale      s > 0: the method runs on f/s (gradient (A x + c')/s); the
  *              objective is still reported unscaled.
- *   g_kind     PDBO_G_QUAD (x^2 - x) or PDBO_G_ENTROPY (x log x + (1-x) log(1-x),
- *              derivative taken at x clipped to [2^-20, 1 - 2^-20]).
+ *   g_kind     the binarity constraint function g of Sec. 3.1: PDBO_G_QUAD
+ *              (x^2 - x), PDBO_G_ENTROPY (x log x + (1-x) log(1-x), derivative
+ *              taken at x clipped to [2^-20, 1 - 2^-20]) or PDBO_G_POLY
+ *              ((2x - 1)^(2d) - 1 with d = g_degree).
  *   precision  operand type of the dense gradient product A.X: PDBO_FP32,
  *              PDBO_BF16 (A and a bf16 copy of X), PDBO_FP8 (A as OCP e4m3 with
  *              one fp32 scale per row, X as e4m3), all with FP32 accumulation;
  *              or PDBO_I8 (A exactly as int8, X quantised to q = round(254 x) -
  *              127 so that x ~ (q + 127)/254 within 1/508, int32 accumulation;
- *              needs |Ahat_ij| <= 127 and 127 sum_j |Ahat_ij| < 2^31).
+ *              needs |Ahat_ij| <= 127 and 127 sum_j |Ahat_ij| < 2^31, else
+ *              EUNSUPPORTED; the other forms take any |Ahat_ij| the exact
+ *              evaluation covers).
  *              Ignored by the CSR and MaxSAT paths, whose integer weights are
  *              stored exactly.
  *   eval_every evaluate round(x^t) every eval_every iterations (>= 1); the
@@ -116,7 +121,18 @@ typedef struct {
  *   tile       dense tile configuration id (0 = default for the shape).
  *   graph_chunk  dense path: 0 = eager launches; K > 0 (even) = capture K
  *              iterations in one hipGraph and replay it.
- *   x0         HOST (B, n) float64 starting points in [0,1] (required).
+ *   g_degree   d of PDBO_G_POLY, in [1, 16]; ignored for the other kinds.
+ *   dual_kind  PDBO_DUAL_VECTOR: one dual variable per coordinate (Alg. 1);
+ *              PDBO_DUAL_SCALAR: one per restart for the single constraint
+ *              sum_i g(x_i) = 0 (the PDBO-s variant of Sec. 4.5), updated as
+ *              y += beta * sum_i g(x_i^t); dense path only (else EUNSUPPORTED).
+ *   x0         HOST (B, n) float64 starting points in [0,1], or NULL: then the
+ *              library draws X^0 uniformly on [0,1)^n (App. C) with the
+ *              counter-based generator Philox4x32-10 (Salmon et al., SC 2011)
+ *              keyed by (seed mod 2^32, seed div 2^32): coordinate i of restart
+ *              b is word (i mod 4) of the output for the counter
+ *              (i div 4, b, 0, 0), and x = (word >> 8) * 2^-24.
+ *   seed       key of that generator; ignored when x0 is given.
  */
 typedef struct {
   int32_t B;
@@ -130,7 +146,10 @@ typedef struct {
   double scale;
   int32_t tile;
   int32_t graph_chunk;
+  int32_t g_degree;
+  int32_t dual_kind;
   const double* x0;
+  uint64_t seed;
 } pdbo_params;
 
 /* Incumbent of a run: the lexicographic minimum of (F, t, b) over all
@@ -151,8 +170,12 @@ typedef struct {
  * X^0 = x0 and Y^0 = y0 (Alg. 1 input), and returns a context.  EINVAL for any
  * contract violation (checked before any HIP call); ERANGE when the exact
  * int64 evaluation cannot be guaranteed (|Q_ij| >= 2^30, or a row of |A| or
- * |c'| summing to 2^31 or more); EUNSUPPORTED for a CSR instance too large for
- * the on-chip resident kernel.  `stream` is a hipStream_t (NULL = default). */
+ * |c'| summing to 2^31 or more; dense: |Ahat_ij| above 2,139,062,143, the range
+ * of the four int8 limbs Ahat = sum_l 256^l Ahat_l that the exact evaluation
+ * multiplies one by one); EUNSUPPORTED for a CSR instance too large for the
+ * on-chip resident kernel, or the INT8 form with |Ahat_ij| > 127.  The dense
+ * instance is canonicalised before any HIP call, so its range errors come back
+ * on any machine.  `stream` is a hipStream_t (NULL = default). */
 PDBO_API pdbo_status qubo_gda_init(const pdbo_qubo* prob, const pdbo_params* par, void* stream,
                           pdbo_ctx** out);
 
@@ -174,9 +197,10 @@ PDBO_API pdbo_status qubo_gda_get_state(pdbo_ctx* ctx, float* x, float* y, int64
 PDBO_API pdbo_status qubo_gda_set_state(pdbo_ctx* ctx, const float* x, const float* y, int64_t t);
 
 /* Starts the run over on the same instance and parameters: X^0 = x0 (HOST
- * (B, n) float64 in [0,1]), Y^0 = y0, t = 0, incumbent, trace and time origin
+ * (B, n) float64 in [0,1], or NULL for the generator's points of the
+ * parameters' seed), Y^0 = y0, t = 0, incumbent, trace and time origin
  * cleared (Alg. 1 input), without uploading the instance again.  Not for
- * batched contexts (ESTATE).  EINVAL when x0 is NULL or outside [0,1].
+ * batched contexts (ESTATE).  EINVAL when x0 lies outside [0,1].
  * Synchronises. */
 PDBO_API pdbo_status qubo_gda_restart(pdbo_ctx* ctx, const double* x0);
 
@@ -201,7 +225,7 @@ PDBO_API pdbo_status qubo_gda_eval(pdbo_ctx* ctx, const uint8_t* xr, int32_t nb,
  *   1 <= nb <= B.
  * The dense path stages xr and keeps the evaluation's integer partial sums in
  * a 16 MiB device array that the library holds on each GPU it runs on until
- * the process ends; PDBO_EUNSUPPORTED when nb * ld + 16 nb + 256 bytes exceed
+ * the process ends; PDBO_EUNSUPPORTED when nb * ld + 16 nb + 512 bytes exceed
  * it (ld = n rounded up to 128; nb <= 1656 at n = 10^4).  All calls on one GPU
  * share that array: calls that overlap on one GPU (other streams, threads or
  * contexts) race, calls ordered on one stream do not.  The CSR and MaxSAT
@@ -217,7 +241,7 @@ PDBO_API pdbo_status qubo_gda_solve(const pdbo_qubo* prob, const pdbo_params* pa
  * instances is ONE grouped launch per kernel (grouped != 0) or k launches per
  * kernel (grouped == 0), optionally captured in a hipGraph (par[0].graph_chunk).
  * par[i] gives instance i's parameters; B, precision, g_kind and eval_every
- * must agree across instances.  results[i] (with its own best_x) receives
+ * must agree across instances (and dual_kind).  results[i] (with its own best_x) receives
  * instance i's incumbent. */
 PDBO_API pdbo_status qubo_gda_batch_init(int32_t k, const pdbo_qubo* probs, const pdbo_params* par,
                                 int32_t grouped, void* stream, pdbo_ctx** out);

@@ -20,13 +20,16 @@ Modules
                definition (Def. 2.2), for small n
 ``bounds``     the dual lower bound of Prop. 3.3 and the telescoping identity in
                the proof of Thm. 3.7
+``philox``     Philox4x32-10 and the starting points the library draws when the
+               caller passes none (App. C: x^0 uniform on [0,1]^n)
 
 Every function works in float64 (objectives of integer instances in int64).
 Each function is pinned by a CPU test under ``tests/`` against something other
 than itself: plain-loop and brute-force definitions, the paper's worked
 examples and identities, hand-worked golden values under ``tests/golden/``,
-closed forms, exact finite or complex-step differences, and library routines
-(numpy.polynomial, numpy's Philox).  Which test pins which function is listed
-in the design notes; no function here is "parity unpinned".
+closed forms, exact finite or complex-step differences, library routines
+(numpy.polynomial) and the published known-answer vectors of Philox4x32-10.
+Which test pins which function is listed in the design notes; no function here
+is "parity unpinned".
 """
-from . import binarity, bounds, enumerate, gda, maxsat, qubo  # noqa: F401
+from . import binarity, bounds, enumerate, gda, maxsat, philox, qubo  # noqa: F401

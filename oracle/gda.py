@@ -26,13 +26,18 @@ import numpy as np
 
 from .binarity import by_name
 
-__all__ = ["alg1_update", "round_half", "Incumbent", "RunResult", "run", "step"]
+__all__ = ["alg1_update", "constraint_fn", "round_half", "Incumbent", "RunResult", "run", "step"]
 
 
-def alg1_update(X, Y, grad_f, alpha, beta, delta, g):
+def alg1_update(X, Y, grad_f, alpha, beta, delta, g, dual="vector"):
     """One iteration of Alg. 1 for all coordinates of all restarts.
 
-    X, Y, grad_f: arrays of shape (B, n); grad_f is the gradient of f at X.
+    X, grad_f: arrays of shape (B, n); grad_f is the gradient of f at X.
+    Y: shape (B, n), one dual variable per constraint g(x_i) = 0 (Alg. 1), or
+    with dual="scalar" shape (B, 1), one per restart for the single constraint
+    sum_i g(x_i) = 0 (the PDBO-s variant, Sec. 4.5): the same primal step with
+    y in place of every y_i, and the dual ascent along the constraint's value,
+    y + beta * sum_i g(x_i).
     Returns (X^{t+1}, Y^{t+1}, dL/dx)."""
     dL = grad_f + Y * g.deriv(X)
     near_half = np.abs(X - 0.5) <= delta
@@ -42,8 +47,19 @@ def alg1_update(X, Y, grad_f, alpha, beta, delta, g):
     x_pert = np.where(X <= 0.5, 0.5 - delta, 0.5 + delta)
     x_step = np.clip(X - alpha * dL, 0.0, 1.0)
     X_new = np.where(perturb, x_pert, x_step)
-    Y_new = Y + beta * g.value(X)
+    if dual == "scalar":
+        Y_new = Y + beta * np.sum(g.value(X), axis=1, keepdims=True)
+    else:
+        Y_new = Y + beta * g.value(X)
     return X_new, Y_new, dL
+
+
+def constraint_fn(p):
+    """The g named by the parameters (with its degree for the polynomial)."""
+    name = p.get("g", "quad")
+    if name in ("poly", "polynomial"):
+        return by_name(name, d=int(p.get("g_degree", 1)))
+    return by_name(name)
 
 
 def round_half(X):
@@ -81,18 +97,26 @@ class RunResult:
 
 def step(problem, X, Y, p):
     """One Alg. 1 iteration from (X, Y); returns (X+, Y+, grad f, dL/dx)."""
-    g = by_name(p.get("g", "quad"))
+    g = constraint_fn(p)
     G = problem.grad(X)
-    Xn, Yn, dL = alg1_update(X, Y, G, p["alpha"], p["beta"], p["delta"], g)
+    Xn, Yn, dL = alg1_update(X, Y, G, p["alpha"], p["beta"], p["delta"], g,
+                             p.get("dual", "vector"))
     return Xn, Yn, G, dL
 
 
 def run(problem, x0, p, T=None, Y0=None, record=False, eval_every=1) -> RunResult:
-    """Alg. 1 for T iterations over the restarts given by the rows of x0."""
-    g = by_name(p.get("g", "quad"))
+    """Alg. 1 for T iterations over the restarts given by the rows of x0
+    (p["dual"] == "scalar": the single-constraint variant, Y of shape (B, 1))."""
+    g = constraint_fn(p)
+    dual = p.get("dual", "vector")
     T = p["T"] if T is None else T
     X = np.array(x0, dtype=np.float64, copy=True)
-    Y = np.full_like(X, p["y0"]) if Y0 is None else np.array(Y0, dtype=np.float64, copy=True)
+    if Y0 is not None:
+        Y = np.array(Y0, dtype=np.float64, copy=True)
+    elif dual == "scalar":
+        Y = np.full((X.shape[0], 1), float(p["y0"]))
+    else:
+        Y = np.full_like(X, p["y0"])
     res = RunResult(inc=Incumbent(), X=X, Y=Y, steps=0)
     for t in range(T):
         G = problem.grad(X)
@@ -100,7 +124,7 @@ def run(problem, x0, p, T=None, Y0=None, record=False, eval_every=1) -> RunResul
             res.sum_g.append(np.sum(g.value(X), axis=1))
             res.y_min.append(float(Y.min()))
             res.f_values.append(problem.f(X))
-        X, Y, _ = alg1_update(X, Y, G, p["alpha"], p["beta"], p["delta"], g)
+        X, Y, _ = alg1_update(X, Y, G, p["alpha"], p["beta"], p["delta"], g, dual)
         if (t + 1) % eval_every == 0:
             Xr = round_half(X)
             F = problem.objective(Xr)

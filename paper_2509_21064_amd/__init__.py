@@ -10,7 +10,8 @@ Instances are duck-typed: a QUBO has ``n`` and either a dense int32 ``Q`` or CSR
 has ``n``, ``lits`` (m, k) DIMACS int32 and ``w`` (m,) int32.  Parameters are a
 dict with B, alpha, beta, y0, delta, scale, g ("quad"/"entropy"), and
 optionally precision ("fp32"/"bf16"/"fp8"/"i8"), eval_every, tile, graph_chunk.
-Starting points x0 are float64 arrays of shape (B, n).
+Starting points x0 are float64 arrays of shape (B, n), or None: then the
+library draws them with its Philox4x32-10 generator keyed by params["seed"].
 """
 from __future__ import annotations
 
@@ -34,7 +35,8 @@ __all__ = [
 ]
 
 _PREC = {"fp32": PDBO_FP32, "bf16": PDBO_BF16, "fp8": PDBO_FP8, "i8": PDBO_I8}
-_G = {"quad": PDBO_G_QUAD, "entropy": PDBO_G_ENTROPY}
+_G = {"quad": PDBO_G_QUAD, "entropy": PDBO_G_ENTROPY, "poly": _abi.PDBO_G_POLY}
+_DUAL = {"vector": _abi.PDBO_DUAL_VECTOR, "scalar": _abi.PDBO_DUAL_SCALAR}
 
 
 def _ptr(a):
@@ -102,7 +104,10 @@ def _params_struct(p: dict, x0, keep: _Keep) -> _abi.pdbo_params:
     s.delta, s.scale = float(p["delta"]), float(p.get("scale", 1.0))
     s.tile = int(p.get("tile", 0))
     s.graph_chunk = int(p.get("graph_chunk", 0))
+    s.g_degree = int(p.get("g_degree", 1))
+    s.dual_kind = _DUAL[p.get("dual", "vector")]
     s.x0 = _ptr(keep.arr(x0, np.float64)) if x0 is not None else None
+    s.seed = int(p.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
     return s
 
 
@@ -214,10 +219,13 @@ def qubo_gda_set_state(ctx: Context, x=None, y=None, t=0):
     check(load().qubo_gda_set_state(ctx.h, _ptr(xa), _ptr(ya), int(t)), ctx.h)
 
 
-def qubo_gda_restart(ctx: Context, x0):
-    xa = np.ascontiguousarray(x0, dtype=np.float64)
-    if xa.shape != (ctx.B, ctx.n):
-        raise ValueError(f"x0 must have shape {(ctx.B, ctx.n)}")
+def qubo_gda_restart(ctx: Context, x0=None):
+    """x0 None: the library's generator with the parameters' seed."""
+    xa = None
+    if x0 is not None:
+        xa = np.ascontiguousarray(x0, dtype=np.float64)
+        if xa.shape != (ctx.B, ctx.n):
+            raise ValueError(f"x0 must have shape {(ctx.B, ctx.n)}")
     check(load().qubo_gda_restart(ctx.h, _ptr(xa)), ctx.h)
 
 

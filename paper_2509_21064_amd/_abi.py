@@ -7,14 +7,15 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint8, c_uint32, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint8, c_uint32, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpdbo.so")
 
 PDBO_OK, PDBO_EINVAL, PDBO_ENOMEM, PDBO_EDEVICE, PDBO_ERANGE, PDBO_ESTATE, PDBO_EUNSUPPORTED = range(7)
 PDBO_DENSE, PDBO_CSR = 0, 1
-PDBO_G_QUAD, PDBO_G_ENTROPY = 0, 1
+PDBO_G_QUAD, PDBO_G_ENTROPY, PDBO_G_POLY = 0, 1, 2
+PDBO_DUAL_VECTOR, PDBO_DUAL_SCALAR = 0, 1
 PDBO_FP32, PDBO_BF16, PDBO_FP8, PDBO_I8 = 0, 1, 2, 3
 PDBO_K_STEP, PDBO_K_EVAL, PDBO_K_ARGMIN, PDBO_K_PERSISTENT, PDBO_K_INCR = 0, 1, 2, 3, 4
 
@@ -31,7 +32,8 @@ class pdbo_maxsat(ctypes.Structure):
 class pdbo_params(ctypes.Structure):
     _fields_ = [("B", c_int32), ("g_kind", c_int32), ("precision", c_int32), ("eval_every", c_int32),
                 ("alpha", c_double), ("beta", c_double), ("y0", c_double), ("delta", c_double),
-                ("scale", c_double), ("tile", c_int32), ("graph_chunk", c_int32), ("x0", c_void_p)]
+                ("scale", c_double), ("tile", c_int32), ("graph_chunk", c_int32),
+                ("g_degree", c_int32), ("dual_kind", c_int32), ("x0", c_void_p), ("seed", c_uint64)]
 
 
 class pdbo_result(ctypes.Structure):

@@ -2,8 +2,9 @@
 
     python -m paper_2509_21064_amd.build [-v]
 
-Every HIP source under csrc/ is compiled to an object under _build/ (in
-parallel) and linked into paper_2509_21064_amd/libpdbo.so.  Always recompiles.
+Every HIP source under csrc/ is compiled to objects under _build/ (in
+parallel; dense.hip in four parts) and linked into
+paper_2509_21064_amd/libpdbo.so.  Always recompiles.
 """
 from __future__ import annotations
 
@@ -28,12 +29,26 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
-SOURCES = ["dense.hip", "sparse.hip", "maxsat.hip", "api.hip"]
+# (source, object, extra flags): dense.hip is compiled four times, each part
+# instantiating one share of its kernels (part 0: everything but the step
+# kernels; parts 1-3: the step kernels of one kind of g), so that the parts
+# compile in parallel.
+UNITS = [
+    ("dense.hip", "dense_p0.o", ["-DPDBO_DENSE_PART=0"]),
+    ("dense.hip", "dense_p1.o", ["-DPDBO_DENSE_PART=1"]),
+    ("dense.hip", "dense_p2.o", ["-DPDBO_DENSE_PART=2"]),
+    ("dense.hip", "dense_p3.o", ["-DPDBO_DENSE_PART=3"]),
+    ("sparse.hip", "sparse.o", []),
+    ("maxsat.hip", "maxsat.o", []),
+    ("api.hip", "api.o", []),
+]
+SOURCES = sorted({u[0] for u in UNITS})
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit, verbose: bool) -> str:
+    src, oname, extra = unit
+    obj = os.path.join(BUILD, oname)
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -45,8 +60,9 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    workers = max(1, min(len(UNITS), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(lambda u: _compile(u, verbose), UNITS))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -30,6 +30,7 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr int kTraceCap = 4096;
+constexpr int kMaxLimbs = 4;  // int8 limbs of the dense exact evaluation
 constexpr int64_t kI64Max = LLONG_MAX;
 
 int roundup(int v, int a) { return (v + a - 1) / a * a; }
@@ -194,6 +195,13 @@ pdbo_status temp_upload(pdbo_ctx* c, TempDev& t, const void* host, size_t bytes)
 
 // ---------------------------------------------------------------- validation
 
+// Uploads the caller's starting points, or leaves t empty when there are none
+// (the init kernel then draws them from the generator keyed by the seed).
+pdbo_status upload_x0(pdbo_ctx* c, TempDev& t, const double* x0, size_t count) {
+  if (!x0) return PDBO_OK;
+  return temp_upload(c, t, x0, count * sizeof(double));
+}
+
 pdbo_status check_params(const pdbo_params* p, int n, bool x0_required = true) {
   if (!p) return fail(nullptr, PDBO_EINVAL, "params is NULL");
   if (p->B < 1 || p->B > (1 << 20)) return fail(nullptr, PDBO_EINVAL, "B must be in [1, 2^20]");
@@ -203,7 +211,7 @@ pdbo_status check_params(const pdbo_params* p, int n, bool x0_required = true) {
   if (!finite_pos(p->scale)) return fail(nullptr, PDBO_EINVAL, "scale must be finite and > 0");
   if (!(std::isfinite(p->delta) && p->delta > 0.0 && p->delta < 0.5))
     return fail(nullptr, PDBO_EINVAL, "delta must be in (0, 1/2)");
-  if (p->g_kind != PDBO_G_QUAD && p->g_kind != PDBO_G_ENTROPY)
+  if (p->g_kind != PDBO_G_QUAD && p->g_kind != PDBO_G_ENTROPY && p->g_kind != PDBO_G_POLY)
     return fail(nullptr, PDBO_EINVAL, "unknown g_kind");
   if (p->precision < PDBO_FP32 || p->precision > PDBO_I8)
     return fail(nullptr, PDBO_EINVAL, "unknown precision");
@@ -212,8 +220,11 @@ pdbo_status check_params(const pdbo_params* p, int n, bool x0_required = true) {
     return fail(nullptr, PDBO_EINVAL, "graph_chunk must be 0 or a positive even number");
   if (p->tile < 0 || p->tile > dense_num_cfgs())
     return fail(nullptr, PDBO_EINVAL, "unknown tile configuration");
-  if (x0_required) {
-    if (!p->x0) return fail(nullptr, PDBO_EINVAL, "x0 is required");
+  if (p->g_kind == PDBO_G_POLY && (p->g_degree < 1 || p->g_degree > 16))
+    return fail(nullptr, PDBO_EINVAL, "g_degree must be in [1, 16]");
+  if (p->dual_kind != PDBO_DUAL_VECTOR && p->dual_kind != PDBO_DUAL_SCALAR)
+    return fail(nullptr, PDBO_EINVAL, "unknown dual_kind");
+  if (x0_required && p->x0) {  // NULL: drawn by the library's generator
     const size_t tot = (size_t)p->B * (size_t)n;
     for (size_t i = 0; i < tot; ++i) {
       const double v = p->x0[i];
@@ -268,6 +279,7 @@ struct DenseCanon {
   std::vector<int32_t> Ahat;   // n*n
   std::vector<int64_t> cp;     // n
   int32_t amax = 0;
+  int nlimb = 1;               // int8 limbs of the exact evaluation copy
   std::vector<float> rowmax;   // max_j |Ahat_ij|
 };
 
@@ -333,6 +345,13 @@ pdbo_status canon_dense(const pdbo_qubo* q, DenseCanon& C) {
     C.rowmax[i] = (float)rm;
     C.amax = std::max(C.amax, rm);
   }
+  // The exact evaluation copy holds Ahat as nlimb signed base-256 int8 digits,
+  // which cover |Ahat_ij| <= 127 (256^nlimb - 1) / 255.
+  auto limb_max = [](int L) { return 127 * (((int64_t(1) << (8 * L)) - 1) / 255); };
+  C.nlimb = 1;
+  while (C.nlimb < kMaxLimbs && (int64_t)C.amax > limb_max(C.nlimb)) ++C.nlimb;
+  if ((int64_t)C.amax > limb_max(C.nlimb))
+    return fail(nullptr, PDBO_ERANGE, "|Ahat_ij| beyond the four int8 limbs of the exact evaluation");
   return PDBO_OK;
 }
 
@@ -404,7 +423,14 @@ GdaP make_gp(const pdbo_params* p) {
   g.beta = (float)p->beta;
   g.delta = (float)p->delta;
   g.gkind = p->g_kind;
+  g.deg = p->g_kind == PDBO_G_POLY ? p->g_degree : 1;
   return g;
+}
+
+int32_t f32_bits(float v) {
+  int32_t b;
+  std::memcpy(&b, &v, sizeof(b));
+  return b;
 }
 
 int element_bytes(int prec) { return prec == PDBO_FP32 ? 4 : prec == PDBO_BF16 ? 2 : 1; }
@@ -506,14 +532,14 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
   I.kos = (float)((double)C.kappa / p->scale);
   I.gp = make_gp(p);
   I.trace_cap = kTraceCap;
-  if (C.amax > 127)
-    return fail(c, PDBO_EUNSUPPORTED,
-                "dense exact evaluation needs |Ahat_ij| <= 127 (int8 MFMA path)");
+  const int nlimb = C.nlimb;
+  I.nlimb = nlimb;
+  I.limb_stride = (int64_t)n * ld;
 
   uint8_t* A = nullptr;
   int8_t* A8 = nullptr;
   float* rs = nullptr;
-  STCHK(dalloc(c, &A8, (size_t)n * ld));
+  STCHK(dalloc(c, &A8, (size_t)nlimb * n * ld));
   if (prec == PDBO_I8) {
     // the exact int8 matrix is the gradient operand as well
     int64_t worst = 0;
@@ -547,7 +573,7 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
   {
     TempDev t;
     STCHK(temp_upload(c, t, C.Ahat.data(), (size_t)n * n * sizeof(int32_t)));
-    HIPCHK(c, launch_quantize_A((const int32_t*)t.p, n, ld, prec, A, A8, rs, c->stream));
+    HIPCHK(c, launch_quantize_A((const int32_t*)t.p, n, ld, prec, A, A8, nlimb, rs, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   if (prec == PDBO_I8) A = (uint8_t*)A8;
@@ -602,6 +628,11 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
     STCHK(dalloc(c, &I.cand, (size_t)B * ld));
     HIPCHK(c, launch_fill_i32(I.nflip, kFlipMax + 1, B, c->stream));
   }
+  I.ys = nullptr;
+  if (p->dual_kind == PDBO_DUAL_SCALAR) {
+    STCHK(dalloc(c, &I.ys, (size_t)B));
+    HIPCHK(c, launch_fill_i32((int32_t*)I.ys, f32_bits((float)p->y0), B, c->stream));
+  }
   STCHK(dalloc(c, &I.inc, 1));
   STCHK(dalloc(c, &I.best_x, (size_t)ld));
   STCHK(dalloc(c, &I.trace, kTraceCap));
@@ -612,9 +643,9 @@ pdbo_status setup_dense_instance(pdbo_ctx* c, const DenseCanon& C, const pdbo_pa
   HIPCHK(c, hipMemcpyAsync(I.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
   {
     TempDev t;
-    STCHK(temp_upload(c, t, p->x0, (size_t)B * n * sizeof(double)));
+    STCHK(upload_x0(c, t, p->x0, (size_t)B * n));
     HIPCHK(c, launch_init_state((const double*)t.p, B, n, ld, (float)p->y0, I.X[0], I.Y,
-                                prec == PDBO_FP32 ? nullptr : I.Xs[0], prec, I.Xr, c->stream));
+                                prec == PDBO_FP32 ? nullptr : I.Xs[0], prec, I.Xr, p->seed, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   return PDBO_OK;
@@ -935,12 +966,27 @@ int64_t full_eval_iters() {
 // With incremental evaluation an iteration's best of B is left pending: it
 // runs in extra workgroups of the next step launch (on CUs the tiles leave
 // free), or in a launch of its own when the steps stop (flush_argmin).
+// The evaluation GEMM, one pass per int8 limb of Ahat (instances with fewer
+// limbs skip the later passes).
+hipError_t launch_eval_gemm(const pdbo_ctx* c, const TileDev* tiles, int ntiles,
+                            const InstDev* insts, hipStream_t s) {
+  int L = 1;
+  for (const InstDev& I : c->insts_h) L = std::max(L, I.nlimb);
+  for (int l = 0; l < L; ++l) {
+    hipError_t e = launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, tiles, ntiles, insts, l, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 pdbo_status dense_one_step(pdbo_ctx* c) {
   const bool do_eval = ((c->t_host + 1) % c->eval_every) == 0;
   const int ninst = (int)c->insts_h.size();
   const bool incr = c->incr_off.back() > 0;  // every instance, eval_every = 1
   const bool full = do_eval && (!incr || c->t_host < c->full_until);
   TimedLaunch tl;
+  if (c->par.dual_kind == PDBO_DUAL_SCALAR)
+    HIPCHK(c, launch_dual_scalar(c->insts_d, ninst, c->B, c->par.g_kind, c->parity, c->stream));
   if (c->grouped) {
     t_begin(c, tl, PDBO_K_STEP);
     HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, c->par.g_kind, c->tiles_d,
@@ -952,8 +998,7 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
       // exact differences of every restart with few rounding changes
       if (full) {
         t_begin(c, tl, PDBO_K_EVAL);
-        HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d,
-                                    (int)c->tiles_h.size(), c->insts_d, c->parity, 0, c->stream));
+        HIPCHK(c, launch_eval_gemm(c, c->tiles_d, (int)c->tiles_h.size(), c->insts_d, c->stream));
         t_end(c, tl);
       }
       if (incr) {
@@ -980,8 +1025,8 @@ pdbo_status dense_one_step(pdbo_ctx* c) {
       for (int k = 0; k < ninst; ++k) {
         if (full) {
           t_begin(c, tl, PDBO_K_EVAL);
-          HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d + c->tile_off[k],
-                                      c->tile_cnt[k], c->insts_d, c->parity, 0, c->stream));
+          HIPCHK(c, launch_eval_gemm(c, c->tiles_d + c->tile_off[k], c->tile_cnt[k], c->insts_d,
+                                     c->stream));
           t_end(c, tl);
         }
         const int w0 = c->incr_off[k], nw = c->incr_off[k + 1] - w0;
@@ -1125,7 +1170,7 @@ pdbo_status begin_ctx(pdbo_ctx* c, void* stream, const pdbo_params* p) {
 // hipGetSymbolAddress returns for the current device (the array's name is a
 // host-side stand-in, not a device address).
 constexpr size_t kNoallocScratchBytes = size_t(16) << 20;
-constexpr size_t kNoallocDescBytes = 256;  // room for one InstDev, 256-byte aligned
+constexpr size_t kNoallocDescBytes = 512;  // room for one InstDev, 256-byte aligned
 static_assert(sizeof(InstDev) <= kNoallocDescBytes, "descriptor slot");
 static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
 
@@ -1212,29 +1257,33 @@ static pdbo_status dense_init(int k, const pdbo_qubo* probs, const pdbo_params* 
     STCHK(check_qubo(&probs[i]));
     STCHK(check_params(&pars[i], probs[i].n));
     if (pars[i].B != pars[0].B || pars[i].precision != pars[0].precision ||
-        pars[i].g_kind != pars[0].g_kind || pars[i].eval_every != pars[0].eval_every)
-      return fail(nullptr, PDBO_EINVAL, "B, precision, g_kind and eval_every must agree");
+        pars[i].g_kind != pars[0].g_kind || pars[i].eval_every != pars[0].eval_every ||
+        pars[i].dual_kind != pars[0].dual_kind)
+      return fail(nullptr, PDBO_EINVAL, "B, precision, g_kind, dual_kind and eval_every must agree");
   }
   pdbo_ctx* c = new pdbo_ctx();
   c->kind = 0;
   c->grouped = grouped ? 1 : 0;
   c->full_until = full_eval_iters();
-  pdbo_status st = begin_ctx(c, stream, &pars[0]);
-  if (st == PDBO_OK) {
-    if (pars[0].tile > 0) {
-      c->cfg = pars[0].tile - 1;
-    } else {
-      std::vector<int> ns;
-      for (int i = 0; i < k; ++i) ns.push_back(probs[i].n);
-      c->cfg = default_cfg(ns, pars[0].B);
-    }
-    c->insts_h.resize(k);
-    for (int i = 0; i < k && st == PDBO_OK; ++i) {
-      DenseCanon C;
-      st = canon_dense(&probs[i], C);
-      if (st == PDBO_OK) st = setup_dense_instance(c, C, &pars[i], c->insts_h[i]);
-      c->n_of.push_back(probs[i].n);
-    }
+  if (pars[0].tile > 0) {
+    c->cfg = pars[0].tile - 1;
+  } else {
+    std::vector<int> ns;
+    for (int i = 0; i < k; ++i) ns.push_back(probs[i].n);
+    c->cfg = default_cfg(ns, pars[0].B);
+  }
+  c->insts_h.resize(k);
+  // The first instance is canonicalised (host only) before any HIP call, so
+  // that its range errors come back on any machine.
+  pdbo_status st = PDBO_OK;
+  for (int i = 0; i < k && st == PDBO_OK; ++i) {
+    DenseCanon C;
+    st = canon_dense(&probs[i], C);
+    if (st == PDBO_OK && pars[i].precision == PDBO_I8 && C.amax > 127)
+      st = fail(nullptr, PDBO_EUNSUPPORTED, "the INT8 operand form needs |Ahat_ij| <= 127");
+    if (st == PDBO_OK && i == 0) st = begin_ctx(c, stream, &pars[0]);
+    if (st == PDBO_OK) st = setup_dense_instance(c, C, &pars[i], c->insts_h[i]);
+    c->n_of.push_back(probs[i].n);
   }
   if (st == PDBO_OK && pars[0].tile == 0) {
     // autotune large problems (or when asked); PDBO_AUTOTUNE=0 keeps the heuristic
@@ -1255,7 +1304,18 @@ static pdbo_status dense_init(int k, const pdbo_qubo* probs, const pdbo_params* 
   return PDBO_OK;
 }
 
+// The persistent CSR and MaxSAT kernels are built for the quadratic and the
+// entropy g with one dual variable per coordinate.
+static pdbo_status persistent_supported(const pdbo_params* p) {
+  if (p->g_kind == PDBO_G_POLY)
+    return fail(nullptr, PDBO_EUNSUPPORTED, "the persistent kernels take the quadratic or entropy g");
+  if (p->dual_kind != PDBO_DUAL_VECTOR)
+    return fail(nullptr, PDBO_EUNSUPPORTED, "the scalar dual is built for the dense path only");
+  return PDBO_OK;
+}
+
 static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stream, pdbo_ctx** out) {
+  STCHK(persistent_supported(p));
   if (p->eval_every != 1) return fail(nullptr, PDBO_EUNSUPPORTED, "the CSR path evaluates every iteration");
   CsrCanon C;
   STCHK(canon_csr(q, C));
@@ -1338,9 +1398,9 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
     Incumbent init{kI64Max, -1, -1, 0};
     HIPCHK(c, hipMemcpyAsync(c->inc_d, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
     TempDev t;
-    STCHK(temp_upload(c, t, p->x0, (size_t)B * n * sizeof(double)));
+    STCHK(upload_x0(c, t, p->x0, (size_t)B * n));
     HIPCHK(c, launch_init_state((const double*)t.p, B, n, ld, (float)p->y0, d.X, d.Y, nullptr,
-                                P_F32, nullptr, c->stream));
+                                P_F32, nullptr, p->seed, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PDBO_OK;
   };
@@ -1444,9 +1504,15 @@ pdbo_status qubo_gda_get_state(pdbo_ctx* c, float* x, float* y, int64_t* t) {
   if (x)
     HIPCHK(c, hipMemcpy2D(x, n * sizeof(float), X, ld * sizeof(float), n * sizeof(float), c->B,
                           hipMemcpyDeviceToHost));
-  if (y)
+  if (y && c->kind == 0 && c->insts_h[0].ys) {
+    // scalar dual: every coordinate of restart b carries the restart's y
+    std::vector<float> ys(c->B);
+    HIPCHK(c, hipMemcpy(ys.data(), c->insts_h[0].ys, c->B * sizeof(float), hipMemcpyDeviceToHost));
+    for (int b = 0; b < c->B; ++b) std::fill(y + (size_t)b * n, y + (size_t)(b + 1) * n, ys[b]);
+  } else if (y) {
     HIPCHK(c, hipMemcpy2D(y, n * sizeof(float), Y, ld * sizeof(float), n * sizeof(float), c->B,
                           hipMemcpyDeviceToHost));
+  }
   if (t) *t = c->t_host;
   return PDBO_OK;
 }
@@ -1475,6 +1541,14 @@ pdbo_status qubo_gda_set_state(pdbo_ctx* c, const float* x, const float* y, int6
                              c->stream));
   c->t_host = t;
   c->full_until = t + full_eval_iters();
+  if (c->kind == 0 && y && c->insts_h[0].ys) {
+    // scalar dual: restart b's y is y[b][0]
+    std::vector<float> ys(c->B);
+    for (int b = 0; b < c->B; ++b) ys[b] = y[(size_t)b * n];
+    HIPCHK(c, hipMemcpyAsync(c->insts_h[0].ys, ys.data(), c->B * sizeof(float), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   if (c->kind == 0) {
     HIPCHK(c, hipMemcpyAsync(c->insts_h[0].t_dev, &t, sizeof(t), hipMemcpyHostToDevice, c->stream));
     // the rounded iterate no longer follows the recorded changes
@@ -1488,21 +1562,22 @@ pdbo_status qubo_gda_set_state(pdbo_ctx* c, const float* x, const float* y, int6
 pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
   if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
-  if (!x0) return fail(c, PDBO_EINVAL, "x0 is NULL");
   const int n = c->n_of[0], B = c->B;
   const size_t tot = (size_t)B * n;
-  for (size_t i = 0; i < tot; ++i)
-    if (!(x0[i] >= 0.0 && x0[i] <= 1.0)) return fail(c, PDBO_EINVAL, "x0 must lie in [0,1]");
+  if (x0)
+    for (size_t i = 0; i < tot; ++i)
+      if (!(x0[i] >= 0.0 && x0[i] <= 1.0)) return fail(c, PDBO_EINVAL, "x0 must lie in [0,1]");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   TempDev t;
-  STCHK(temp_upload(c, t, x0, tot * sizeof(double)));
+  STCHK(upload_x0(c, t, x0, tot));
   const float y0 = (float)c->par.y0;
   Incumbent init{kI64Max, -1, -1, 0};
   if (c->kind == 0) {
     InstDev& I = c->insts_h[0];
     c->parity = 0;
     HIPCHK(c, launch_init_state((const double*)t.p, B, n, I.ld, y0, I.X[0], I.Y,
-                                c->prec == PDBO_FP32 ? nullptr : I.Xs[0], c->prec, I.Xr, c->stream));
+                                c->prec == PDBO_FP32 ? nullptr : I.Xs[0], c->prec, I.Xr, c->par.seed,
+                                c->stream));
     const int64_t zero = 0;
     HIPCHK(c, hipMemcpyAsync(I.t_dev, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(I.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
@@ -1514,6 +1589,7 @@ pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
       HIPCHK(c, launch_fill_i32(I.nflip, kFlipMax + 1, B, c->stream));
       HIPCHK(c, launch_fill_i32((int32_t*)I.fbits, 0, (int64_t)B * (I.ld / 32), c->stream));
     }
+    if (I.ys) HIPCHK(c, launch_fill_i32((int32_t*)I.ys, f32_bits(y0), B, c->stream));
     c->argmin_pending = false;
   } else {
     float* X = c->kind == 1 ? c->csr.X : c->sat.X;
@@ -1522,7 +1598,7 @@ pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
     int64_t* rbF = c->kind == 1 ? c->csr.rbestF : c->sat.rbestF;
     int64_t* rbT = c->kind == 1 ? c->csr.rbestT : c->sat.rbestT;
     HIPCHK(c, launch_init_state((const double*)t.p, B, n, ld, y0, X, Y, nullptr, P_F32, nullptr,
-                                c->stream));
+                                c->par.seed, c->stream));
     HIPCHK(c, launch_fill_i64(rbF, kI64Max, B, c->stream));
     HIPCHK(c, launch_fill_i64(rbT, kI64Max, B, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->inc_d, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
@@ -1630,8 +1706,7 @@ pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F
     I.B = nb;
     HIPCHK(c, hipMemcpyAsync(c->scratch_inst_d, &I, sizeof(I), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d, (int)c->tiles_h.size(),
-                                c->scratch_inst_d, 0, 0, c->stream));
+    HIPCHK(c, launch_eval_gemm(c, c->tiles_d, (int)c->tiles_h.size(), c->scratch_inst_d, c->stream));
     HIPCHK(c, launch_argmin(c->scratch_inst_d, 0, 1, 2, c->stream));
   } else if (c->kind == 1) {
     HIPCHK(c, launch_csr_eval(c->csr, c->xr_scratch, nb, c->f_scratch, c->stream));
@@ -1668,7 +1743,7 @@ pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* c, const uint8_t* xr, int32_t nb, in
   const size_t need = kNoallocDescBytes + 2 * sizeof(int64_t) * (size_t)nb + (size_t)nb * I0.ld;
   if (need > kNoallocScratchBytes)
     return fail(c, PDBO_EUNSUPPORTED,
-                "nb * ld + 16 nb + 256 = " + std::to_string(need) + " bytes exceeds the " +
+                "nb * ld + 16 nb + 512 = " + std::to_string(need) + " bytes exceeds the " +
                     std::to_string(kNoallocScratchBytes) + "-byte scratch of qubo_gda_eval_noalloc");
   uint8_t* base = nullptr;
   STCHK(scratch_for_current_device(c, &base));
@@ -1690,8 +1765,7 @@ pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* c, const uint8_t* xr, int32_t nb, in
   hipLaunchKernelGGL(put_eval_desc_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, desc,
                      I, S, C, nb);
   HIPCHK(c, hipGetLastError());
-  HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_EVAL, 0, c->tiles_d, (int)c->tiles_h.size(), desc,
-                              0, 0, s));
+  HIPCHK(c, launch_eval_gemm(c, c->tiles_d, (int)c->tiles_h.size(), desc, s));
   HIPCHK(c, launch_argmin(desc, 0, 1, 2, s));
   return PDBO_OK;
 }
@@ -1751,6 +1825,7 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
   *out = nullptr;
   STCHK(check_maxsat(prob));
   STCHK(check_params(p, prob->n));
+  STCHK(persistent_supported(p));
   if (p->eval_every != 1) return fail(nullptr, PDBO_EUNSUPPORTED, "the MaxSAT path evaluates every iteration");
   const int n = prob->n, m = prob->m, k = prob->k;
   if (!sat_fits(n, nullptr))
@@ -1841,9 +1916,9 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
     Incumbent init{kI64Max, -1, -1, 0};
     HIPCHK(c, hipMemcpyAsync(c->inc_d, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
     TempDev t;
-    STCHK(temp_upload(c, t, p->x0, (size_t)B * n * sizeof(double)));
+    STCHK(upload_x0(c, t, p->x0, (size_t)B * n));
     HIPCHK(c, launch_init_state((const double*)t.p, B, n, ld, (float)p->y0, d.X, d.Y, nullptr,
-                                P_F32, nullptr, c->stream));
+                                P_F32, nullptr, p->seed, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PDBO_OK;
   };

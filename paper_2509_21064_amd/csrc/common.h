@@ -6,7 +6,8 @@
 //   Xr           int8 {0,1} [B][ld] rounded iterate [x > 1/2]
 //   A            canonical Ahat = offdiag(Q + Q^T)/kappa in the operand type,
 //                n rows x ld columns (columns n..ld-1 are zero)
-//   A8           the same matrix as exact int8 (evaluation operand)
+//   A8           the same matrix exactly, as nlimb int8 limbs of n x ld each
+//                (evaluation operand; one limb when every |Ahat_ij| <= 127)
 // ld is n rounded up to a multiple of 128 elements, so every row of every
 // operand is a whole number of 128-byte K chunks.
 #pragma once
@@ -41,13 +42,15 @@ struct TraceRec {
 // Alg. 1 step-size parameters, kernel-argument sized.
 struct GdaP {
   float alpha, beta, delta;
-  int gkind;        // 0 quadratic, 1 entropy
+  int gkind;        // 0 quadratic, 1 entropy, 2 polynomial
+  int deg;          // d of the polynomial g
 };
 
 // One dense instance as seen by the kernels.
 struct InstDev {
   const uint8_t* A;       // Ahat in the GEMM operand type
-  const int8_t* A8;       // Ahat as int8 (evaluation)
+  const int8_t* A8;       // Ahat as nlimb int8 limbs (evaluation): limb l at A8 + l * limb_stride,
+                          // Ahat = sum_l 256^l Ahat_l with signed digits Ahat_l in [-128, 127]
   const float* rscale;    // e4m3 row scale (FP8 form), else nullptr
   const int32_t* rsum;    // sum_j Ahat_ij (INT8 form: offset of the quantised x)
   const float* cps;       // c'/s, padded to ld with zeros
@@ -76,8 +79,15 @@ struct InstDev {
   uint32_t* fbits;        // [B][ld / 32] bitmap of the changed coordinates
   uint8_t* cand;          // [B][ld] rounded rows that beat the incumbent when evaluated
   uint64_t* ts0;          // clock at the first step
+  // Scalar dual (PDBO-s, single constraint sum_i g(x_i) = 0): one y per
+  // restart, or nullptr for the vector dual of Alg. 1.  Before each step the
+  // scalar of restart b is copied into its row of Y (which the step reads as
+  // y_i) and raised by beta * sum_i g(x_i^t).
+  float* ys;              // [B]
   int n, ld, B, mblocks;
   int kappa, trace_cap;
+  int nlimb;              // int8 limbs of Ahat (1 when every |Ahat_ij| <= 127)
+  int64_t limb_stride;    // bytes between limbs (n * ld)
   float kos;              // kappa / s
   GdaP gp;
 };
@@ -88,15 +98,32 @@ struct TileDev {
 
 // ---- device helpers -------------------------------------------------------
 
-__device__ __forceinline__ float g_value(float x, int gkind) {
+// The binarity constraint functions of Sec. 3.1: quadratic x^2 - x, entropy
+// x log x + (1-x) log(1-x) (continuous at 0 and 1), and the even polynomial
+// (2x - 1)^(2d) - 1, whose derivative is 4d (2x - 1)^(2d-1).
+__device__ __forceinline__ float poly_pow(float u2, int deg) {  // u2^(deg-1)
+  float t = 1.f;
+  for (int k = 1; k < deg; ++k) t *= u2;
+  return t;
+}
+
+__device__ __forceinline__ float g_value(float x, int gkind, int deg = 1) {
   if (gkind == 0) return x * x - x;
+  if (gkind == 2) {
+    const float u = 2.f * x - 1.f, u2 = u * u;
+    return u2 * poly_pow(u2, deg) - 1.f;
+  }
   float a = x > 0.f ? x * logf(x) : 0.f;
   float b = x < 1.f ? (1.f - x) * logf(1.f - x) : 0.f;
   return a + b;
 }
 
-__device__ __forceinline__ float g_deriv(float x, int gkind) {
+__device__ __forceinline__ float g_deriv(float x, int gkind, int deg = 1) {
   if (gkind == 0) return 2.f * x - 1.f;
+  if (gkind == 2) {
+    const float u = 2.f * x - 1.f;
+    return 4.f * (float)deg * u * poly_pow(u * u, deg);
+  }
   float xc = fminf(fmaxf(x, kEntropyEps), 1.f - kEntropyEps);
   return logf(xc) - logf(1.f - xc);
 }
@@ -105,12 +132,12 @@ __device__ __forceinline__ float g_deriv(float x, int gkind) {
 // ascent with g evaluated at the old x (simultaneous update, Eq. 6).
 __device__ __forceinline__ void gda_update(float x, float y, float G, const GdaP& p,
                                            float& xn, float& yn) {
-  float dL = fmaf(y, g_deriv(x, p.gkind), G);
+  float dL = fmaf(y, g_deriv(x, p.gkind, p.deg), G);
   bool pert = (fabsf(x - 0.5f) <= p.delta) && (fabsf(dL) <= 2.f * p.delta) && (y <= 0.f);
   float xs = fminf(fmaxf(fmaf(-p.alpha, dL, x), 0.f), 1.f);
   float xp = x <= 0.5f ? 0.5f - p.delta : 0.5f + p.delta;
   xn = pert ? xp : xs;
-  yn = fmaf(p.beta, g_value(x, p.gkind), y);
+  yn = fmaf(p.beta, g_value(x, p.gkind, p.deg), y);
 }
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
@@ -149,7 +176,10 @@ int dense_num_cfgs();
 const TileCfgInfo& dense_cfg(int id);
 
 // gkind: the kind of g (GdaP::gkind) of every instance of the launch; only the
-// step epilogue uses it
+// step epilogue uses it.  parity: the operand shadow the step and gradient
+// epilogues read (STEP, GRAD); the limb of Ahat an evaluation launch adds
+// (EVAL: pass l adds 256^l Ahat_l x_r, and c'^T x_r in pass 0; instances with
+// fewer limbs skip the pass)
 // A step launch may also run the best of B of the previous iteration for
 // instances am0 .. am0 + amn - 1 (incremental evaluation only), in amn extra
 // workgroups after the tiles.
@@ -163,13 +193,20 @@ hipError_t launch_argmin(const InstDev* insts, int inst0, int ninst, int mode, h
 hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, int full_done,
                             hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
+// Scalar dual of every restart of ninst instances (grid B x ninst): writes y^t
+// into the restart's row of Y and sets y^{t+1} = y^t + beta sum_i g(x_i^t),
+// with x^t in X[parity].
+hipError_t launch_dual_scalar(const InstDev* insts, int ninst, int B, int gkind, int parity,
+                              hipStream_t s);
 hipError_t launch_stamp(uint64_t* ts0, hipStream_t s);
+// x0 == nullptr: X^0 is drawn by Philox4x32-10 keyed by seed (pdbo_params)
 hipError_t launch_init_state(const double* x0, int B, int n, int ld, float y0, float* X,
-                             float* Y, uint8_t* Xs, int xs_prec, int8_t* Xr, hipStream_t s);
+                             float* Y, uint8_t* Xs, int xs_prec, int8_t* Xr, uint64_t seed,
+                             hipStream_t s);
 hipError_t launch_set_state(const float* x, const float* y, int B, int n, int ld, float* X,
                             float* Y, uint8_t* Xs, int xs_prec, hipStream_t s);
 hipError_t launch_quantize_A(const int32_t* Ahat, int n, int ld, int prec, uint8_t* A,
-                             int8_t* A8, const float* rscale, hipStream_t s);
+                             int8_t* A8, int nlimb, const float* rscale, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t cnt, hipStream_t s);
 
 // ---- launchers (sparse.hip) -------------------------------------------------

@@ -23,6 +23,13 @@
 
 #include "common.h"
 
+// This file is compiled four times (see build.py): part 0 holds everything but
+// the step kernels, part 1 + k the step kernels of the k-th kind of g, so that
+// the parts compile in parallel.
+#ifndef PDBO_DENSE_PART
+#define PDBO_DENSE_PART 0
+#endif
+
 namespace pdbo {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -435,6 +442,9 @@ __device__ __forceinline__ void gemm_epilogue(
       }
     }
   } else {
+    // parity is the limb: this pass adds 256^limb (Ahat_limb x_r)_i, and the
+    // linear term only in pass 0
+    const int64_t lmul = int64_t(1) << (8 * parity);
     int64_t sS[FN], sC[FN];
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) sS[fn] = sC[fn] = 0;
@@ -468,7 +478,7 @@ __device__ __forceinline__ void gemm_epilogue(
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (((r.xr[fn] >> (8 * q)) & 1u) && (i + q < n)) {
-            sS[fn] += acc[fm][fn][q];
+            sS[fn] += (int64_t)acc[fm][fn][q] * lmul;
             sC[fn] += r.cp[q];
           }
         }
@@ -483,7 +493,8 @@ __device__ __forceinline__ void gemm_epilogue(
       const int b = bbase + fn * 16;
       if (lane < 16 && b < B) {
         if (sS[fn]) atomicAdd((unsigned long long*)(I.Sacc + b), (unsigned long long)sS[fn]);
-        if (sC[fn]) atomicAdd((unsigned long long*)(I.Cacc + b), (unsigned long long)sC[fn]);
+        if (sC[fn] && parity == 0)
+          atomicAdd((unsigned long long*)(I.Cacc + b), (unsigned long long)sC[fn]);
       }
     }
   }
@@ -690,12 +701,13 @@ __global__ void __launch_bounds__(64 * WM * WN)
     const TileDev td = tiles[w];
     const InstDev& I = insts[td.inst];
     if constexpr (EPI == EPI_EVAL) {
+      if (parity >= I.nlimb) continue;
       if (I.nflip && !eval_block_needed<BN, 64 * WM * WN>(I, td.n0, threadIdx.x)) continue;
     }
     const int n = I.n, ld = I.ld, B = I.B;
     const size_t rbytes = (size_t)ld * EB;
     const int nk = (int)(rbytes / 128);
-    const uint8_t* Ag = (EPI == EPI_EVAL) ? (const uint8_t*)I.A8 : I.A;
+    const uint8_t* Ag = (EPI == EPI_EVAL) ? (const uint8_t*)I.A8 + parity * I.limb_stride : I.A;
     const uint8_t* Bg = (EPI == EPI_EVAL) ? (const uint8_t*)I.Xr : I.Xs[parity];
 
     const uint8_t* pa[APC];
@@ -836,12 +848,13 @@ __global__ void __launch_bounds__(64 * WM * WN)
     const TileDev td = tiles[w];
     const InstDev& I = insts[td.inst];
     if constexpr (EPI == EPI_EVAL) {
+      if (parity >= I.nlimb) continue;
       if (I.nflip && !eval_block_needed<BN, 64 * WM * WN>(I, td.n0, threadIdx.x)) continue;
     }
     const int n = I.n, B = I.B;
     const size_t rbytes = (size_t)I.ld * EB;
     const int nk = (int)(rbytes / 128);
-    const uint8_t* Ag = (EPI == EPI_EVAL) ? (const uint8_t*)I.A8 : I.A;
+    const uint8_t* Ag = (EPI == EPI_EVAL) ? (const uint8_t*)I.A8 + parity * I.limb_stride : I.A;
     const uint8_t* Bg = (EPI == EPI_EVAL) ? (const uint8_t*)I.Xr : I.Xs[parity];
 
     // DMA instruction j of this wave fills stage rows r0 .. r0+7, r0 = 8 (j NW + wid);
@@ -1015,16 +1028,6 @@ __global__ void __launch_bounds__(64 * WM * WN)
   X(8, 256, 128, 4, 2, 1)      \
   X(9, 64, 64, 2, 2, 1)
 
-static const TileCfgInfo kCfgs[] = {
-#define X(id, bm, bn, wm, wn, dma) \
-  {#bm "x" #bn "_w" #wm "x" #wn "_" #dma, bm, bn, wm, wn, 64 * wm * wn, dma},
-    PDBO_TILE_CFGS(X)
-#undef X
-};
-
-int dense_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
-const TileCfgInfo& dense_cfg(int id) { return kCfgs[id]; }
-
 template <int BM, int BN, int WM, int WN, int P, int EPI, int DMA, int GK>
 static hipError_t launch_one(const TileDev* tiles, int ntiles, const InstDev* insts, int parity,
                              int grid, hipStream_t s, int am0, int amn) {
@@ -1051,29 +1054,79 @@ static hipError_t launch_one(const TileDev* tiles, int ntiles, const InstDev* in
   return hipGetLastError();
 }
 
-// The step kernels come in one variant per kind of g (GK); the others do not
-// use g and take GK = 0.
+// Step launches of one kind of g (0 quadratic, 1 entropy, 2 polynomial), each
+// defined in its own part.
+hipError_t launch_step_g0(int cfg, int prec, const TileDev* tiles, int ntiles, const InstDev* insts,
+                          int parity, int grid, hipStream_t s, int am0, int amn);
+hipError_t launch_step_g1(int cfg, int prec, const TileDev* tiles, int ntiles, const InstDev* insts,
+                          int parity, int grid, hipStream_t s, int am0, int amn);
+hipError_t launch_step_g2(int cfg, int prec, const TileDev* tiles, int ntiles, const InstDev* insts,
+                          int parity, int grid, hipStream_t s, int am0, int amn);
+
+#if PDBO_DENSE_PART >= 1
+#if PDBO_DENSE_PART == 1
+#define PDBO_STEP_FN launch_step_g0
+#elif PDBO_DENSE_PART == 2
+#define PDBO_STEP_FN launch_step_g1
+#else
+#define PDBO_STEP_FN launch_step_g2
+#endif
+// The kind of g of this part's step kernels is a compile-time constant: read at
+// run time it made the compiler evaluate every form of g and g' for each
+// element.
 template <int BM, int BN, int WM, int WN, int DMA>
-static hipError_t launch_cfg(int prec, int epi, int gkind, const TileDev* tiles, int ntiles,
-                             const InstDev* insts, int parity, int grid, hipStream_t s, int am0,
-                             int amn) {
-#define PDBO_L(P, E, G) \
-  launch_one<BM, BN, WM, WN, P, E, DMA, G>(tiles, ntiles, insts, parity, grid, s, am0, amn)
-  if (epi == EPI_EVAL) return PDBO_L(P_I8, EPI_EVAL, 0);
-  const int g = (epi == EPI_STEP && gkind != 0) ? 1 : 0;
-  switch ((prec * 2 + epi) * 2 + g) {
-    case (P_F32 * 2 + EPI_STEP) * 2: return PDBO_L(P_F32, EPI_STEP, 0);
-    case (P_F32 * 2 + EPI_STEP) * 2 + 1: return PDBO_L(P_F32, EPI_STEP, 1);
-    case (P_F32 * 2 + EPI_GRAD) * 2: return PDBO_L(P_F32, EPI_GRAD, 0);
-    case (P_BF16 * 2 + EPI_STEP) * 2: return PDBO_L(P_BF16, EPI_STEP, 0);
-    case (P_BF16 * 2 + EPI_STEP) * 2 + 1: return PDBO_L(P_BF16, EPI_STEP, 1);
-    case (P_BF16 * 2 + EPI_GRAD) * 2: return PDBO_L(P_BF16, EPI_GRAD, 0);
-    case (P_FP8 * 2 + EPI_STEP) * 2: return PDBO_L(P_FP8, EPI_STEP, 0);
-    case (P_FP8 * 2 + EPI_STEP) * 2 + 1: return PDBO_L(P_FP8, EPI_STEP, 1);
-    case (P_FP8 * 2 + EPI_GRAD) * 2: return PDBO_L(P_FP8, EPI_GRAD, 0);
-    case (P_I8 * 2 + EPI_STEP) * 2: return PDBO_L(P_I8, EPI_STEP, 0);
-    case (P_I8 * 2 + EPI_STEP) * 2 + 1: return PDBO_L(P_I8, EPI_STEP, 1);
-    case (P_I8 * 2 + EPI_GRAD) * 2: return PDBO_L(P_I8, EPI_GRAD, 0);
+static hipError_t launch_step_cfg(int prec, const TileDev* tiles, int ntiles, const InstDev* insts,
+                                  int parity, int grid, hipStream_t s, int am0, int amn) {
+  constexpr int GK = PDBO_DENSE_PART - 1;
+#define PDBO_L(P) \
+  launch_one<BM, BN, WM, WN, P, EPI_STEP, DMA, GK>(tiles, ntiles, insts, parity, grid, s, am0, amn)
+  switch (prec) {
+    case P_F32: return PDBO_L(P_F32);
+    case P_BF16: return PDBO_L(P_BF16);
+    case P_FP8: return PDBO_L(P_FP8);
+    case P_I8: return PDBO_L(P_I8);
+    default: return hipErrorInvalidValue;
+  }
+#undef PDBO_L
+}
+
+hipError_t PDBO_STEP_FN(int cfg, int prec, const TileDev* tiles, int ntiles, const InstDev* insts,
+                        int parity, int grid, hipStream_t s, int am0, int amn) {
+  switch (cfg) {
+#define X(id, bm, bn, wm, wn, dma) \
+  case id:                         \
+    return launch_step_cfg<bm, bn, wm, wn, dma>(prec, tiles, ntiles, insts, parity, grid, s, am0, amn);
+    PDBO_TILE_CFGS(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+#endif  // PDBO_DENSE_PART >= 1
+
+#if PDBO_DENSE_PART == 0
+static const TileCfgInfo kCfgs[] = {
+#define X(id, bm, bn, wm, wn, dma) \
+  {#bm "x" #bn "_w" #wm "x" #wn "_" #dma, bm, bn, wm, wn, 64 * wm * wn, dma},
+    PDBO_TILE_CFGS(X)
+#undef X
+};
+
+int dense_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
+const TileCfgInfo& dense_cfg(int id) { return kCfgs[id]; }
+
+// Gradient and evaluation launches (the kernels that do not use g).
+template <int BM, int BN, int WM, int WN, int DMA>
+static hipError_t launch_cfg(int prec, int epi, const TileDev* tiles, int ntiles,
+                             const InstDev* insts, int parity, int grid, hipStream_t s) {
+#define PDBO_L(P, E) launch_one<BM, BN, WM, WN, P, E, DMA, 0>(tiles, ntiles, insts, parity, grid, s, 0, 0)
+  if (epi == EPI_EVAL) return PDBO_L(P_I8, EPI_EVAL);
+  if (epi != EPI_GRAD) return hipErrorInvalidValue;
+  switch (prec) {
+    case P_F32: return PDBO_L(P_F32, EPI_GRAD);
+    case P_BF16: return PDBO_L(P_BF16, EPI_GRAD);
+    case P_FP8: return PDBO_L(P_FP8, EPI_GRAD);
+    case P_I8: return PDBO_L(P_I8, EPI_GRAD);
     default: return hipErrorInvalidValue;
   }
 #undef PDBO_L
@@ -1082,11 +1135,18 @@ static hipError_t launch_cfg(int prec, int epi, int gkind, const TileDev* tiles,
 hipError_t launch_dense_gemm(int cfg, int prec, int epi, int gkind, const TileDev* tiles,
                              int ntiles, const InstDev* insts, int parity, int grid, hipStream_t s,
                              int am0, int amn) {
+  if (epi == EPI_STEP) {
+    switch (gkind) {
+      case 0: return launch_step_g0(cfg, prec, tiles, ntiles, insts, parity, grid, s, am0, amn);
+      case 1: return launch_step_g1(cfg, prec, tiles, ntiles, insts, parity, grid, s, am0, amn);
+      case 2: return launch_step_g2(cfg, prec, tiles, ntiles, insts, parity, grid, s, am0, amn);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (cfg) {
-#define X(id, bm, bn, wm, wn, dma)                                                            \
-  case id:                                                                                    \
-    return launch_cfg<bm, bn, wm, wn, dma>(prec, epi, gkind, tiles, ntiles, insts, parity, grid, \
-                                           s, am0, amn);
+#define X(id, bm, bn, wm, wn, dma) \
+  case id:                         \
+    return launch_cfg<bm, bn, wm, wn, dma>(prec, epi, tiles, ntiles, insts, parity, grid, s);
     PDBO_TILE_CFGS(X)
 #undef X
     default:
@@ -1133,13 +1193,40 @@ __device__ __forceinline__ void store_shadow(uint8_t* Xs, size_t off, float v, i
   }
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of
+// (c0, c1, c2, c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
+// lo(M0 c0)) with the key raised by the Weyl constants between rounds.  The
+// starting point of coordinate i of restart b is word i mod 4 of the output for
+// the counter (i / 4, b, 0, 0) under the key (seed lo, seed hi), scaled to a
+// multiple of 2^-24 in [0, 1) (App. C: x^0 uniform on [0,1]^n).
+__device__ float philox_start(uint64_t seed, uint32_t b, uint32_t i) {
+  uint32_t c0 = i >> 2, c1 = b, c2 = 0u, c3 = 0u;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+  }
+  const uint32_t w = (i & 3u) == 0u ? c0 : (i & 3u) == 1u ? c1 : (i & 3u) == 2u ? c2 : c3;
+  return (float)(w >> 8) * 5.9604644775390625e-08f;  // 2^-24
+}
+
 __global__ void init_state_kernel(const double* __restrict__ x0, int B, int n, int ld, float y0,
-                                  float* X, float* Y, uint8_t* Xs, int prec, int8_t* Xr) {
+                                  float* X, float* Y, uint8_t* Xs, int prec, int8_t* Xr,
+                                  uint64_t seed) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)B * n) return;
   const int b = (int)(idx / n), i = (int)(idx % n);
   const size_t off = (size_t)b * ld + i;
-  const float x = (float)x0[idx];
+  const float x = x0 ? (float)x0[idx] : philox_start(seed, (uint32_t)b, (uint32_t)i);
   X[off] = x;
   Y[off] = y0;
   store_shadow(Xs, off, x, prec);
@@ -1147,11 +1234,12 @@ __global__ void init_state_kernel(const double* __restrict__ x0, int B, int n, i
 }
 
 hipError_t launch_init_state(const double* x0, int B, int n, int ld, float y0, float* X,
-                             float* Y, uint8_t* Xs, int xs_prec, int8_t* Xr, hipStream_t s) {
+                             float* Y, uint8_t* Xs, int xs_prec, int8_t* Xr, uint64_t seed,
+                             hipStream_t s) {
   const size_t tot = (size_t)B * n;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(init_state_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x0,
-                     B, n, ld, y0, X, Y, Xs, xs_prec, Xr);
+                     B, n, ld, y0, X, Y, Xs, xs_prec, Xr, seed);
   return hipGetLastError();
 }
 
@@ -1178,13 +1266,23 @@ hipError_t launch_set_state(const float* x, const float* y, int B, int n, int ld
 }
 
 // Ahat (int32, n x n) -> operand copy (n x ld, zero padded) and the int8 copy.
+// The int8 copy is written as nlimb signed base-256 digits: digit l is the
+// sign-extended low byte of r_l, r_{l+1} = (r_l - digit_l) / 256, r_0 = v.
 __global__ void quantize_A_kernel(const int32_t* __restrict__ Ah, int n, int ld, int prec,
-                                  uint8_t* A, int8_t* A8, const float* __restrict__ rscale) {
+                                  uint8_t* A, int8_t* A8, int nlimb,
+                                  const float* __restrict__ rscale) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n * ld) return;
   const int i = (int)(idx / ld), k = (int)(idx % ld);
   const int32_t v = k < n ? Ah[(size_t)i * n + k] : 0;
-  if (A8) A8[idx] = (int8_t)v;
+  if (A8) {
+    int64_t r = v;
+    for (int l = 0; l < nlimb; ++l) {
+      const int8_t d = (int8_t)(r & 0xff);
+      A8[(size_t)l * n * ld + idx] = d;
+      r = (r - d) / 256;
+    }
+  }
   if (!A) return;
   if (prec == P_F32) {
     ((float*)A)[idx] = (float)v;
@@ -1197,10 +1295,10 @@ __global__ void quantize_A_kernel(const int32_t* __restrict__ Ah, int n, int ld,
 }
 
 hipError_t launch_quantize_A(const int32_t* Ahat, int n, int ld, int prec, uint8_t* A,
-                             int8_t* A8, const float* rscale, hipStream_t s) {
+                             int8_t* A8, int nlimb, const float* rscale, hipStream_t s) {
   const size_t tot = (size_t)n * ld;
   hipLaunchKernelGGL(quantize_A_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Ahat,
-                     n, ld, prec, A, A8, rscale);
+                     n, ld, prec, A, A8, nlimb, rscale);
   return hipGetLastError();
 }
 
@@ -1266,28 +1364,31 @@ __device__ int64_t objective_by_rows(const InstDev& I, const PDBO_GLOBAL int8_t*
       const int m = *cnt;  // at most 4 * NT
       if (v0 == 0)
         for (int e = tid; e < m; e += NT) accC += *gptr(I.cp + lst[e]);
-      for (int g = 0; g < m; g += E) {
-        u32x4 a[E][V];
+      for (int l = 0; l < I.nlimb; ++l) {  // limb l adds 256^l (Ahat_l x')_i
+        const PDBO_GLOBAL int8_t* Al = A8 + l * I.limb_stride;
+        for (int g = 0; g < m; g += E) {
+          u32x4 a[E][V];
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
-          const PDBO_GLOBAL int8_t* arow = A8 + (size_t)lst[min(g + j, m - 1)] * ld;
+          for (int j = 0; j < E; ++j) {
+            const PDBO_GLOBAL int8_t* arow = Al + (size_t)lst[min(g + j, m - 1)] * ld;
 #pragma unroll
-          for (int v = 0; v < V; ++v)
-            a[j][v] =
-                *(const PDBO_GLOBAL u32x4*)(arow + (size_t)min(v0 + v * NT + tid, nv - 1) * 16);
-        }
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-          if (g + j >= m) break;
-          int d = 0;
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            d = __builtin_amdgcn_sdot4((int)a[j][v].x, (int)x[v].x, d, false);
-            d = __builtin_amdgcn_sdot4((int)a[j][v].y, (int)x[v].y, d, false);
-            d = __builtin_amdgcn_sdot4((int)a[j][v].z, (int)x[v].z, d, false);
-            d = __builtin_amdgcn_sdot4((int)a[j][v].w, (int)x[v].w, d, false);
+            for (int v = 0; v < V; ++v)
+              a[j][v] =
+                  *(const PDBO_GLOBAL u32x4*)(arow + (size_t)min(v0 + v * NT + tid, nv - 1) * 16);
           }
-          accS += d;
+#pragma unroll
+          for (int j = 0; j < E; ++j) {
+            if (g + j >= m) break;
+            int d = 0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              d = __builtin_amdgcn_sdot4((int)a[j][v].x, (int)x[v].x, d, false);
+              d = __builtin_amdgcn_sdot4((int)a[j][v].y, (int)x[v].y, d, false);
+              d = __builtin_amdgcn_sdot4((int)a[j][v].z, (int)x[v].z, d, false);
+              d = __builtin_amdgcn_sdot4((int)a[j][v].w, (int)x[v].w, d, false);
+            }
+            accS += (int64_t)d << (8 * l);
+          }
         }
       }
       __syncthreads();  // every thread is done with lst
@@ -1401,11 +1502,18 @@ __global__ void __launch_bounds__(kIncrThreads)
   const int xi = xrow[ci];
   const int pe = min(tid / kk, kk - 1), pf = tid - (tid / kk) * kk;
   const int pie = fl[pe], pjf = fl[pf];
-  const int pa = A8[(size_t)pie * ld + pjf];
+  int64_t pa = A8[(size_t)pie * ld + pjf];
+  for (int l = 1; l < I.nlimb; ++l)
+    pa += (int64_t)A8[l * I.limb_stride + (size_t)pie * ld + pjf] << (8 * l);
   const int pxe = xrow[pie], pxf = xrow[pjf];
   const bool pair_ok = tid < kk * kk && tid / kk < pf;
 
-  // red[w][e]: wave w's part of (Ahat x')_i for change e, summed over passes
+  // red[w][e]: wave w's part of (Ahat_l x')_i for change e, summed over
+  // passes; dsum (thread e < kk): (Ahat x')_i = sum over limbs l of 256^l times
+  // the total over waves
+  int64_t dsum = 0;
+  for (int l = 0; l < I.nlimb; ++l) {
+  const PDBO_GLOBAL int8_t* Al = A8 + l * I.limb_stride;
   if (lane < kFlipMax) red[wid][lane] = 0;
   for (int v0 = 0; v0 < nv; v0 += NT * V) {
     // chunks past the row end are loaded at the last chunk and x is zeroed there
@@ -1418,7 +1526,7 @@ __global__ void __launch_bounds__(kIncrThreads)
       u32x4 a[E][V];
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        const PDBO_GLOBAL int8_t* arow = A8 + (size_t)fl[min(g + j, kk - 1)] * ld;
+        const PDBO_GLOBAL int8_t* arow = Al + (size_t)fl[min(g + j, kk - 1)] * ld;
 #pragma unroll
         for (int v = 0; v < V; ++v)
           a[j][v] = *(const PDBO_GLOBAL u32x4*)(arow + (size_t)min(v0 + v * NT + tid, nv - 1) * 16);
@@ -1442,20 +1550,26 @@ __global__ void __launch_bounds__(kIncrThreads)
     }
   }
   __syncthreads();
-  int64_t acc64 = 0;
   if (tid < kk) {
     int d = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) d += red[w][tid];
-    acc64 = (xi ? 1 : -1) * (cpi + (int64_t)I.kappa * d);
+    dsum += (int64_t)d << (8 * l);
   }
+  __syncthreads();  // red is cleared for the next limb
+  }
+  int64_t acc64 = 0;
+  if (tid < kk) acc64 = (xi ? 1 : -1) * (cpi + (int64_t)I.kappa * dsum);
   if (pair_ok) acc64 -= (int64_t)I.kappa * ((pxe ? 1 : -1) * (pxf ? 1 : -1) * pa);
   for (int pq = tid + NT; pq < kk * kk; pq += NT) {
     const int e = pq / kk, f = pq % kk;
     if (e < f) {
       const int ie = fl[e], jf = fl[f];
       const int de = xrow[ie] ? 1 : -1, df = xrow[jf] ? 1 : -1;
-      acc64 -= (int64_t)I.kappa * de * df * (int)A8[(size_t)ie * ld + jf];
+      int64_t a = A8[(size_t)ie * ld + jf];
+      for (int l = 1; l < I.nlimb; ++l)
+        a += (int64_t)A8[l * I.limb_stride + (size_t)ie * ld + jf] << (8 * l);
+      acc64 -= (int64_t)I.kappa * de * df * a;
     }
   }
 #pragma unroll
@@ -1473,6 +1587,48 @@ hipError_t launch_eval_incr(const InstDev* insts, const int2* work, int nwork, i
   if (nwork == 0) return hipSuccess;
   hipLaunchKernelGGL(eval_incr_kernel, dim3(nwork), dim3(kIncrThreads), 0, s, insts, work,
                      full_done);
+  return hipGetLastError();
+}
+
+// The dual step of the single-constraint variant (PDBO-s): y of restart b is
+// one number, raised by beta times sum_i g(x_i^t) (the constraint's value at
+// the old x, as in the simultaneous update of Alg. 1).  The sum is taken in
+// float64 in a fixed order (strided per thread, then a tree), so runs are
+// reproducible.  y^t is first copied into the restart's row of Y, where the
+// step kernel reads it for the perturbation test and dL/dx_i = G_i + y g'(x_i).
+template <int GK>
+__global__ void __launch_bounds__(256) dual_scalar_kernel(const InstDev* __restrict__ insts,
+                                                          int parity) {
+  __shared__ double red[256];
+  const InstDev& I = insts[blockIdx.y];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (b >= I.B) return;
+  const float* x = I.X[parity] + (size_t)b * I.ld;
+  float* y = I.Y + (size_t)b * I.ld;
+  const float yb = I.ys[b];
+  double acc = 0.0;
+  for (int i = tid; i < I.n; i += 256) {
+    acc += (double)g_value(x[i], GK, I.gp.deg);
+    y[i] = yb;
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) I.ys[b] = (float)((double)yb + (double)I.gp.beta * red[0]);
+}
+
+hipError_t launch_dual_scalar(const InstDev* insts, int ninst, int B, int gkind, int parity,
+                              hipStream_t s) {
+  const dim3 grid(B, ninst);
+  if (gkind == 0)
+    hipLaunchKernelGGL(dual_scalar_kernel<0>, grid, dim3(256), 0, s, insts, parity);
+  else if (gkind == 1)
+    hipLaunchKernelGGL(dual_scalar_kernel<1>, grid, dim3(256), 0, s, insts, parity);
+  else
+    hipLaunchKernelGGL(dual_scalar_kernel<2>, grid, dim3(256), 0, s, insts, parity);
   return hipGetLastError();
 }
 
@@ -1499,5 +1655,7 @@ hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t cnt, hipStream_t s) {
                      cnt);
   return hipGetLastError();
 }
+
+#endif  // PDBO_DENSE_PART == 0
 
 }  // namespace pdbo

@@ -274,8 +274,8 @@ __global__ void __launch_bounds__(512)
       dx[(size_t)b * ldo + i] = g;
     } else {
       const float yi = Yv[(size_t)b * ldx + i];
-      dx[(size_t)b * ldo + i] = scale * fmaf(yi, g_deriv(xi, D.gp.gkind), g);
-      dy[(size_t)b * ldo + i] = scale * g_value(xi, D.gp.gkind);
+      dx[(size_t)b * ldo + i] = scale * fmaf(yi, g_deriv(xi, D.gp.gkind, D.gp.deg), g);
+      dy[(size_t)b * ldo + i] = scale * g_value(xi, D.gp.gkind, D.gp.deg);
     }
   }
 }
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(256)
     }
     acc += (double)D.w[j] * (double)prod * (double)D.ios;
   }
-  for (int i = tid; i < D.n; i += 256) acc += (double)yb[i] * (double)g_value(xb[i], D.gp.gkind);
+  for (int i = tid; i < D.n; i += 256) acc += (double)yb[i] * (double)g_value(xb[i], D.gp.gkind, D.gp.deg);
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();

@@ -28,10 +28,15 @@ def normwise(G, G64):
 def lockstep_compare(X, Y, G64, Xg, Yg, p, gtol_abs):
     """Compares one GPU iteration (Xg, Yg) from float32 inputs (X, Y) with the
     oracle's iteration from the same inputs.  Coordinates whose branch of Alg. 1
-    could flip within the gradient tolerance are excluded and counted."""
-    g = by_name(p.get("g", "quad"))
+    could flip within the gradient tolerance are excluded and counted.  With
+    the scalar dual, Y and Yg carry restart b's y in every coordinate of row b."""
+    g = gda.constraint_fn(p)
     d = p["delta"]
-    Xn, Yn, dL = gda.alg1_update(X, Y, G64, p["alpha"], p["beta"], d, g)
+    dual = p.get("dual", "vector")
+    Xn, Yn, dL = gda.alg1_update(X, Y[:, :1] if dual == "scalar" else Y, G64, p["alpha"],
+                                 p["beta"], d, g, dual)
+    if dual == "scalar":
+        Yn = np.broadcast_to(Yn, Yg.shape)
     # |x - 1/2| <= delta and y <= 0 are decided exactly in float32 and float64
     # on the same float32 inputs; only |dL| <= 2 delta depends on the gradient
     eps = 4e-7

@@ -49,7 +49,8 @@ int main(void) {
   printf("pdbo_qubo %zu\npdbo_maxsat %zu\npdbo_params %zu\npdbo_result %zu\n",
          sizeof(pdbo_qubo), sizeof(pdbo_maxsat), sizeof(pdbo_params), sizeof(pdbo_result));
   P(pdbo_qubo, nnz) P(pdbo_qubo, c) P(pdbo_params, alpha) P(pdbo_params, scale)
-  P(pdbo_params, tile) P(pdbo_params, x0) P(pdbo_result, best_iter) P(pdbo_result, best_x)
+  P(pdbo_params, tile) P(pdbo_params, x0) P(pdbo_params, g_degree) P(pdbo_params, dual_kind)
+  P(pdbo_params, seed) P(pdbo_result, best_iter) P(pdbo_result, best_x)
   P(pdbo_maxsat, lits) P(pdbo_maxsat, w)
   return 0;
 }
@@ -99,11 +100,14 @@ def _base():
 @pytest.mark.parametrize("field,value", [
     ("B", 0), ("alpha", 0.0), ("beta", -1.0), ("y0", 0.0), ("delta", 0.5), ("delta", 0.0),
     ("scale", 0.0), ("alpha", float("nan")), ("eval_every", 0), ("graph_chunk", 3), ("tile", 99),
+    ("g_degree", 0), ("g_degree", 17),
 ])
 def test_invalid_params(lib, field, value):
     q, p, x0 = _base()
     p = dict(p)
     p[field] = value
+    if field == "g_degree":
+        p["g"] = "poly"
     if field == "B":
         x0 = x0[:0]
     assert _init(lib, q, p, x0) == _abi.PDBO_EINVAL
@@ -116,7 +120,11 @@ def test_invalid_x0(lib):
     assert _init(lib, q, p, bad) == _abi.PDBO_EINVAL
     bad[1, 3] = float("nan")
     assert _init(lib, q, p, bad) == _abi.PDBO_EINVAL
-    assert _init(lib, q, p, None) == _abi.PDBO_EINVAL
+    # no x0: the library draws the starting points (on the CPU the first
+    # device allocation then fails)
+    import torch
+    if not torch.cuda.is_available():
+        assert _init(lib, q, p, None) in (_abi.PDBO_EDEVICE, _abi.PDBO_ENOMEM)
 
 
 def test_invalid_csr(lib):
@@ -141,6 +149,27 @@ def test_exactness_guard(lib):
     Q = q.Q.copy()
     Q[2, 3] = 1 << 30
     assert _init(lib, W.Qubo(n=q.n, Q=Q, c=None), p, x0) == _abi.PDBO_ERANGE
+
+
+def test_limb_range_guards(lib):
+    """Dense: |Ahat_ij| beyond the four int8 limbs (2,139,062,143) is ERANGE,
+    and a row of |Ahat| summing to 2^31 or more is ERANGE; the INT8 operand
+    form with |Ahat_ij| > 127 is EUNSUPPORTED.  All decided on the host, before
+    any HIP call, so on any machine."""
+    q, p, x0 = _base()
+    Q = q.Q.copy()
+    Q[:] = 0
+    # A_01 = Q_01 + Q_10 = 2^31 - 3, odd (kappa = 1): above the limb range,
+    # while its row sum stays below 2^31
+    Q[0, 1], Q[1, 0] = (1 << 30) - 1, (1 << 30) - 2
+    assert _init(lib, W.Qubo(n=q.n, Q=Q, c=None), p, x0) == _abi.PDBO_ERANGE
+    Q[:] = 0
+    Q[0, 1:] = (1 << 30) - 1  # a row of |A| far above 2^31
+    assert _init(lib, W.Qubo(n=q.n, Q=Q, c=None), p, x0) == _abi.PDBO_ERANGE
+    Q[:] = 0
+    Q[0, 1] = 201  # A_01 = 201: two limbs, fine for FP32, not for the INT8 form
+    assert _init(lib, W.Qubo(n=q.n, Q=Q, c=None), dict(p, precision="i8"), x0) == \
+        _abi.PDBO_EUNSUPPORTED
 
 
 def test_invalid_maxsat(lib):

@@ -72,7 +72,7 @@ def test_noalloc_sparse_and_maxsat_match_eval():
 
 
 def test_noalloc_size_limit():
-    """nb * ld + 16 nb + 256 bytes beyond the 16 MiB scratch: PDBO_EUNSUPPORTED,
+    """nb * ld + 16 nb + 512 bytes beyond the 16 MiB scratch: PDBO_EUNSUPPORTED,
     raised on the host before any launch."""
     import torch
     P = require_gpu()

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Qubo", "MaxSat", "rng_for", "x0_uniform",
     "gnp_pm1", "qubo_c1", "qubo_c1_twin", "maxcut_c2", "qubo_c3", "batch_c4",
-    "maxsat_c5", "random_dense_qubo", "random_maxsat",
+    "maxsat_c5", "random_dense_qubo", "random_asym_qubo", "random_maxsat",
 ]
 
 
@@ -158,6 +158,14 @@ def random_dense_qubo(n: int, lo: int, hi: int, rng: np.random.Generator,
             Q[bj:bj + bs, bi:bi + bs] = Q[bi:bi + bs, bj:bj + bs].T
     c = rng.integers(lo, hi + 1, size=n).astype(np.int64) if with_c else None
     return Qubo(n=n, Q=Q, c=c, name=f"dense_u{lo}_{hi}_n{n}")
+
+
+def random_asym_qubo(n: int, lo: int, hi: int, rng: np.random.Generator) -> Qubo:
+    """Dense Q with independent entries U{lo..hi} (asymmetric, diagonal
+    included) and c ~ U{lo..hi}."""
+    Q = rng.integers(lo, hi + 1, size=(n, n), dtype=np.int64).astype(np.int32)
+    c = rng.integers(lo, hi + 1, size=n).astype(np.int64)
+    return Qubo(n=n, Q=Q, c=c, name=f"asym_u{lo}_{hi}_n{n}")
 
 
 def qubo_c3(rep: int = 0, n: int = 10000) -> Qubo:
