@@ -56,6 +56,8 @@ typedef struct pdbo_ctx pdbo_ctx;
 enum { PDBO_DENSE = 0, PDBO_CSR = 1 };
 enum { PDBO_G_QUAD = 0, PDBO_G_ENTROPY = 1, PDBO_G_POLY = 2 };
 enum { PDBO_DUAL_VECTOR = 0, PDBO_DUAL_SCALAR = 1 };
+/* values of pdbo_params.tile for CSR instances */
+enum { PDBO_CSR_AUTO = 0, PDBO_CSR_RESIDENT = 1, PDBO_CSR_ROWS = 2 };
 enum { PDBO_FP32 = 0, PDBO_BF16 = 1, PDBO_FP8 = 2, PDBO_I8 = 3 };
 
 /*
@@ -118,9 +120,14 @@ typedef struct {
  *              stored exactly.
  *   eval_every evaluate round(x^t) every eval_every iterations (>= 1); the
  *              persistent CSR and MaxSAT paths require 1.
- *   tile       dense tile configuration id (0 = default for the shape).
- *   graph_chunk  dense path: 0 = eager launches; K > 0 (even) = capture K
- *              iterations in one hipGraph and replay it.
+ *   tile       dense: tile configuration id (0 = default for the shape).
+ *              CSR: PDBO_CSR_RESIDENT (one workgroup per restart for all T
+ *              iterations, x in LDS; n <= 32768, quadratic or entropy g),
+ *              PDBO_CSR_ROWS (one launch per iteration over all rows, the
+ *              restarts of a row in adjacent lanes; any n, any g), or
+ *              PDBO_CSR_AUTO (resident when it fits and B >= 128).
+ *   graph_chunk  dense and row-parallel CSR paths: 0 = eager launches;
+ *              K > 0 (even) = capture K iterations in one hipGraph and replay it.
  *   g_degree   d of PDBO_G_POLY, in [1, 16]; ignored for the other kinds.
  *   dual_kind  PDBO_DUAL_VECTOR: one dual variable per coordinate (Alg. 1);
  *              PDBO_DUAL_SCALAR: one per restart for the single constraint
@@ -173,7 +180,8 @@ typedef struct {
  * |c'| summing to 2^31 or more; dense: |Ahat_ij| above 2,139,062,143, the range
  * of the four int8 limbs Ahat = sum_l 256^l Ahat_l that the exact evaluation
  * multiplies one by one); EUNSUPPORTED for a CSR instance too large for the
- * on-chip resident kernel, or the INT8 form with |Ahat_ij| > 127.  The dense
+ * restart-resident kernel when that kernel is asked for, or the INT8 form with
+ * |Ahat_ij| > 127.  The dense
  * instance is canonicalised before any HIP call, so its range errors come back
  * on any machine.  `stream` is a hipStream_t (NULL = default). */
 PDBO_API pdbo_status qubo_gda_init(const pdbo_qubo* prob, const pdbo_params* par, void* stream,

@@ -40,6 +40,7 @@ UNITS = [
     ("dense.hip", "dense_p3.o", ["-DPDBO_DENSE_PART=3"]),
     ("sparse.hip", "sparse.o", []),
     ("maxsat.hip", "maxsat.o", []),
+    ("spmm.hip", "spmm.o", []),
     ("api.hip", "api.o", []),
 ]
 SOURCES = sorted({u[0] for u in UNITS})

@@ -31,23 +31,31 @@ thread_local std::string g_last_error;
 
 constexpr int kTraceCap = 4096;
 constexpr int kMaxLimbs = 4;  // int8 limbs of the dense exact evaluation
+// the automatic CSR choice gives each restart a workgroup of its own only when
+// there are enough restarts to occupy the chip
+constexpr int kResidentMinB = 128;
 constexpr int64_t kI64Max = LLONG_MAX;
 
 int roundup(int v, int a) { return (v + a - 1) / a * a; }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Allocation counter for fault injection (PDBO_FAIL_ALLOC_AT=k fails the k-th
-// device allocation of the process with PDBO_ENOMEM).
+// Fault injection for tests: PDBO_FAIL_ALLOC_AT=k makes the k-th device
+// allocation after the variable last changed value fail with PDBO_ENOMEM
+// (0 or unset: none fails).
 std::mutex g_alloc_mu;
 long g_alloc_count = 0;
+std::string g_alloc_env;
 
 bool inject_alloc_failure() {
-  static long fail_at = [] {
-    const char* e = std::getenv("PDBO_FAIL_ALLOC_AT");
-    return e ? std::atol(e) : 0L;
-  }();
+  const char* e = std::getenv("PDBO_FAIL_ALLOC_AT");
+  const std::string v = e ? e : "";
   std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (v != g_alloc_env) {
+    g_alloc_env = v;
+    g_alloc_count = 0;
+  }
+  const long fail_at = v.empty() ? 0L : std::atol(v.c_str());
   ++g_alloc_count;
   return fail_at > 0 && g_alloc_count == fail_at;
 }
@@ -60,7 +68,7 @@ struct TimedLaunch {
 };
 
 struct pdbo_ctx {
-  int kind = 0;  // 0 dense (one or many instances), 1 CSR, 2 MaxSAT
+  int kind = 0;  // 0 dense (one or many instances), 1 CSR resident, 2 MaxSAT, 3 CSR row-parallel
   hipStream_t stream = nullptr;
   std::string err;
   pdbo_params par{};
@@ -97,7 +105,9 @@ struct pdbo_ctx {
   // this one (the transient after init or set_state, when many rounded
   // coordinates change); later iterations evaluate such restarts by rows
   int64_t full_until = 0;
-  // CSR / MaxSAT persistent
+  // CSR / MaxSAT persistent (kind 1, 2); row-parallel CSR (kind 3) keeps its
+  // iterates in spmm and the canonical matrix also in csr (for qubo_gda_eval)
+  SpmmDev spmm{};
   CsrDev csr{};
   bool compact = false;
   SatDev sat{};
@@ -1306,6 +1316,10 @@ static pdbo_status dense_init(int k, const pdbo_qubo* probs, const pdbo_params* 
 
 // The persistent CSR and MaxSAT kernels are built for the quadratic and the
 // entropy g with one dual variable per coordinate.
+static bool persistent_ok(const pdbo_params* p) {
+  return p->g_kind != PDBO_G_POLY && p->dual_kind == PDBO_DUAL_VECTOR;
+}
+
 static pdbo_status persistent_supported(const pdbo_params* p) {
   if (p->g_kind == PDBO_G_POLY)
     return fail(nullptr, PDBO_EUNSUPPORTED, "the persistent kernels take the quadratic or entropy g");
@@ -1314,14 +1328,24 @@ static pdbo_status persistent_supported(const pdbo_params* p) {
   return PDBO_OK;
 }
 
+static pdbo_status spmm_init(const CsrCanon& C, const pdbo_params* p, void* stream, pdbo_ctx** out);
+
 static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stream, pdbo_ctx** out) {
-  STCHK(persistent_supported(p));
   if (p->eval_every != 1) return fail(nullptr, PDBO_EUNSUPPORTED, "the CSR path evaluates every iteration");
+  if (p->tile > PDBO_CSR_ROWS)
+    return fail(nullptr, PDBO_EINVAL, "CSR instances take tile 0 (automatic), 1 (restart-resident) "
+                                      "or 2 (row-parallel)");
   CsrCanon C;
   STCHK(canon_csr(q, C));
   const int n = q->n;
   const bool compact = n <= 65536 && C.amax <= 32767;  // packed 16-bit column / 16-bit value
-  if (!csr_fits(n, (int64_t)C.col.size(), compact, nullptr))
+  const bool fits = csr_fits(n, (int64_t)C.col.size(), compact, nullptr);
+  int path = p->tile;
+  if (path == PDBO_CSR_AUTO)
+    path = (fits && p->B >= kResidentMinB && persistent_ok(p)) ? PDBO_CSR_RESIDENT : PDBO_CSR_ROWS;
+  if (path == PDBO_CSR_ROWS) return spmm_init(C, p, stream, out);
+  STCHK(persistent_supported(p));
+  if (!fits)
     return fail(nullptr, PDBO_EUNSUPPORTED, "instance too large for the restart-resident CSR kernel");
   pdbo_ctx* c = new pdbo_ctx();
   c->kind = 1;
@@ -1415,6 +1439,176 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
   return PDBO_OK;
 }
 
+// Row-parallel CSR path (spmm.hip): node-major iterates, one launch per
+// iteration over all rows plus the best of B.
+static pdbo_status spmm_init(const CsrCanon& C, const pdbo_params* p, void* stream, pdbo_ctx** out) {
+  if (p->dual_kind != PDBO_DUAL_VECTOR)
+    return fail(nullptr, PDBO_EUNSUPPORTED, "the scalar dual is built for the dense path only");
+  const int n = C.n, B = p->B;
+  pdbo_ctx* c = new pdbo_ctx();
+  c->kind = 3;
+  c->n_of.push_back(n);
+  pdbo_status st = begin_ctx(c, stream, p);
+  auto run = [&]() -> pdbo_status {
+    const int64_t nnz = (int64_t)C.col.size();
+    SpmmDev& d = c->spmm;
+    std::memset(&d, 0, sizeof(d));
+    d.n = n;
+    d.B = B;
+    d.kappa = C.kappa;
+    d.trace_cap = kTraceCap;
+    d.kos = (float)((double)C.kappa / p->scale);
+    d.gp = make_gp(p);
+    d.W = std::min(B, 64);
+    d.G = 64 / d.W;
+    d.nslices = (B + d.W - 1) / d.W;
+    const int rows_per_wg = 4 * d.G;
+    const int nrb = (n + rows_per_wg - 1) / rows_per_wg;
+    const int gpw = std::max(1, std::min(nrb, std::max(1, 2048 / d.nslices)));
+    d.grid = gpw * d.nslices;
+    int32_t *rp = nullptr, *col = nullptr, *val = nullptr;
+    float* cps = nullptr;
+    int64_t* cp = nullptr;
+    STCHK(dalloc(c, &rp, n + 1));
+    STCHK(dalloc(c, &col, nnz));
+    STCHK(dalloc(c, &val, nnz));
+    STCHK(dalloc(c, &cps, n));
+    STCHK(dalloc(c, &cp, n));
+    std::vector<float> hcps(n);
+    for (int i = 0; i < n; ++i) hcps[i] = (float)((double)C.cp[i] / p->scale);
+    HIPCHK(c, hipMemcpyAsync(rp, C.rp.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream));
+    if (nnz > 0) {
+      HIPCHK(c, hipMemcpyAsync(col, C.col.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(val, C.val.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(cps, hcps.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cp, C.cp.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    d.row_ptr = rp;
+    d.col = col;
+    d.val = val;
+    d.cps = cps;
+    d.cp = cp;
+    const size_t sz = (size_t)n * B;
+    STCHK(dalloc(c, &d.X[0], sz));
+    STCHK(dalloc(c, &d.X[1], sz));
+    STCHK(dalloc(c, &d.Y, sz));
+    STCHK(dalloc(c, &d.part, (size_t)d.grid * 2 * d.W));
+    STCHK(dalloc(c, &d.Flast, B));
+    STCHK(dalloc(c, &d.inc, 1));
+    STCHK(dalloc(c, &d.best_x, n));
+    STCHK(dalloc(c, &d.trace, kTraceCap));
+    STCHK(dalloc(c, &d.trace_len, 1));
+    STCHK(dalloc(c, &d.t_dev, 1));
+    d.ts0 = c->ts0_d;
+    Incumbent init{kI64Max, -1, -1, 0};
+    HIPCHK(c, hipMemcpyAsync(d.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    // qubo_gda_eval of given vectors goes through the restart-major CSR kernel
+    CsrDev& e = c->csr;
+    std::memset(&e, 0, sizeof(e));
+    e.row_ptr = rp;
+    e.col = col;
+    e.val = val;
+    e.cps = cps;
+    e.cp = cp;
+    e.nnz = nnz;
+    e.n = n;
+    e.ld = roundup(n, kLdAlign);
+    e.B = B;
+    e.kappa = C.kappa;
+    e.kos = d.kos;
+    e.gp = d.gp;
+    TempDev t;
+    STCHK(upload_x0(c, t, p->x0, (size_t)B * n));
+    HIPCHK(c, launch_spmm_init((const double*)t.p, d, (float)p->y0, p->seed, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDBO_OK;
+  };
+  if (st == PDBO_OK) st = run();
+  if (st != PDBO_OK) {
+    const std::string msg = c->err.empty() ? g_last_error : c->err;
+    pdbo_destroy(c);
+    g_last_error = msg;
+    return st;
+  }
+  *out = c;
+  return PDBO_OK;
+}
+
+pdbo_status spmm_one_step(pdbo_ctx* c) {
+  TimedLaunch tl;
+  t_begin(c, tl, PDBO_K_STEP);
+  HIPCHK(c, launch_spmm(c->spmm, 0, c->parity, nullptr, c->stream));
+  t_end(c, tl);
+  t_begin(c, tl, PDBO_K_ARGMIN);
+  HIPCHK(c, launch_spmm_best(c->spmm, c->parity, 1, c->stream));
+  t_end(c, tl);
+  c->parity ^= 1;
+  c->t_host += 1;
+  return PDBO_OK;
+}
+
+// Each iteration evaluates round(x^t) in the gathers of its own gradient, so
+// after the last one the rounded x^T is evaluated by a pass of its own.
+pdbo_status spmm_steps(pdbo_ctx* c, int nsteps) {
+  const int K = c->par.graph_chunk;
+  const bool use_graph = K > 0 && !c->timing;
+  int left = nsteps;
+  while (left > 0) {
+    if (use_graph && left >= K) {
+      if (!c->gexec) {
+        // recorded on a private stream: the caller's may be the legacy default
+        if (!c->cap_stream)
+          HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const int64_t t_save = c->t_host;
+        const int par_save = c->parity;
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+          c->stream = user;
+          return hipfail(c, "hipStreamBeginCapture", e);
+        }
+        pdbo_status st = PDBO_OK;
+        for (int k = 0; k < K && st == PDBO_OK; ++k) st = spmm_one_step(c);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->stream, &g);
+        c->stream = user;
+        c->t_host = t_save;
+        c->parity = par_save;
+        if (st != PDBO_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return st;
+        }
+        if (e != hipSuccess) return hipfail(c, "hipStreamEndCapture", e);
+        c->graph = g;
+        HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+        c->graph_parity0 = par_save;
+      }
+      if (c->parity != c->graph_parity0) {
+        STCHK(spmm_one_step(c));
+        --left;
+        continue;
+      }
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      c->t_host += K;
+      c->parity ^= (K & 1);
+      left -= K;
+    } else {
+      STCHK(spmm_one_step(c));
+      --left;
+    }
+  }
+  TimedLaunch tl;
+  t_begin(c, tl, PDBO_K_EVAL);
+  HIPCHK(c, launch_spmm(c->spmm, 1, c->parity, nullptr, c->stream));
+  t_end(c, tl);
+  t_begin(c, tl, PDBO_K_ARGMIN);
+  HIPCHK(c, launch_spmm_best(c->spmm, c->parity, 0, c->stream));
+  t_end(c, tl);
+  return PDBO_OK;
+}
+
 pdbo_status qubo_gda_init(const pdbo_qubo* prob, const pdbo_params* par, void* stream,
                           pdbo_ctx** out) {
   if (!out) return fail(nullptr, PDBO_EINVAL, "out is NULL");
@@ -1439,6 +1633,7 @@ pdbo_status qubo_gda_step(pdbo_ctx* c, int32_t nsteps) {
     c->stamped = true;
   }
   if (c->kind == 0) return dense_steps(c, nsteps);
+  if (c->kind == 3) return spmm_steps(c, nsteps);
   TimedLaunch tl;
   t_begin(c, tl, PDBO_K_PERSISTENT);
   if (c->kind == 1)
@@ -1458,6 +1653,7 @@ pdbo_status qubo_gda_result(pdbo_ctx* c, pdbo_result* r) {
   }
   const int B = c->B;
   const int n = c->n_of[0];
+  if (c->kind == 3) return fill_result(c, c->spmm.inc, c->spmm.best_x, n, r);
   if (c->kind == 1)
     HIPCHK(c, launch_restart_best(c->csr.rbestF, c->csr.rbestT, c->csr.rbestTs, c->csr.best_xr, B,
                                   n, c->inc_d, c->best_x_d, c->stream));
@@ -1486,6 +1682,11 @@ static void state_ptrs(pdbo_ctx* c, float** X, float** Y, int* ld, int* n) {
     *Y = c->csr.Y;
     *ld = c->csr.ld;
     *n = c->csr.n;
+  } else if (c->kind == 3) {  // node-major: callers transpose
+    *X = c->spmm.X[c->parity];
+    *Y = c->spmm.Y;
+    *ld = c->spmm.n;
+    *n = c->spmm.n;
   } else {
     *X = c->sat.X;
     *Y = c->sat.Y;
@@ -1494,9 +1695,35 @@ static void state_ptrs(pdbo_ctx* c, float** X, float** Y, int* ld, int* n) {
   }
 }
 
+// Row-parallel CSR: node-major device arrays <-> restart-major host arrays.
+static pdbo_status spmm_download(pdbo_ctx* c, const float* src, float* dst) {
+  const int n = c->spmm.n, B = c->B;
+  std::vector<float> h((size_t)n * B);
+  HIPCHK(c, hipMemcpy(h.data(), src, h.size() * sizeof(float), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i)
+    for (int b = 0; b < B; ++b) dst[(size_t)b * n + i] = h[(size_t)i * B + b];
+  return PDBO_OK;
+}
+
+static pdbo_status spmm_upload(pdbo_ctx* c, const float* src, float* dst) {
+  const int n = c->spmm.n, B = c->B;
+  std::vector<float> h((size_t)n * B);
+  for (int i = 0; i < n; ++i)
+    for (int b = 0; b < B; ++b) h[(size_t)i * B + b] = src[(size_t)b * n + i];
+  HIPCHK(c, hipMemcpy(dst, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+  return PDBO_OK;
+}
+
 pdbo_status qubo_gda_get_state(pdbo_ctx* c, float* x, float* y, int64_t* t) {
   if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (c->kind == 3) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (x) STCHK(spmm_download(c, c->spmm.X[c->parity], x));
+    if (y) STCHK(spmm_download(c, c->spmm.Y, y));
+    if (t) *t = c->t_host;
+    return PDBO_OK;
+  }
   float *X, *Y;
   int ld, n;
   state_ptrs(c, &X, &Y, &ld, &n);
@@ -1532,6 +1759,13 @@ pdbo_status qubo_gda_set_state(pdbo_ctx* c, const float* x, const float* y, int6
     for (size_t i = 0; i < tot; ++i)
       if (!std::isfinite(y[i])) return fail(c, PDBO_EINVAL, "y must be finite");
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->kind == 3) {
+    if (x) STCHK(spmm_upload(c, x, c->spmm.X[c->parity]));
+    if (y) STCHK(spmm_upload(c, y, c->spmm.Y));
+    c->t_host = t;
+    HIPCHK(c, hipMemcpy(c->spmm.t_dev, &t, sizeof(t), hipMemcpyHostToDevice));
+    return PDBO_OK;
+  }
   TempDev tx, ty;
   if (x) STCHK(temp_upload(c, tx, x, tot * sizeof(float)));
   if (y) STCHK(temp_upload(c, ty, y, tot * sizeof(float)));
@@ -1591,6 +1825,14 @@ pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
     }
     if (I.ys) HIPCHK(c, launch_fill_i32((int32_t*)I.ys, f32_bits(y0), B, c->stream));
     c->argmin_pending = false;
+  } else if (c->kind == 3) {
+    SpmmDev& d = c->spmm;
+    c->parity = 0;
+    HIPCHK(c, launch_spmm_init((const double*)t.p, d, y0, c->par.seed, c->stream));
+    const int64_t zero = 0;
+    HIPCHK(c, hipMemcpyAsync(d.t_dev, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_fill_i32(d.trace_len, 0, 1, c->stream));
   } else {
     float* X = c->kind == 1 ? c->csr.X : c->sat.X;
     float* Y = c->kind == 1 ? c->csr.Y : c->sat.Y;
@@ -1615,7 +1857,10 @@ pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
 pdbo_status qubo_gda_objectives(pdbo_ctx* c, int64_t* F) {
   if (!c || !F) return fail(c, PDBO_EINVAL, "NULL argument");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
-  const int64_t* src = c->kind == 0 ? c->insts_h[0].Fall : c->kind == 1 ? c->csr.Flast : c->sat.Flast;
+  const int64_t* src = c->kind == 0   ? c->insts_h[0].Fall
+                       : c->kind == 1 ? c->csr.Flast
+                       : c->kind == 3 ? c->spmm.Flast
+                                      : c->sat.Flast;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(F, src, c->B * sizeof(int64_t), hipMemcpyDeviceToHost));
   return PDBO_OK;
@@ -1626,7 +1871,7 @@ static pdbo_status ensure_scratch(pdbo_ctx* c) {
   int ld = 0;
   if (c->kind == 0)
     ld = c->insts_h[0].ld;
-  else if (c->kind == 1)
+  else if (c->kind == 1 || c->kind == 3)
     ld = c->csr.ld;
   else
     ld = c->sat.ld;
@@ -1653,6 +1898,14 @@ pdbo_status qubo_gda_grad(pdbo_ctx* c, const float* x, float* G) {
   for (size_t i = 0; i < tot; ++i)
     if (!(x[i] >= 0.f && x[i] <= 1.f)) return fail(c, PDBO_EINVAL, "x must lie in [0,1]");
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->kind == 3) {  // node-major operand and result
+    STCHK(spmm_upload(c, x, c->gx_scratch));
+    SpmmDev d = c->spmm;
+    d.X[0] = c->gx_scratch;
+    HIPCHK(c, launch_spmm(d, 2, 0, c->g_scratch, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return spmm_download(c, c->g_scratch, G);
+  }
   TempDev tx;
   STCHK(temp_upload(c, tx, x, tot * sizeof(float)));
   int ld;
@@ -1692,7 +1945,7 @@ pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F
   for (size_t i = 0; i < (size_t)nb * n; ++i)
     if (xr[i] > 1) return fail(c, PDBO_EINVAL, "xr must be 0/1 bytes");
   STCHK(ensure_scratch(c));
-  const int ld = c->kind == 0 ? c->insts_h[0].ld : c->kind == 1 ? c->csr.ld : c->sat.ld;
+  const int ld = c->kind == 0 ? c->insts_h[0].ld : (c->kind == 1 || c->kind == 3) ? c->csr.ld : c->sat.ld;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemsetAsync(c->xr_scratch, 0, (size_t)c->B * ld, c->stream));
   HIPCHK(c, hipMemcpy2DAsync(c->xr_scratch, ld, xr, n, n, nb, hipMemcpyHostToDevice, c->stream));
@@ -1708,7 +1961,7 @@ pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, launch_eval_gemm(c, c->tiles_d, (int)c->tiles_h.size(), c->scratch_inst_d, c->stream));
     HIPCHK(c, launch_argmin(c->scratch_inst_d, 0, 1, 2, c->stream));
-  } else if (c->kind == 1) {
+  } else if (c->kind == 1 || c->kind == 3) {
     HIPCHK(c, launch_csr_eval(c->csr, c->xr_scratch, nb, c->f_scratch, c->stream));
   } else {
     HIPCHK(c, launch_sat_eval(c->sat, c->xr_scratch, nb, c->f_scratch, c->stream));
@@ -1728,7 +1981,7 @@ pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* c, const uint8_t* xr, int32_t nb, in
   if (c->kind != 0) {
     // the CSR and MaxSAT evaluation kernels read the caller's rows directly
     // (row stride n, nonzero bytes are 1) and need no scratch
-    if (c->kind == 1) {
+    if (c->kind == 1 || c->kind == 3) {
       CsrDev d = c->csr;
       d.ld = n;
       HIPCHK(c, launch_csr_eval(d, (const int8_t*)xr, nb, F, s));
@@ -1976,16 +2229,25 @@ pdbo_status qubo_gda_trace(pdbo_ctx* c, int32_t cap, int64_t* t, int64_t* F, int
   if (!c || !len) return fail(c, PDBO_EINVAL, "NULL argument");
   if (cap < 0) return fail(c, PDBO_EINVAL, "cap must be >= 0");
   *len = 0;
-  if (c->kind != 0 || c->insts_h.size() != 1) return PDBO_OK;
-  const InstDev& I = c->insts_h[0];
+  const TraceRec* trace_d = nullptr;
+  const int32_t* len_d = nullptr;
+  if (c->kind == 0 && c->insts_h.size() == 1) {
+    trace_d = c->insts_h[0].trace;
+    len_d = c->insts_h[0].trace_len;
+  } else if (c->kind == 3) {
+    trace_d = c->spmm.trace;
+    len_d = c->spmm.trace_len;
+  } else {
+    return PDBO_OK;
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   int32_t k = 0;
   uint64_t ts0 = 0;
-  HIPCHK(c, hipMemcpy(&k, I.trace_len, sizeof(k), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(&k, len_d, sizeof(k), hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(&ts0, c->ts0_d, sizeof(ts0), hipMemcpyDeviceToHost));
   k = std::min(k, cap);
   std::vector<TraceRec> tr(k);
-  if (k > 0) HIPCHK(c, hipMemcpy(tr.data(), I.trace, k * sizeof(TraceRec), hipMemcpyDeviceToHost));
+  if (k > 0) HIPCHK(c, hipMemcpy(tr.data(), trace_d, k * sizeof(TraceRec), hipMemcpyDeviceToHost));
   const double hz = clock_rate_hz();
   for (int i = 0; i < k; ++i) {
     if (t) t[i] = tr[i].t;

@@ -148,6 +148,33 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 
 __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_memrealtime(); }
 
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of
+// (c0, c1, c2, c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
+// lo(M0 c0)) with the key raised by the Weyl constants between rounds.  The
+// starting point of coordinate i of restart b is word i mod 4 of the output for
+// the counter (i / 4, b, 0, 0) under the key (seed lo, seed hi), scaled to a
+// multiple of 2^-24 in [0, 1) (App. C: x^0 uniform on [0,1]^n).
+__device__ __forceinline__ float philox_start(uint64_t seed, uint32_t b, uint32_t i) {
+  uint32_t c0 = i >> 2, c1 = b, c2 = 0u, c3 = 0u;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+  }
+  const uint32_t w = (i & 3u) == 0u ? c0 : (i & 3u) == 1u ? c1 : (i & 3u) == 2u ? c2 : c3;
+  return (float)(w >> 8) * 5.9604644775390625e-08f;  // 2^-24
+}
+
+
 // Sum of an int32 over the 64 lanes of a wave through DPP moves (no LDS):
 // shifts by 1, 2, 4 and 8 within each row of 16 lanes leave the row's total in
 // its lane 15; row_bcast:15 adds row 0's total into row 1 and row 2's into
@@ -237,6 +264,50 @@ hipError_t launch_csr_persistent(const CsrDev& d, bool packed, int64_t t0, int n
 hipError_t launch_csr_grad(const CsrDev& d, const float* X, float* G, int nb, hipStream_t s);
 hipError_t launch_csr_eval(const CsrDev& d, const int8_t* xr, int nb, int64_t* F, hipStream_t s);
 
+// ---- launchers (spmm.hip) ---------------------------------------------------
+//
+// Sparse path that is not restart-resident: one launch per iteration over all
+// rows, the restarts of a row in adjacent lanes.  Iterates are node-major
+// ([n][B]: the B restarts of coordinate i are contiguous), so gathering x_j
+// for all restarts of a group reads B contiguous floats.  Used when x of one
+// restart does not fit in LDS, or when there are too few restarts to fill the
+// chip with one workgroup each.
+struct SpmmDev {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const int32_t* val;     // canonical Ahat
+  const float* cps;       // c'/s
+  const int64_t* cp;      // c'
+  float* X[2];            // node-major ping-pong iterate
+  float* Y;               // node-major dual iterate
+  int64_t* part;          // [grid][2][W]: per-workgroup partial sums S, C of its slice
+  int64_t* Flast;         // [B] objectives of the last evaluation
+  Incumbent* inc;
+  uint8_t* best_x;        // [n]
+  TraceRec* trace;
+  int32_t* trace_len;
+  int64_t* t_dev;         // completed iterations
+  uint64_t* ts0;
+  int n, B, kappa, trace_cap;
+  int W;                  // restarts per lane group (slice width, <= 64)
+  int G;                  // lane groups per wave (64 / W)
+  int nslices;            // ceil(B / W)
+  int grid;               // workgroups of a launch (a multiple of nslices)
+  float kos;              // kappa / s
+  GdaP gp;
+};
+// mode 0: gradient, Alg. 1 update into X[parity ^ 1] and Y, and the exact
+// objective of round(X[parity]) into the partials; mode 1: the objective only;
+// mode 2: the gradient only, into G (node-major)
+hipError_t launch_spmm(const SpmmDev& d, int mode, int parity, float* G, hipStream_t s);
+// Objectives from the partials, first argmin over b, incumbent update for
+// evaluations of x^t with t >= 1 (label: the completed iterations), and, for
+// advance != 0, the iteration counter moves on.  The winning rounded vector
+// is read from X[parity].
+hipError_t launch_spmm_best(const SpmmDev& d, int parity, int advance, hipStream_t s);
+// node-major state <-> restart-major host layout helpers on the device
+hipError_t launch_spmm_init(const double* x0, const SpmmDev& d, float y0, uint64_t seed,
+                            hipStream_t s);
 // Reduction of per-restart bests to the incumbent (persistent paths).
 hipError_t launch_restart_best(const int64_t* rbestF, const int64_t* rbestT,
                                const uint64_t* rbestTs, const uint8_t* best_xr, int B, int n,

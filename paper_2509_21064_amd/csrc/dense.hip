@@ -1193,32 +1193,6 @@ __device__ __forceinline__ void store_shadow(uint8_t* Xs, size_t off, float v, i
   }
 }
 
-// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of
-// (c0, c1, c2, c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
-// lo(M0 c0)) with the key raised by the Weyl constants between rounds.  The
-// starting point of coordinate i of restart b is word i mod 4 of the output for
-// the counter (i / 4, b, 0, 0) under the key (seed lo, seed hi), scaled to a
-// multiple of 2^-24 in [0, 1) (App. C: x^0 uniform on [0,1]^n).
-__device__ float philox_start(uint64_t seed, uint32_t b, uint32_t i) {
-  uint32_t c0 = i >> 2, c1 = b, c2 = 0u, c3 = 0u;
-  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    c0 = hi1 ^ c1 ^ k0;
-    c1 = lo1;
-    c2 = hi0 ^ c3 ^ k1;
-    c3 = lo0;
-  }
-  const uint32_t w = (i & 3u) == 0u ? c0 : (i & 3u) == 1u ? c1 : (i & 3u) == 2u ? c2 : c3;
-  return (float)(w >> 8) * 5.9604644775390625e-08f;  // 2^-24
-}
-
 __global__ void init_state_kernel(const double* __restrict__ x0, int B, int n, int ld, float y0,
                                   float* X, float* Y, uint8_t* Xs, int prec, int8_t* Xr,
                                   uint64_t seed) {

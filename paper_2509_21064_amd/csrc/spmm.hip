@@ -1,0 +1,228 @@
+// Sparse QUBO path without restart residency: one launch per iteration.
+//
+// The restart-resident kernel of sparse.hip keeps x of one restart in LDS and
+// gives each restart a workgroup.  That stops working when x of one restart
+// exceeds LDS (n > 32768) and wastes the chip when there are few restarts (the
+// paper runs MIS with B = 10 restarts, App. C).  Here every iteration is one
+// launch over all rows of the canonical CSR matrix Ahat = offdiag(Q + Q^T)/kappa
+// with the iterates node-major ([n][B]): a group of W adjacent lanes owns one
+// row i and W restarts, so the gather of x_j reads W contiguous floats for all
+// of them, and the update of (x_i, y_i) writes W contiguous floats.
+//
+// The same gathers give the gradient of x^t (Alg. 1) and the exact objective
+// of round(x^t): with E_i = sum_j Ahat_ij [x_j > 1/2] in integers,
+// F = (kappa/2) sum_i x_r,i E_i + sum_i c'_i x_r,i.  Each workgroup reduces
+// its rows' contributions per restart in LDS (integer atomics, so the order
+// does not matter) and stores them once; spmm_best_kernel adds the
+// workgroups' partials in a fixed order, takes the first argmin over the
+// restarts and updates the incumbent (strict improvement, so the earliest
+// iteration wins ties), copying the winning rounded vector from x^t.
+#include <climits>
+
+#include "common.h"
+
+namespace pdbo {
+
+constexpr int kSpmmThreads = 256;  // four waves
+constexpr int kSpmmUnroll = 8;     // gathers in flight per lane
+
+template <int GK, int MODE>
+__global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parity, float* Gout) {
+  __shared__ unsigned long long sred[2][64];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int W = D.W, G = D.G, n = D.n, B = D.B;
+  const int g = lane / W, bl = lane - g * W;
+  const int slice = blockIdx.x % D.nslices;
+  const int gpw = D.grid / D.nslices;  // workgroups per slice
+  const int b = slice * W + bl;
+  const bool bok = g < G && b < B;
+  const int rows_per_wg = 4 * G;
+  const int nrb = (n + rows_per_wg - 1) / rows_per_wg;
+  const float* __restrict__ Xc = D.X[parity];
+  float* __restrict__ Xn = D.X[parity ^ 1];
+  const int32_t* __restrict__ rp = D.row_ptr;
+  const int32_t* __restrict__ col = D.col;
+  const int32_t* __restrict__ val = D.val;
+  if (MODE != 2 && tid < 128) sred[tid >> 6][tid & 63] = 0;
+  GdaP gp = D.gp;
+  gp.gkind = GK;
+  long long S = 0, C = 0;
+  for (int rb = blockIdx.x / D.nslices; rb < nrb; rb += gpw) {
+    const int i = rb * rows_per_wg + wid * G + g;
+    if (!bok || i >= n) continue;
+    const int pe = rp[i + 1];
+    int p = rp[i];
+    float acc = 0.f;
+    int accr = 0;
+    for (; p + kSpmmUnroll <= pe; p += kSpmmUnroll) {
+      int c[kSpmmUnroll], v[kSpmmUnroll];
+      float xk[kSpmmUnroll];
+#pragma unroll
+      for (int u = 0; u < kSpmmUnroll; ++u) {
+        c[u] = col[p + u];
+        v[u] = val[p + u];
+      }
+#pragma unroll
+      for (int u = 0; u < kSpmmUnroll; ++u) xk[u] = Xc[(size_t)c[u] * B + b];
+#pragma unroll
+      for (int u = 0; u < kSpmmUnroll; ++u) {
+        acc = fmaf((float)v[u], xk[u], acc);
+        accr += xk[u] > 0.5f ? v[u] : 0;
+      }
+    }
+    for (; p < pe; ++p) {
+      const float xk = Xc[(size_t)col[p] * B + b];
+      acc = fmaf((float)val[p], xk, acc);
+      accr += xk > 0.5f ? val[p] : 0;
+    }
+    const size_t off = (size_t)i * B + b;
+    const float x = Xc[off];
+    if constexpr (MODE != 2) {
+      if (x > 0.5f) {
+        S += accr;
+        C += D.cp[i];
+      }
+    }
+    if constexpr (MODE == 0) {
+      float xn, yn;
+      gda_update(x, D.Y[off], fmaf(D.kos, acc, D.cps[i]), gp, xn, yn);
+      Xn[off] = xn;
+      D.Y[off] = yn;
+    } else if constexpr (MODE == 2) {
+      Gout[off] = fmaf(D.kos, acc, D.cps[i]);
+    }
+  }
+  if constexpr (MODE != 2) {
+    __syncthreads();  // sred is cleared
+    if (bok) {
+      // two's complement: unsigned addition modulo 2^64 is the signed sum
+      if (S) atomicAdd(&sred[0][bl], (unsigned long long)S);
+      if (C) atomicAdd(&sred[1][bl], (unsigned long long)C);
+    }
+    __syncthreads();
+    if (tid < W) {
+      int64_t* part = D.part + (size_t)blockIdx.x * 2 * W;
+      part[tid] = (int64_t)sred[0][tid];
+      part[W + tid] = (int64_t)sred[1][tid];
+    }
+  }
+}
+
+hipError_t launch_spmm(const SpmmDev& d, int mode, int parity, float* G, hipStream_t s) {
+  const dim3 grid(d.grid), blk(kSpmmThreads);
+#define PDBO_S(GK, M) hipLaunchKernelGGL((spmm_kernel<GK, M>), grid, blk, 0, s, d, parity, G)
+  const int gk = d.gp.gkind;
+  if (mode == 1) {
+    PDBO_S(0, 1);
+  } else if (mode == 2) {
+    PDBO_S(0, 2);
+  } else if (gk == 0) {
+    PDBO_S(0, 0);
+  } else if (gk == 1) {
+    PDBO_S(1, 0);
+  } else {
+    PDBO_S(2, 0);
+  }
+#undef PDBO_S
+  return hipGetLastError();
+}
+
+constexpr int kBestThreads = 1024;
+
+__global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int parity,
+                                                                 int advance) {
+  __shared__ int64_t sF[kBestThreads / 64];
+  __shared__ int sb[kBestThreads / 64];
+  __shared__ int win;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int64_t t = *D.t_dev;  // the evaluated iterate is x^t
+  const int gpw = D.grid / D.nslices;
+  int64_t bestF = LLONG_MAX;
+  int bestb = INT_MAX;
+  for (int b = tid; b < D.B; b += kBestThreads) {
+    const int slice = b / D.W, bl = b - slice * D.W;
+    int64_t S = 0, C = 0;
+    for (int k = 0; k < gpw; ++k) {  // fixed order
+      const int64_t* part = D.part + (size_t)(k * D.nslices + slice) * 2 * D.W;
+      S += part[bl];
+      C += part[D.W + bl];
+    }
+    const int64_t F = (D.kappa == 2 ? S : S / 2) + C;
+    D.Flast[b] = F;
+    if (F < bestF) {  // increasing b per thread: the first minimum is kept
+      bestF = F;
+      bestb = b;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t F2 = __shfl_xor(bestF, o);
+    const int b2 = __shfl_xor(bestb, o);
+    if (F2 < bestF || (F2 == bestF && b2 < bestb)) {
+      bestF = F2;
+      bestb = b2;
+    }
+  }
+  if (lane == 0) {
+    sF[wid] = bestF;
+    sb[wid] = bestb;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < kBestThreads / 64; ++w)
+      if (sF[w] < bestF || (sF[w] == bestF && sb[w] < bestb)) {
+        bestF = sF[w];
+        bestb = sb[w];
+      }
+    int improved = 0;
+    if (t >= 1 && bestb != INT_MAX && bestF < D.inc->F) {
+      const uint64_t ts = wall_clock();
+      D.inc->F = bestF;
+      D.inc->t = t;
+      D.inc->b = bestb;
+      D.inc->ts = ts;
+      const int len = *D.trace_len;
+      if (len < D.trace_cap) {
+        D.trace[len] = TraceRec{t, bestF, (int64_t)bestb, ts};
+        *D.trace_len = len + 1;
+      }
+      improved = 1;
+    }
+    win = improved ? bestb : -1;
+    if (advance) *D.t_dev = t + 1;
+  }
+  __syncthreads();
+  if (win >= 0) {
+    const float* X = D.X[parity];
+    for (int i = tid; i < D.n; i += kBestThreads)
+      D.best_x[i] = (uint8_t)(X[(size_t)i * D.B + win] > 0.5f);
+  }
+}
+
+hipError_t launch_spmm_best(const SpmmDev& d, int parity, int advance, hipStream_t s) {
+  hipLaunchKernelGGL(spmm_best_kernel, dim3(1), dim3(kBestThreads), 0, s, d, parity, advance);
+  return hipGetLastError();
+}
+
+// X^0 (node-major) from the caller's restart-major x0, or drawn by the
+// library's generator (same counters as the restart-major paths); Y^0 = y0.
+__global__ void spmm_init_kernel(const double* __restrict__ x0, SpmmDev D, float y0,
+                                 uint64_t seed) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)D.B * D.n) return;
+  const int b = (int)(idx / D.n), i = (int)(idx % D.n);
+  const size_t off = (size_t)i * D.B + b;
+  D.X[0][off] = x0 ? (float)x0[idx] : philox_start(seed, (uint32_t)b, (uint32_t)i);
+  D.Y[off] = y0;
+}
+
+hipError_t launch_spmm_init(const double* x0, const SpmmDev& d, float y0, uint64_t seed,
+                            hipStream_t s) {
+  const size_t tot = (size_t)d.B * d.n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(spmm_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x0, d,
+                     y0, seed);
+  return hipGetLastError();
+}
+
+}  // namespace pdbo

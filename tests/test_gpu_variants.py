@@ -97,10 +97,68 @@ def test_scalar_dual_fp32_trajectory_and_batch():
         assert r["best_obj"] == oq.objective(qq, r["best_x"][None])[0]
 
 
-def test_variants_rejected_on_persistent_paths():
+def test_variants_on_the_sparse_paths():
+    """The restart-resident CSR and MaxSAT kernels take neither variant
+    (EUNSUPPORTED); the row-parallel CSR path takes the polynomial g (chosen
+    automatically for it), not the scalar dual."""
     P = require_gpu()
     q = W.maxcut_c2(0, n=300, M=900)
-    for over in (dict(g="poly", g_degree=2), dict(dual="scalar")):
+    x0 = W.x0_uniform(2, 4, 8, q.n)
+    for over in (dict(g="poly", g_degree=2, tile=1), dict(dual="scalar", tile=1),
+                 dict(dual="scalar", tile=2), dict(dual="scalar")):
         with pytest.raises(P.PdboError) as ei:
-            P.qubo_gda_init(q, W.gda_params("maxcut", B=8, T=1, **over), W.x0_uniform(2, 4, 8, q.n))
-        assert ei.value.status == 6
+            P.qubo_gda_init(q, W.gda_params("maxcut", B=8, T=1, **over), x0)
+        assert ei.value.status == 6, over
+    f = W.random_maxsat(100, 400, 3, 1, 5, W.rng_for(5, 45, 0))
+    with pytest.raises(P.PdboError) as ei:
+        P.maxsat_gda_init(f, W.gda_params("maxsat", B=8, T=1, g="poly"), W.x0_uniform(5, 45, 8, 100))
+    assert ei.value.status == 6
+    p = W.gda_params("maxcut", B=8, T=1, g="poly", g_degree=2, y0=0.01, beta=0.05)
+    ctx = P.qubo_gda_init(q, p, x0)
+    A, cp = oq.canonicalize(q)
+    X, Y, _ = ctx.get_state()
+    for step in range(3):
+        ctx.step(1)
+        Xn, Yn, _ = ctx.get_state()
+        G64 = oq.grad_f(A, cp, X.astype(np.float64), 1.0)
+        gabs = 1e-5 * float(np.max(np.abs(G64))) + 1e-6
+        dx, dy, namb, _, _ = lockstep_compare(X.astype(np.float64), Y.astype(np.float64), G64, Xn,
+                                              Yn, p, gabs)
+        assert dx <= p["alpha"] * gabs + 2e-6 and dy <= 2e-6 * (1 + np.max(np.abs(Y)))
+        assert np.array_equal(ctx.objectives(), oq.objective(q, Xn > 0.5))
+        X, Y = Xn, Yn
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr", "maxsat"])
+def test_enomem_injection_frees_everything(kind, monkeypatch):
+    """A device allocation failing part-way through init returns PDBO_ENOMEM
+    and leaves no device memory behind; a later init succeeds."""
+    import torch
+    P = require_gpu()
+    if kind == "dense":
+        q = W.random_dense_qubo(300, -50, 50, W.rng_for(3, 44, 0, 300))
+        mk = lambda: P.qubo_gda_init(q, W.gda_params("qubo", B=64, T=1, scale=50.0), None)
+    elif kind == "csr":
+        q = W.maxcut_c2(0, n=400, M=1200)
+        mk = lambda: P.qubo_gda_init(q, W.gda_params("maxcut", B=32, T=1), None)
+    else:
+        f = W.random_maxsat(300, 1200, 3, 1, 10, W.rng_for(5, 44, 0))
+        mk = lambda: P.maxsat_gda_init(f, W.gda_params("maxsat", B=16, T=1, scale=5.5), None)
+    mk().destroy()  # modules loaded, caches warm
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    failures = 0
+    for k in (1, 2, 3, 5, 8, 13, 21, 34):
+        monkeypatch.setenv("PDBO_FAIL_ALLOC_AT", str(k))
+        try:
+            mk().destroy()
+        except P.PdboError as e:
+            assert e.status == 2, e
+            failures += 1
+        monkeypatch.setenv("PDBO_FAIL_ALLOC_AT", "0")
+        free1 = torch.cuda.mem_get_info()[0]
+        say(f"[enomem] {kind} k={k}: free {free0 - free1} bytes below the start")
+        assert free1 >= free0 - (2 << 20), k
+    assert failures >= 3
+    mk().destroy()

@@ -27,6 +27,7 @@ __all__ = [
     "Qubo", "MaxSat", "rng_for", "x0_uniform",
     "gnp_pm1", "qubo_c1", "qubo_c1_twin", "maxcut_c2", "qubo_c3", "batch_c4",
     "maxsat_c5", "random_dense_qubo", "random_asym_qubo", "random_maxsat",
+    "random_regular_graph", "mis_qubo",
 ]
 
 
@@ -166,6 +167,54 @@ def random_asym_qubo(n: int, lo: int, hi: int, rng: np.random.Generator) -> Qubo
     Q = rng.integers(lo, hi + 1, size=(n, n), dtype=np.int64).astype(np.int32)
     c = rng.integers(lo, hi + 1, size=n).astype(np.int64)
     return Qubo(n=n, Q=Q, c=c, name=f"asym_u{lo}_{hi}_n{n}")
+
+
+def random_regular_graph(n: int, d: int, rng: np.random.Generator) -> np.ndarray:
+    """Edges (i < j), shape (n d / 2, 2), of a simple d-regular graph on n
+    vertices: a uniform random pairing of the n d half-edges (configuration
+    model), after which every loop or repeated edge is replaced through a
+    degree-preserving switch with a random other edge."""
+    if (n * d) % 2 or not 0 <= d < n:
+        raise ValueError("need n d even and d < n")
+    stubs = np.repeat(np.arange(n, dtype=np.int64), d)
+    rng.shuffle(stubs)
+    E = np.sort(stubs.reshape(-1, 2), axis=1)
+    key = E[:, 0] * n + E[:, 1]
+    order = np.argsort(key, kind="stable")
+    dup = np.zeros(len(E), dtype=bool)
+    dup[order[1:]] = key[order[1:]] == key[order[:-1]]
+    bad = np.flatnonzero((E[:, 0] == E[:, 1]) | dup)
+    good = set(key[~((E[:, 0] == E[:, 1]) | dup)].tolist())
+    for e in bad:
+        while True:
+            f = int(rng.integers(len(E)))
+            if f == e or E[f, 0] * n + E[f, 1] not in good:
+                continue
+            u, v = int(E[e, 0]), int(E[e, 1])
+            x, y = (int(E[f, 0]), int(E[f, 1])) if rng.random() < 0.5 else (int(E[f, 1]), int(E[f, 0]))
+            a, b = min(u, x), max(u, x)
+            c, dd = min(v, y), max(v, y)
+            if a == b or c == dd or a * n + b in good or c * n + dd in good or (a, b) == (c, dd):
+                continue
+            good.discard(E[f, 0] * n + E[f, 1])
+            E[e] = (a, b)
+            E[f] = (c, dd)
+            good.add(a * n + b)
+            good.add(c * n + dd)
+            break
+    return E[np.lexsort((E[:, 1], E[:, 0]))]
+
+
+def mis_qubo(n: int, d: int, rep: int = 0, lam: int = 4) -> Qubo:
+    """Maximum independent set on a random d-regular graph as the penalised
+    QUBO of App. D: minimise -sum_i x_i + lam sum_{(i,j) in E} x_i x_j (CSR
+    holding lam/2 at (i,j) and (j,i) for every edge, c = -1)."""
+    if lam % 2:
+        raise ValueError("lam must be even: Q holds lam/2 at (i,j) and (j,i)")
+    E = random_regular_graph(n, d, rng_for(6, rep, 0, n, d))
+    rp, col, val = _csr_from_upper(n, E[:, 0], E[:, 1], np.full(len(E), lam // 2, dtype=np.int64))
+    return Qubo(n=n, row_ptr=rp, col_idx=col, vals=val, c=np.full(n, -1, dtype=np.int64),
+                name=f"mis_d{d}_n{n}", meta=dict(edges=E, d=d, lam=lam))
 
 
 def qubo_c3(rep: int = 0, n: int = 10000) -> Qubo:

@@ -43,7 +43,7 @@ def gda_params(kind: str, B: int, T: int, scale: float = 1.0, **over) -> dict:
     return p
 
 
-def qubo_scale(q) -> float:
+def _qubo_scale(q) -> float:
     """s = -lambda_min(offdiag(Q+Q^T)/2) / 4, floored at 1 (ARPACK, fixed start)."""
     import scipy.sparse as sp
     from scipy.sparse.linalg import LinearOperator, eigsh
@@ -66,6 +66,24 @@ def qubo_scale(q) -> float:
     op = LinearOperator((n, n), matvec=mv, dtype=np.float64)
     lam = eigsh(op, k=1, which="SA", tol=1e-3, v0=np.ones(n), return_eigenvectors=False)[0]
     return max(1.0, float(-lam / 4.0))
+
+
+_SCALES = {}
+
+
+def qubo_scale(q) -> float:
+    """s = -lambda_min(offdiag(Q+Q^T)/2) / 4, floored at 1, computed once per
+    instance in a process: ARPACK keeps a random seed between calls, so a
+    second call can end in different last bits, and runs compared bit for bit
+    must share s."""
+    import hashlib
+    h = hashlib.sha1(str(q.n).encode())
+    for a in (q.Q, q.row_ptr, q.col_idx, q.vals, q.c):
+        h.update(b"|" if a is None else np.ascontiguousarray(a).view(np.uint8).ravel())
+    key = h.hexdigest()
+    if key not in _SCALES:
+        _SCALES[key] = _qubo_scale(q)
+    return _SCALES[key]
 
 
 def maxsat_scale(inst) -> float:
