@@ -241,6 +241,26 @@ PDBO_API pdbo_status qubo_gda_eval(pdbo_ctx* ctx, const uint8_t* xr, int32_t nb,
 PDBO_API pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* ctx, const uint8_t* xr, int32_t nb, int64_t* F,
                                            void* stream);
 
+/* Dual certificate (App. D, Dual Certificate): a lower bound on min F over
+ * {0,1}^n.  For any y, the minimum of L(., y) over [0,1]^n is at most its
+ * minimum over {0,1}^n, where L = F/s (weak duality, proof of Thm. 3.2).  With
+ * the quadratic g and y = ybar * 1 the function L(., y) is convex when
+ * A/s + 2 ybar I is positive semidefinite (ybar >= -lambda_min(A) / (2 s));
+ * the caller vouches for that, the library does not check it.  The call runs
+ * `iters` iterations of projected gradient descent on L(., ybar 1) (Alg. 1
+ * with beta = 0, from x = 1/2, through the context's own step kernels and
+ * precision) and then, at the point x reached, evaluates in float64 the bound
+ *   s * (L(x) + sum_i min(-d_i x_i, d_i (1 - x_i))),  d = grad L(x),
+ * less a bound on its rounding errors, into *lower_bound (valid at any x when
+ * L is convex; tight at the minimiser).  value (or NULL) receives s L(x), the
+ * Frank-Wolfe gap s * max_z d.(x - z) >= 0 and the rounding bound subtracted;
+ * x_out (host float[n] or NULL) the point.  ybar = 0 takes the parameters'
+ * y0.  Dense (single instance) and CSR contexts with the quadratic g, else
+ * EUNSUPPORTED.  The run's own iterate and incumbent are left untouched.
+ * Synchronises. */
+PDBO_API pdbo_status qubo_dual_bound(pdbo_ctx* ctx, double ybar, int32_t iters, double* lower_bound,
+                                     double* value, float* x_out);
+
 /* init + step(T) + result + destroy. */
 PDBO_API pdbo_status qubo_gda_solve(const pdbo_qubo* prob, const pdbo_params* par, int32_t T,
                            void* stream, pdbo_result* result);

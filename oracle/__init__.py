@@ -22,6 +22,8 @@ Modules
                the proof of Thm. 3.7
 ``philox``     Philox4x32-10 and the starting points the library draws when the
                caller passes none (App. C: x^0 uniform on [0,1]^n)
+``dual``       the dual certificate of App. D: a lower bound on min F from the
+               Lagrangian at a fixed y, and projected descent to reach it
 ``mis``        maximum independent set as the penalised QUBO of App. D, set
                size of feasible vectors, independence number by enumeration
 
@@ -34,4 +36,4 @@ closed forms, exact finite or complex-step differences, library routines
 Which test pins which function is listed in the design notes; no function here
 is "parity unpinned".
 """
-from . import binarity, bounds, enumerate, gda, maxsat, mis, philox, qubo  # noqa: F401
+from . import binarity, bounds, dual, enumerate, gda, maxsat, mis, philox, qubo  # noqa: F401

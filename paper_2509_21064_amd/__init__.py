@@ -27,7 +27,7 @@ from ._abi import (PDBO_BF16, PDBO_CSR, PDBO_DENSE, PDBO_FP8, PDBO_FP32, PDBO_G_
 __all__ = [
     "load", "PdboError", "Context", "qubo_gda_init", "qubo_gda_step", "qubo_gda_result",
     "qubo_gda_get_state", "qubo_gda_set_state", "qubo_gda_restart", "qubo_gda_objectives", "qubo_gda_grad",
-    "qubo_gda_eval", "qubo_gda_eval_noalloc", "qubo_gda_trace", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
+    "qubo_gda_eval", "qubo_gda_eval_noalloc", "qubo_dual_bound", "qubo_gda_trace", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
     "qubo_gda_batch_solve", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
     "maxsat_gda_solve", "maxsat_lagrangian_fwd", "maxsat_lagrangian_bwd", "MaxSATLagrangian",
     "PDBO_FP32", "PDBO_BF16", "PDBO_FP8", "PDBO_I8", "PDBO_K_STEP", "PDBO_K_EVAL", "PDBO_K_ARGMIN",
@@ -260,6 +260,18 @@ def qubo_gda_eval_noalloc(ctx: Context, xr, F, stream=None):
     check(load().qubo_gda_eval_noalloc(ctx.h, ctypes.c_void_p(xr.data_ptr()), int(xr.shape[0]),
                                        ctypes.c_void_p(F.data_ptr()), s), ctx.h)
     return F
+
+
+def qubo_dual_bound(ctx: Context, iters: int, ybar: float = 0.0) -> dict:
+    """Certified lower bound on min F from the Lagrangian at y = ybar 1 (valid
+    when that Lagrangian is convex); see pdbo.h."""
+    lb = ctypes.c_double()
+    val = np.zeros(3, dtype=np.float64)
+    x = np.zeros(ctx.n, dtype=np.float32)
+    check(load().qubo_dual_bound(ctx.h, float(ybar), int(iters), ctypes.byref(lb), _ptr(val), _ptr(x)),
+          ctx.h)
+    return dict(lower_bound=lb.value, value=float(val[0]), gap=float(val[1]),
+                rounding=float(val[2]), x=x)
 
 
 def qubo_gda_trace(ctx: Context, cap: int = 4096) -> dict:

@@ -57,6 +57,7 @@ SIGNATURES = {
     "qubo_gda_grad": (_st, [_ctx, c_void_p, c_void_p]),
     "qubo_gda_eval": (_st, [_ctx, c_void_p, c_int32, c_void_p]),
     "qubo_gda_eval_noalloc": (_st, [_ctx, c_void_p, c_int32, c_void_p, c_void_p]),
+    "qubo_dual_bound": (_st, [_ctx, c_double, c_int32, POINTER(c_double), c_void_p, c_void_p]),
     "qubo_gda_solve": (_st, [POINTER(pdbo_qubo), POINTER(pdbo_params), c_int32, c_void_p,
                              POINTER(pdbo_result)]),
     "qubo_gda_batch_init": (_st, [c_int32, POINTER(pdbo_qubo), POINTER(pdbo_params), c_int32,

@@ -41,6 +41,7 @@ UNITS = [
     ("sparse.hip", "sparse.o", []),
     ("maxsat.hip", "maxsat.o", []),
     ("spmm.hip", "spmm.o", []),
+    ("cert.hip", "cert.o", []),
     ("api.hip", "api.o", []),
 ]
 SOURCES = sorted({u[0] for u in UNITS})

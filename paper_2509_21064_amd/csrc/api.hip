@@ -94,6 +94,16 @@ struct pdbo_ctx {
   float* g_scratch = nullptr;      // gradient out
   int8_t* xr_scratch = nullptr;
   int64_t *sp_scratch = nullptr, *cp_scratch = nullptr, *f_scratch = nullptr;
+  // dual certificate: one descent point (two for ping-pong), its dual, shadow,
+  // rounding, per-row terms and the result; per-restart records of the
+  // resident CSR kernel and the partial sums of the row-parallel one
+  float *cert_x = nullptr, *cert_y = nullptr;
+  uint8_t* cert_xs = nullptr;
+  int8_t* cert_xr = nullptr;
+  double *cert_rows = nullptr, *cert_res = nullptr;
+  int64_t *cert_i64 = nullptr;
+  uint64_t* cert_u64 = nullptr;
+  uint8_t* cert_bx = nullptr;
   // graph
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -2020,6 +2030,114 @@ pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* c, const uint8_t* xr, int32_t nb, in
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, launch_eval_gemm(c, c->tiles_d, (int)c->tiles_h.size(), desc, s));
   HIPCHK(c, launch_argmin(desc, 0, 1, 2, s));
+  return PDBO_OK;
+}
+
+pdbo_status qubo_dual_bound(pdbo_ctx* c, double ybar, int32_t iters, double* lower_bound,
+                            double* value, float* x_out) {
+  if (!c || !lower_bound) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (c->kind == 2) return fail(c, PDBO_EUNSUPPORTED, "the dual certificate is built for QUBO contexts");
+  if (c->par.g_kind != PDBO_G_QUAD)
+    return fail(c, PDBO_EUNSUPPORTED, "the dual certificate is built for the quadratic g");
+  if (ybar == 0.0) ybar = c->par.y0;
+  if (!finite_pos(ybar)) return fail(c, PDBO_EINVAL, "ybar must be finite and > 0 (or 0 for y0)");
+  if (iters < 0) return fail(c, PDBO_EINVAL, "iters must be >= 0");
+  const int n = c->n_of[0];
+  const int ld = roundup(n, kLdAlign);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!c->cert_x) {
+    STCHK(dalloc(c, &c->cert_x, 2 * (size_t)ld));
+    STCHK(dalloc(c, &c->cert_y, (size_t)ld));
+    STCHK(dalloc(c, &c->cert_xs, 2 * (size_t)ld * 4));
+    STCHK(dalloc(c, &c->cert_xr, (size_t)ld));
+    STCHK(dalloc(c, &c->cert_rows, 4 * (size_t)n));
+    STCHK(dalloc(c, &c->cert_res, 4));
+    STCHK(dalloc(c, &c->cert_i64, 4 + 2 * (size_t)std::max(1, 2048)));
+    STCHK(dalloc(c, &c->cert_u64, 1));
+    STCHK(dalloc(c, &c->cert_bx, (size_t)n));
+  }
+  if (c->kind == 0 && !c->scratch_inst_d) STCHK(dalloc(c, &c->scratch_inst_d, 1));
+  float* x0 = c->cert_x;
+  float* x1 = c->cert_x + ld;
+  // projected gradient descent on L(., ybar 1) (Alg. 1 with beta = 0: y stays
+  // positive, so the perturbation never applies) from x = 1/2
+  HIPCHK(c, launch_fill_f32(x0, 0.5f, n, c->stream));
+  HIPCHK(c, launch_fill_f32(x1, 0.f, ld, c->stream));
+  HIPCHK(c, launch_fill_f32(c->cert_y, (float)ybar, ld, c->stream));
+  const float* xhat = x0;
+  if (c->kind == 0) {
+    InstDev I = c->insts_h[0];
+    I.B = 1;
+    I.X[0] = x0;
+    I.X[1] = c->prec == PDBO_FP32 ? x1 : x0;
+    I.Y = c->cert_y;
+    I.Xs[0] = c->prec == PDBO_FP32 ? (uint8_t*)x0 : c->cert_xs;
+    I.Xs[1] = c->prec == PDBO_FP32 ? (uint8_t*)x1 : c->cert_xs + (size_t)ld * 4;
+    I.Xr = c->cert_xr;
+    I.nflip = nullptr;
+    I.fbits = nullptr;
+    I.cand = nullptr;
+    I.ys = nullptr;
+    I.gp.beta = 0.f;
+    I.gp.gkind = PDBO_G_QUAD;
+    if (c->prec != PDBO_FP32)
+      HIPCHK(c, launch_set_state(x0, nullptr, 1, n, ld, x0, nullptr, I.Xs[0], c->prec, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->scratch_inst_d, &I, sizeof(I), hipMemcpyHostToDevice, c->stream));
+    int parity = 0;
+    for (int t = 0; t < iters; ++t) {
+      HIPCHK(c, launch_dense_gemm(c->cfg, c->prec, EPI_STEP, PDBO_G_QUAD, c->tiles_d,
+                                  (int)c->tiles_h.size(), c->scratch_inst_d, parity, 0, c->stream));
+      parity ^= 1;
+    }
+    xhat = I.X[parity];
+    HIPCHK(c, launch_cert_dense(c->insts_h[0], xhat, c->par.scale, ybar, c->cert_rows, c->cert_res,
+                                c->stream));
+  } else if (c->kind == 1) {
+    CsrDev d = c->csr;
+    d.B = 1;
+    d.X = x0;
+    d.Y = c->cert_y;
+    d.rbestF = c->cert_i64;
+    d.rbestT = c->cert_i64 + 1;
+    d.Flast = c->cert_i64 + 2;
+    d.rbestTs = c->cert_u64;
+    d.best_xr = c->cert_bx;
+    d.gp.beta = 0.f;
+    d.gp.gkind = PDBO_G_QUAD;
+    if (iters > 0) HIPCHK(c, launch_csr_persistent(d, c->compact, 0, iters, c->stream));
+    HIPCHK(c, launch_cert_csr(c->csr, x0, c->par.scale, ybar, c->cert_rows, c->cert_res, c->stream));
+  } else {
+    SpmmDev d = c->spmm;
+    d.B = 1;
+    d.W = 1;
+    d.G = 64;
+    d.nslices = 1;
+    d.grid = std::max(1, std::min((n + 255) / 256, 2048));
+    d.X[0] = x0;
+    d.X[1] = x1;
+    d.Y = c->cert_y;
+    d.part = c->cert_i64 + 4;
+    d.gp.beta = 0.f;
+    d.gp.gkind = PDBO_G_QUAD;
+    int parity = 0;
+    for (int t = 0; t < iters; ++t) {
+      HIPCHK(c, launch_spmm(d, 0, parity, nullptr, c->stream));
+      parity ^= 1;
+    }
+    xhat = d.X[parity];
+    HIPCHK(c, launch_cert_csr(c->csr, xhat, c->par.scale, ybar, c->cert_rows, c->cert_res, c->stream));
+  }
+  double res[4];
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(res, c->cert_res, sizeof(res), hipMemcpyDeviceToHost));
+  *lower_bound = res[0];
+  if (value) {
+    value[0] = res[1];
+    value[1] = res[2];
+    value[2] = res[3];
+  }
+  if (x_out) HIPCHK(c, hipMemcpy(x_out, xhat, (size_t)n * sizeof(float), hipMemcpyDeviceToHost));
   return PDBO_OK;
 }
 

@@ -308,6 +308,18 @@ hipError_t launch_spmm_best(const SpmmDev& d, int parity, int advance, hipStream
 // node-major state <-> restart-major host layout helpers on the device
 hipError_t launch_spmm_init(const double* x0, const SpmmDev& d, float y0, uint64_t seed,
                             hipStream_t s);
+// ---- launchers (cert.hip) ---------------------------------------------------
+//
+// Certified lower bound on min F from the Lagrangian at y = ybar * 1 with the
+// quadratic g, evaluated at one box point x (device float[ld] / float[n]) in
+// float64 with rounding bounds: rows = device double[4 n] scratch; res = device
+// double[4]: bound, s L(x), Frank-Wolfe gap, rounding bound subtracted.
+hipError_t launch_cert_dense(const InstDev& I, const float* x, double s, double ybar, double* rows,
+                             double* res, hipStream_t st);
+hipError_t launch_cert_csr(const CsrDev& d, const float* x, double s, double ybar, double* rows,
+                           double* res, hipStream_t st);
+hipError_t launch_fill_f32(float* p, float v, int64_t cnt, hipStream_t st);
+
 // Reduction of per-restart bests to the incumbent (persistent paths).
 hipError_t launch_restart_best(const int64_t* rbestF, const int64_t* rbestT,
                                const uint64_t* rbestTs, const uint8_t* best_xr, int B, int n,
