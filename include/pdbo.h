@@ -97,6 +97,22 @@ typedef struct {
 } pdbo_maxsat;
 
 /*
+ * Weighted graph for Max-k-Cut (App. B): partition the n nodes into k
+ * categories so as to maximise the weight of the edges between categories.
+ * W is symmetric CSR with both directions of every edge stored (row_ptr[n+1],
+ * col_idx[nnz] strictly increasing per row, w[nnz] int32), no diagonal;
+ * 2 <= k <= 8.  Host pointers.
+ */
+typedef struct {
+  int32_t n;
+  int32_t k;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const int32_t* w;
+  int64_t nnz;
+} pdbo_kcut;
+
+/*
  * Parameters of Alg. 1 and of the execution.
  *   B          number of restarts, >= 1.
  *   alpha,beta primal / dual step sizes (> 0).
@@ -276,6 +292,32 @@ PDBO_API pdbo_status qubo_gda_batch_init(int32_t k, const pdbo_qubo* probs, cons
 PDBO_API pdbo_status qubo_gda_batch_result(pdbo_ctx* ctx, int32_t inst, pdbo_result* result);
 PDBO_API pdbo_status qubo_gda_batch_solve(int32_t k, const pdbo_qubo* probs, const pdbo_params* par,
                                  int32_t T, int32_t grouped, void* stream, pdbo_result* results);
+
+/* ---- Max-k-Cut (softmax reparametrisation, row-parallel kernel) ----------- */
+
+/* Max-k-Cut through the softmax reparametrisation of App. B: node i of a
+ * restart has logits Z_{:,i} (k reals) and probabilities X_{:,i} =
+ * softmax(Z_{:,i}); simultaneous gradient descent-ascent on
+ * L(Z, y) = Tr(X W X^T)/s + sum_i y_i g(X_{:,i}) over (Z, y), with g quadratic
+ * (sum_c X_ci^2 - 1, g_kind PDBO_G_QUAD) or entropy (sum_c X_ci log X_ci with
+ * log taken at X clipped below at 2^-20, PDBO_G_ENTROPY):
+ *   Z_ci -= alpha X_ci (G_ci - sum_c' X_c'i G_c'i),
+ *   G_ci = (2/s) (X W)_ci + y_i dg/dX_ci,   y_i += beta g(X_{:,i}) (old X);
+ * Z is unconstrained, so Alg. 1's projection and perturbation do not apply.
+ * Every iteration the assignment c_i = argmax_c X_ci (lowest c on ties) is
+ * evaluated exactly: F = the weight of the edges whose ends share a category
+ * (each edge once; minimised, the cut is the total weight minus F).
+ * x0: HOST (B, n, k) float64 logits Z^0 (finite), or NULL for the library's
+ * generator (coordinate index i k + c, values in [0, 1)).  Step, result
+ * (best_x: the n categories), objectives, trace, restart, timing and
+ * destroy use the qubo_gda_* / pdbo_* entry points; get_state / set_state take
+ * x as the logits Z, host (B, n, k) float32, and y as (B, n); eval takes
+ * categories (nb, n) bytes in [0, k); grad returns d(Tr(X W X^T)/s)/dZ at
+ * logits x, (B, n, k).  EINVAL for an asymmetric W, a diagonal entry, k out of
+ * range; ERANGE for a row of |W| summing to 2^31 or more; EUNSUPPORTED for the
+ * polynomial g or the scalar dual. */
+PDBO_API pdbo_status kcut_gda_init(const pdbo_kcut* prob, const pdbo_params* par, void* stream,
+                                   pdbo_ctx** out);
 
 /* ---- weighted MaxSAT (persistent, restart-resident kernel) ---------------- */
 

@@ -24,6 +24,8 @@ Modules
                caller passes none (App. C: x^0 uniform on [0,1]^n)
 ``dual``       the dual certificate of App. D: a lower bound on min F from the
                Lagrangian at a fixed y, and projected descent to reach it
+``kcut``       Max-k-Cut through the softmax reparametrisation (App. B): exact
+               objective, Lagrangian, its gradient in the logits, GDA steps
 ``mis``        maximum independent set as the penalised QUBO of App. D, set
                size of feasible vectors, independence number by enumeration
 
@@ -36,4 +38,4 @@ closed forms, exact finite or complex-step differences, library routines
 Which test pins which function is listed in the design notes; no function here
 is "parity unpinned".
 """
-from . import binarity, bounds, dual, enumerate, gda, maxsat, mis, philox, qubo  # noqa: F401
+from . import binarity, bounds, dual, enumerate, gda, kcut, maxsat, mis, philox, qubo  # noqa: F401

@@ -28,7 +28,7 @@ __all__ = [
     "load", "PdboError", "Context", "qubo_gda_init", "qubo_gda_step", "qubo_gda_result",
     "qubo_gda_get_state", "qubo_gda_set_state", "qubo_gda_restart", "qubo_gda_objectives", "qubo_gda_grad",
     "qubo_gda_eval", "qubo_gda_eval_noalloc", "qubo_dual_bound", "qubo_gda_trace", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
-    "qubo_gda_batch_solve", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
+    "qubo_gda_batch_solve", "kcut_gda_init", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
     "maxsat_gda_solve", "maxsat_lagrangian_fwd", "maxsat_lagrangian_bwd", "MaxSATLagrangian",
     "PDBO_FP32", "PDBO_BF16", "PDBO_FP8", "PDBO_I8", "PDBO_K_STEP", "PDBO_K_EVAL", "PDBO_K_ARGMIN",
     "PDBO_K_PERSISTENT", "PDBO_K_INCR",
@@ -120,10 +120,11 @@ def _result_dict(r: _abi.pdbo_result, best_x) -> dict:
 class Context:
     """Owner of a pdbo_ctx*; the methods call the entry points of the same name."""
 
-    def __init__(self, handle, n, B, kind, ninst=1, ns=None):
+    def __init__(self, handle, n, B, kind, ninst=1, ns=None, k=1):
         self.h = handle
         self.n, self.B, self.kind, self.ninst = n, B, kind, ninst
         self.ns = ns or [n]
+        self.k = k  # values per node of x (Max-k-Cut: the k logits)
 
     def __del__(self):
         self.destroy()
@@ -205,8 +206,12 @@ def qubo_gda_result(ctx: Context) -> dict:
     return _result_dict(r, bx)
 
 
+def _xshape(ctx):
+    return (ctx.B, ctx.n) if ctx.k == 1 else (ctx.B, ctx.n, ctx.k)
+
+
 def qubo_gda_get_state(ctx: Context):
-    x = np.zeros((ctx.B, ctx.n), dtype=np.float32)
+    x = np.zeros(_xshape(ctx), dtype=np.float32)
     y = np.zeros((ctx.B, ctx.n), dtype=np.float32)
     t = ctypes.c_int64()
     check(load().qubo_gda_get_state(ctx.h, _ptr(x), _ptr(y), ctypes.byref(t)), ctx.h)
@@ -224,8 +229,8 @@ def qubo_gda_restart(ctx: Context, x0=None):
     xa = None
     if x0 is not None:
         xa = np.ascontiguousarray(x0, dtype=np.float64)
-        if xa.shape != (ctx.B, ctx.n):
-            raise ValueError(f"x0 must have shape {(ctx.B, ctx.n)}")
+        if xa.shape != _xshape(ctx):
+            raise ValueError(f"x0 must have shape {_xshape(ctx)}")
     check(load().qubo_gda_restart(ctx.h, _ptr(xa)), ctx.h)
 
 
@@ -237,7 +242,7 @@ def qubo_gda_objectives(ctx: Context) -> np.ndarray:
 
 def qubo_gda_grad(ctx: Context, x) -> np.ndarray:
     xa = np.ascontiguousarray(x, dtype=np.float32)
-    G = np.zeros((ctx.B, ctx.n), dtype=np.float32)
+    G = np.zeros(_xshape(ctx), dtype=np.float32)
     check(load().qubo_gda_grad(ctx.h, _ptr(xa), _ptr(G)), ctx.h)
     return G
 
@@ -333,6 +338,24 @@ def qubo_gda_batch_solve(qs, params_list, x0s, T: int, grouped=True, stream=None
     check(lib.qubo_gda_batch_solve(k, probs, pars, int(T), int(bool(grouped)),
                                    stream if stream is not None else _current_stream(), res))
     return [_result_dict(res[i], bxs[i]) for i in range(k)]
+
+
+def kcut_gda_init(graph, params: dict, x0=None, stream=None) -> Context:
+    """graph: n, k, symmetric CSR row_ptr / col_idx / w (int32); x0: (B, n, k)
+    logits or None (the library's generator)."""
+    lib, keep = load(), _Keep()
+    g = _abi.pdbo_kcut()
+    g.n, g.k = int(graph.n), int(graph.k)
+    g.row_ptr = _ptr(keep.arr(graph.row_ptr, np.int32))
+    col = keep.arr(graph.col_idx, np.int32)
+    g.col_idx = _ptr(col)
+    g.w = _ptr(keep.arr(graph.w, np.int32))
+    g.nnz = int(len(col))
+    par = _params_struct(params, x0, keep)
+    h = ctypes.c_void_p()
+    check(lib.kcut_gda_init(ctypes.byref(g), ctypes.byref(par),
+                            stream if stream is not None else _current_stream(), ctypes.byref(h)))
+    return Context(h, int(graph.n), int(params["B"]), "kcut", k=int(graph.k))
 
 
 def maxsat_gda_init(f, params: dict, x0, stream=None) -> Context:

@@ -29,6 +29,11 @@ class pdbo_maxsat(ctypes.Structure):
     _fields_ = [("n", c_int32), ("m", c_int32), ("k", c_int32), ("lits", c_void_p), ("w", c_void_p)]
 
 
+class pdbo_kcut(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("k", c_int32), ("row_ptr", c_void_p), ("col_idx", c_void_p),
+                ("w", c_void_p), ("nnz", c_int64)]
+
+
 class pdbo_params(ctypes.Structure):
     _fields_ = [("B", c_int32), ("g_kind", c_int32), ("precision", c_int32), ("eval_every", c_int32),
                 ("alpha", c_double), ("beta", c_double), ("y0", c_double), ("delta", c_double),
@@ -65,6 +70,7 @@ SIGNATURES = {
     "qubo_gda_batch_result": (_st, [_ctx, c_int32, POINTER(pdbo_result)]),
     "qubo_gda_batch_solve": (_st, [c_int32, POINTER(pdbo_qubo), POINTER(pdbo_params), c_int32,
                                    c_int32, c_void_p, POINTER(pdbo_result)]),
+    "kcut_gda_init": (_st, [POINTER(pdbo_kcut), POINTER(pdbo_params), c_void_p, POINTER(_ctx)]),
     "maxsat_gda_init": (_st, [POINTER(pdbo_maxsat), POINTER(pdbo_params), c_void_p, POINTER(_ctx)]),
     "maxsat_gda_step": (_st, [_ctx, c_int32]),
     "maxsat_gda_result": (_st, [_ctx, POINTER(pdbo_result)]),

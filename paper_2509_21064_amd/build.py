@@ -42,6 +42,7 @@ UNITS = [
     ("maxsat.hip", "maxsat.o", []),
     ("spmm.hip", "spmm.o", []),
     ("cert.hip", "cert.o", []),
+    ("kcut.hip", "kcut.o", []),
     ("api.hip", "api.o", []),
 ]
 SOURCES = sorted({u[0] for u in UNITS})

@@ -68,7 +68,8 @@ struct TimedLaunch {
 };
 
 struct pdbo_ctx {
-  int kind = 0;  // 0 dense (one or many instances), 1 CSR resident, 2 MaxSAT, 3 CSR row-parallel
+  int kind = 0;  // 0 dense (one or many instances), 1 CSR resident, 2 MaxSAT, 3 CSR row-parallel,
+                 // 4 Max-k-Cut
   hipStream_t stream = nullptr;
   std::string err;
   pdbo_params par{};
@@ -118,6 +119,8 @@ struct pdbo_ctx {
   // CSR / MaxSAT persistent (kind 1, 2); row-parallel CSR (kind 3) keeps its
   // iterates in spmm and the canonical matrix also in csr (for qubo_gda_eval)
   SpmmDev spmm{};
+  KcutDev kcut{};  // Max-k-Cut (kind 4)
+  float *kz_scratch = nullptr, *kg_scratch = nullptr;  // node-major (B, n, k) for grad()
   CsrDev csr{};
   bool compact = false;
   SatDev sat{};
@@ -1557,16 +1560,31 @@ pdbo_status spmm_one_step(pdbo_ctx* c) {
   return PDBO_OK;
 }
 
-// Each iteration evaluates round(x^t) in the gathers of its own gradient, so
-// after the last one the rounded x^T is evaluated by a pass of its own.
-pdbo_status spmm_steps(pdbo_ctx* c, int nsteps) {
+pdbo_status kcut_one_step(pdbo_ctx* c) {
+  TimedLaunch tl;
+  t_begin(c, tl, PDBO_K_STEP);
+  HIPCHK(c, launch_kcut(c->kcut, 0, c->parity, nullptr, c->stream));
+  t_end(c, tl);
+  t_begin(c, tl, PDBO_K_ARGMIN);
+  HIPCHK(c, launch_kcut_best(c->kcut, c->parity, 1, c->stream));
+  t_end(c, tl);
+  c->parity ^= 1;
+  c->t_host += 1;
+  return PDBO_OK;
+}
+
+// The row-parallel paths (kinds 3 and 4): each iteration evaluates round(x^t)
+// in the gathers of its own gradient, so after the last one the rounded x^T
+// is evaluated by a pass of its own.  With graph_chunk = K, K iterations are
+// recorded once (on a private stream: the caller's may be the legacy default)
+// and replayed.
+pdbo_status rowpar_steps(pdbo_ctx* c, int nsteps, pdbo_status (*one)(pdbo_ctx*)) {
   const int K = c->par.graph_chunk;
   const bool use_graph = K > 0 && !c->timing;
   int left = nsteps;
   while (left > 0) {
     if (use_graph && left >= K) {
       if (!c->gexec) {
-        // recorded on a private stream: the caller's may be the legacy default
         if (!c->cap_stream)
           HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1580,7 +1598,7 @@ pdbo_status spmm_steps(pdbo_ctx* c, int nsteps) {
           return hipfail(c, "hipStreamBeginCapture", e);
         }
         pdbo_status st = PDBO_OK;
-        for (int k = 0; k < K && st == PDBO_OK; ++k) st = spmm_one_step(c);
+        for (int k = 0; k < K && st == PDBO_OK; ++k) st = one(c);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(c->stream, &g);
         c->stream = user;
@@ -1596,7 +1614,7 @@ pdbo_status spmm_steps(pdbo_ctx* c, int nsteps) {
         c->graph_parity0 = par_save;
       }
       if (c->parity != c->graph_parity0) {
-        STCHK(spmm_one_step(c));
+        STCHK(one(c));
         --left;
         continue;
       }
@@ -1605,16 +1623,22 @@ pdbo_status spmm_steps(pdbo_ctx* c, int nsteps) {
       c->parity ^= (K & 1);
       left -= K;
     } else {
-      STCHK(spmm_one_step(c));
+      STCHK(one(c));
       --left;
     }
   }
   TimedLaunch tl;
   t_begin(c, tl, PDBO_K_EVAL);
-  HIPCHK(c, launch_spmm(c->spmm, 1, c->parity, nullptr, c->stream));
+  if (c->kind == 3)
+    HIPCHK(c, launch_spmm(c->spmm, 1, c->parity, nullptr, c->stream));
+  else
+    HIPCHK(c, launch_kcut(c->kcut, 1, c->parity, nullptr, c->stream));
   t_end(c, tl);
   t_begin(c, tl, PDBO_K_ARGMIN);
-  HIPCHK(c, launch_spmm_best(c->spmm, c->parity, 0, c->stream));
+  if (c->kind == 3)
+    HIPCHK(c, launch_spmm_best(c->spmm, c->parity, 0, c->stream));
+  else
+    HIPCHK(c, launch_kcut_best(c->kcut, c->parity, 0, c->stream));
   t_end(c, tl);
   return PDBO_OK;
 }
@@ -1643,7 +1667,8 @@ pdbo_status qubo_gda_step(pdbo_ctx* c, int32_t nsteps) {
     c->stamped = true;
   }
   if (c->kind == 0) return dense_steps(c, nsteps);
-  if (c->kind == 3) return spmm_steps(c, nsteps);
+  if (c->kind == 3) return rowpar_steps(c, nsteps, spmm_one_step);
+  if (c->kind == 4) return rowpar_steps(c, nsteps, kcut_one_step);
   TimedLaunch tl;
   t_begin(c, tl, PDBO_K_PERSISTENT);
   if (c->kind == 1)
@@ -1664,6 +1689,7 @@ pdbo_status qubo_gda_result(pdbo_ctx* c, pdbo_result* r) {
   const int B = c->B;
   const int n = c->n_of[0];
   if (c->kind == 3) return fill_result(c, c->spmm.inc, c->spmm.best_x, n, r);
+  if (c->kind == 4) return fill_result(c, c->kcut.inc, c->kcut.best_x, n, r);
   if (c->kind == 1)
     HIPCHK(c, launch_restart_best(c->csr.rbestF, c->csr.rbestT, c->csr.rbestTs, c->csr.best_xr, B,
                                   n, c->inc_d, c->best_x_d, c->stream));
@@ -1724,9 +1750,37 @@ static pdbo_status spmm_upload(pdbo_ctx* c, const float* src, float* dst) {
   return PDBO_OK;
 }
 
+// Max-k-Cut: node-major [n][B][m] <-> restart-major [B][n][m] (m = k or 1).
+static pdbo_status kcut_download(pdbo_ctx* c, const float* src, float* dst, int m) {
+  const int n = c->kcut.n, B = c->B;
+  std::vector<float> h((size_t)n * B * m);
+  HIPCHK(c, hipMemcpy(h.data(), src, h.size() * sizeof(float), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i)
+    for (int b = 0; b < B; ++b)
+      for (int u = 0; u < m; ++u) dst[((size_t)b * n + i) * m + u] = h[((size_t)i * B + b) * m + u];
+  return PDBO_OK;
+}
+
+static pdbo_status kcut_upload(pdbo_ctx* c, const float* src, float* dst, int m) {
+  const int n = c->kcut.n, B = c->B;
+  std::vector<float> h((size_t)n * B * m);
+  for (int i = 0; i < n; ++i)
+    for (int b = 0; b < B; ++b)
+      for (int u = 0; u < m; ++u) h[((size_t)i * B + b) * m + u] = src[((size_t)b * n + i) * m + u];
+  HIPCHK(c, hipMemcpy(dst, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+  return PDBO_OK;
+}
+
 pdbo_status qubo_gda_get_state(pdbo_ctx* c, float* x, float* y, int64_t* t) {
   if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (c->kind == 4) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (x) STCHK(kcut_download(c, c->kcut.Z, x, c->kcut.k));
+    if (y) STCHK(kcut_download(c, c->kcut.Y, y, 1));
+    if (t) *t = c->t_host;
+    return PDBO_OK;
+  }
   if (c->kind == 3) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (x) STCHK(spmm_download(c, c->spmm.X[c->parity], x));
@@ -1758,6 +1812,29 @@ pdbo_status qubo_gda_set_state(pdbo_ctx* c, const float* x, const float* y, int6
   if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
   if (t < 0) return fail(c, PDBO_EINVAL, "t must be >= 0");
+  if (c->kind == 4) {  // x: the logits Z (B, n, k); X = softmax(Z) follows
+    KcutDev& d = c->kcut;
+    const size_t tz = (size_t)c->B * d.n * d.k, ty = (size_t)c->B * d.n;
+    if (x)
+      for (size_t i = 0; i < tz; ++i)
+        if (!std::isfinite(x[i])) return fail(c, PDBO_EINVAL, "Z must be finite");
+    if (y)
+      for (size_t i = 0; i < ty; ++i)
+        if (!std::isfinite(y[i])) return fail(c, PDBO_EINVAL, "y must be finite");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (x) {
+      TempDev tx, tyd;
+      STCHK(temp_upload(c, tx, x, tz * sizeof(float)));
+      if (y) STCHK(temp_upload(c, tyd, y, ty * sizeof(float)));
+      HIPCHK(c, launch_kcut_set((const float*)tx.p, (const float*)tyd.p, d, c->parity, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else if (y) {
+      STCHK(kcut_upload(c, y, d.Y, 1));
+    }
+    c->t_host = t;
+    HIPCHK(c, hipMemcpy(d.t_dev, &t, sizeof(t), hipMemcpyHostToDevice));
+    return PDBO_OK;
+  }
   float *X, *Y;
   int ld, n;
   state_ptrs(c, &X, &Y, &ld, &n);
@@ -1807,6 +1884,28 @@ pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
   if (!c) return fail(nullptr, PDBO_ESTATE, "context is NULL");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
   const int n = c->n_of[0], B = c->B;
+  if (c->kind == 4) {  // x0: the logits Z^0 (B, n, k)
+    KcutDev& d = c->kcut;
+    const size_t tz = (size_t)B * n * d.k;
+    if (x0)
+      for (size_t i = 0; i < tz; ++i)
+        if (!std::isfinite(x0[i])) return fail(c, PDBO_EINVAL, "Z^0 must be finite");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    TempDev t;
+    STCHK(upload_x0(c, t, x0, tz));
+    c->parity = 0;
+    HIPCHK(c, launch_kcut_init((const double*)t.p, d, (float)c->par.y0, c->par.seed, c->stream));
+    const int64_t zero = 0;
+    Incumbent init{kI64Max, -1, -1, 0};
+    HIPCHK(c, hipMemcpyAsync(d.t_dev, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_fill_i32(d.trace_len, 0, 1, c->stream));
+    HIPCHK(c, launch_fill_i64((int64_t*)c->ts0_d, 0, 1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->t_host = 0;
+    c->stamped = false;
+    return PDBO_OK;
+  }
   const size_t tot = (size_t)B * n;
   if (x0)
     for (size_t i = 0; i < tot; ++i)
@@ -1870,6 +1969,7 @@ pdbo_status qubo_gda_objectives(pdbo_ctx* c, int64_t* F) {
   const int64_t* src = c->kind == 0   ? c->insts_h[0].Fall
                        : c->kind == 1 ? c->csr.Flast
                        : c->kind == 3 ? c->spmm.Flast
+                       : c->kind == 4 ? c->kcut.Flast
                                       : c->sat.Flast;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(F, src, c->B * sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -1883,6 +1983,8 @@ static pdbo_status ensure_scratch(pdbo_ctx* c) {
     ld = c->insts_h[0].ld;
   else if (c->kind == 1 || c->kind == 3)
     ld = c->csr.ld;
+  else if (c->kind == 4)
+    ld = roundup(c->kcut.n, kLdAlign);
   else
     ld = c->sat.ld;
   const size_t sz = (size_t)c->B * ld;
@@ -1903,6 +2005,26 @@ pdbo_status qubo_gda_grad(pdbo_ctx* c, const float* x, float* G) {
   if (!c || !x || !G) return fail(c, PDBO_EINVAL, "NULL argument");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
   STCHK(ensure_scratch(c));
+  if (c->kind == 4) {  // x: the logits Z (B, n, k); G: d(f/s)/dZ, same layout
+    KcutDev d = c->kcut;
+    const size_t tz = (size_t)c->B * d.n * d.k;
+    for (size_t i = 0; i < tz; ++i)
+      if (!std::isfinite(x[i])) return fail(c, PDBO_EINVAL, "Z must be finite");
+    if (!c->kz_scratch) {
+      STCHK(dalloc(c, &c->kz_scratch, 3 * tz));
+      STCHK(dalloc(c, &c->kg_scratch, tz));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    TempDev tx;
+    STCHK(temp_upload(c, tx, x, tz * sizeof(float)));
+    d.Z = c->kz_scratch;
+    d.X[0] = c->kz_scratch + tz;
+    d.X[1] = c->kz_scratch + 2 * tz;
+    HIPCHK(c, launch_kcut_set((const float*)tx.p, nullptr, d, 0, c->stream));
+    HIPCHK(c, launch_kcut(d, 2, 0, c->kg_scratch, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return kcut_download(c, c->kg_scratch, G, d.k);
+  }
   int n = c->n_of[0];
   const size_t tot = (size_t)c->B * n;
   for (size_t i = 0; i < tot; ++i)
@@ -1952,9 +2074,18 @@ pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
   if (nb < 1 || nb > c->B) return fail(c, PDBO_EINVAL, "nb must be in [1, B]");
   const int n = c->n_of[0];
+  const int vmax = c->kind == 4 ? c->kcut.k - 1 : 1;  // Max-k-Cut: categories 0..k-1
   for (size_t i = 0; i < (size_t)nb * n; ++i)
-    if (xr[i] > 1) return fail(c, PDBO_EINVAL, "xr must be 0/1 bytes");
+    if (xr[i] > vmax) return fail(c, PDBO_EINVAL, "xr must be 0/1 bytes (categories 0..k-1 for Max-k-Cut)");
   STCHK(ensure_scratch(c));
+  if (c->kind == 4) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->xr_scratch, xr, (size_t)nb * n, hipMemcpyHostToDevice));
+    HIPCHK(c, launch_kcut_eval(c->kcut, (const uint8_t*)c->xr_scratch, nb, c->f_scratch, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(F, c->f_scratch, nb * sizeof(int64_t), hipMemcpyDeviceToHost));
+    return PDBO_OK;
+  }
   const int ld = c->kind == 0 ? c->insts_h[0].ld : (c->kind == 1 || c->kind == 3) ? c->csr.ld : c->sat.ld;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemsetAsync(c->xr_scratch, 0, (size_t)c->B * ld, c->stream));
@@ -1989,9 +2120,12 @@ pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* c, const uint8_t* xr, int32_t nb, in
   const hipStream_t s = (hipStream_t)stream;
   const int n = c->n_of[0];
   if (c->kind != 0) {
-    // the CSR and MaxSAT evaluation kernels read the caller's rows directly
-    // (row stride n, nonzero bytes are 1) and need no scratch
-    if (c->kind == 1 || c->kind == 3) {
+    // the CSR, MaxSAT and Max-k-Cut evaluation kernels read the caller's rows
+    // directly (row stride n; nonzero bytes are 1, or categories for
+    // Max-k-Cut) and need no scratch
+    if (c->kind == 4) {
+      HIPCHK(c, launch_kcut_eval(c->kcut, xr, nb, F, s));
+    } else if (c->kind == 1 || c->kind == 3) {
       CsrDev d = c->csr;
       d.ld = n;
       HIPCHK(c, launch_csr_eval(d, (const int8_t*)xr, nb, F, s));
@@ -2037,7 +2171,8 @@ pdbo_status qubo_dual_bound(pdbo_ctx* c, double ybar, int32_t iters, double* low
                             double* value, float* x_out) {
   if (!c || !lower_bound) return fail(c, PDBO_EINVAL, "NULL argument");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
-  if (c->kind == 2) return fail(c, PDBO_EUNSUPPORTED, "the dual certificate is built for QUBO contexts");
+  if (c->kind == 2 || c->kind == 4)
+    return fail(c, PDBO_EUNSUPPORTED, "the dual certificate is built for QUBO contexts");
   if (c->par.g_kind != PDBO_G_QUAD)
     return fail(c, PDBO_EUNSUPPORTED, "the dual certificate is built for the quadratic g");
   if (ybar == 0.0) ybar = c->par.y0;
@@ -2187,6 +2322,114 @@ static pdbo_status check_maxsat(const pdbo_maxsat* s) {
     if (s->w && (s->w[j] < 0 || s->w[j] >= (1 << 24)))
       return fail(nullptr, PDBO_EINVAL, "clause weights must be in [0, 2^24)");
   }
+  return PDBO_OK;
+}
+
+static pdbo_status check_kcut(const pdbo_kcut* g, const pdbo_params* p) {
+  if (!g) return fail(nullptr, PDBO_EINVAL, "problem is NULL");
+  if (g->n < 1 || g->n > 65536) return fail(nullptr, PDBO_EINVAL, "n must be in [1, 65536]");
+  if (g->k < 2 || g->k > 8) return fail(nullptr, PDBO_EINVAL, "k must be in [2, 8]");
+  if (!g->row_ptr || (g->nnz > 0 && (!g->col_idx || !g->w)))
+    return fail(nullptr, PDBO_EINVAL, "CSR arrays are NULL");
+  if (g->nnz < 0 || g->nnz > (int64_t)INT_MAX) return fail(nullptr, PDBO_EINVAL, "bad nnz");
+  const int n = g->n;
+  if (g->row_ptr[0] != 0 || (int64_t)g->row_ptr[n] != g->nnz)
+    return fail(nullptr, PDBO_EINVAL, "row_ptr must start at 0 and end at nnz");
+  for (int i = 0; i < n; ++i) {
+    if (g->row_ptr[i + 1] < g->row_ptr[i]) return fail(nullptr, PDBO_EINVAL, "row_ptr must be non-decreasing");
+    int64_t rs = 0;
+    for (int q = g->row_ptr[i]; q < g->row_ptr[i + 1]; ++q) {
+      const int j = g->col_idx[q];
+      if (j < 0 || j >= n || j == i) return fail(nullptr, PDBO_EINVAL, "column out of range or on the diagonal");
+      if (q > g->row_ptr[i] && j <= g->col_idx[q - 1])
+        return fail(nullptr, PDBO_EINVAL, "columns of a row must be strictly increasing");
+      // the mirror entry (j, i) with the same weight
+      const int32_t* b = g->col_idx + g->row_ptr[j];
+      const int32_t* e = g->col_idx + g->row_ptr[j + 1];
+      const int32_t* f = std::lower_bound(b, e, i);
+      if (f == e || *f != i || g->w[g->row_ptr[j] + (f - b)] != g->w[q])
+        return fail(nullptr, PDBO_EINVAL, "W must be symmetric with both directions stored");
+      rs += g->w[q] < 0 ? -(int64_t)g->w[q] : g->w[q];
+    }
+    if (rs >= (int64_t(1) << 31)) return fail(nullptr, PDBO_ERANGE, "a row of |W| sums to 2^31 or more");
+  }
+  STCHK(check_params(p, n, false));
+  if (p->x0) {
+    const size_t tot = (size_t)p->B * n * g->k;
+    for (size_t i = 0; i < tot; ++i)
+      if (!std::isfinite(p->x0[i])) return fail(nullptr, PDBO_EINVAL, "x0 (the logits Z^0) must be finite");
+  }
+  if (p->g_kind == PDBO_G_POLY || p->dual_kind != PDBO_DUAL_VECTOR)
+    return fail(nullptr, PDBO_EUNSUPPORTED, "Max-k-Cut takes the quadratic or entropy g with a dual per node");
+  if (p->eval_every != 1) return fail(nullptr, PDBO_EUNSUPPORTED, "Max-k-Cut evaluates every iteration");
+  return PDBO_OK;
+}
+
+pdbo_status kcut_gda_init(const pdbo_kcut* g, const pdbo_params* p, void* stream, pdbo_ctx** out) {
+  if (!out) return fail(nullptr, PDBO_EINVAL, "out is NULL");
+  *out = nullptr;
+  STCHK(check_kcut(g, p));
+  const int n = g->n, B = p->B, k = g->k;
+  pdbo_ctx* c = new pdbo_ctx();
+  c->kind = 4;
+  c->n_of.push_back(n);
+  pdbo_status st = begin_ctx(c, stream, p);
+  auto run = [&]() -> pdbo_status {
+    KcutDev& d = c->kcut;
+    std::memset(&d, 0, sizeof(d));
+    d.n = n;
+    d.B = B;
+    d.k = k;
+    d.trace_cap = kTraceCap;
+    d.tos = (float)(2.0 / p->scale);
+    d.gp = make_gp(p);
+    d.W = std::min(B, 64);
+    d.G = 64 / d.W;
+    d.nslices = (B + d.W - 1) / d.W;
+    const int nrb = (n + 4 * d.G - 1) / (4 * d.G);
+    d.grid = std::max(1, std::min(nrb, std::max(1, 2048 / d.nslices))) * d.nslices;
+    const int64_t nnz = g->nnz;
+    int32_t *rp = nullptr, *col = nullptr, *w = nullptr;
+    STCHK(dalloc(c, &rp, n + 1));
+    STCHK(dalloc(c, &col, nnz));
+    STCHK(dalloc(c, &w, nnz));
+    HIPCHK(c, hipMemcpyAsync(rp, g->row_ptr, (n + 1) * 4, hipMemcpyHostToDevice, c->stream));
+    if (nnz > 0) {
+      HIPCHK(c, hipMemcpyAsync(col, g->col_idx, nnz * 4, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(w, g->w, nnz * 4, hipMemcpyHostToDevice, c->stream));
+    }
+    d.row_ptr = rp;
+    d.col = col;
+    d.w = w;
+    const size_t sz = (size_t)n * B * k;
+    STCHK(dalloc(c, &d.Z, sz));
+    STCHK(dalloc(c, &d.X[0], sz));
+    STCHK(dalloc(c, &d.X[1], sz));
+    STCHK(dalloc(c, &d.Y, (size_t)n * B));
+    STCHK(dalloc(c, &d.part, (size_t)d.grid * d.W));
+    STCHK(dalloc(c, &d.Flast, B));
+    STCHK(dalloc(c, &d.inc, 1));
+    STCHK(dalloc(c, &d.best_x, n));
+    STCHK(dalloc(c, &d.trace, kTraceCap));
+    STCHK(dalloc(c, &d.trace_len, 1));
+    STCHK(dalloc(c, &d.t_dev, 1));
+    d.ts0 = c->ts0_d;
+    Incumbent init{kI64Max, -1, -1, 0};
+    HIPCHK(c, hipMemcpyAsync(d.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    TempDev t;
+    STCHK(upload_x0(c, t, p->x0, (size_t)B * n * k));
+    HIPCHK(c, launch_kcut_init((const double*)t.p, d, (float)p->y0, p->seed, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDBO_OK;
+  };
+  if (st == PDBO_OK) st = run();
+  if (st != PDBO_OK) {
+    const std::string msg = c->err.empty() ? g_last_error : c->err;
+    pdbo_destroy(c);
+    g_last_error = msg;
+    return st;
+  }
+  *out = c;
   return PDBO_OK;
 }
 
@@ -2355,6 +2598,9 @@ pdbo_status qubo_gda_trace(pdbo_ctx* c, int32_t cap, int64_t* t, int64_t* F, int
   } else if (c->kind == 3) {
     trace_d = c->spmm.trace;
     len_d = c->spmm.trace_len;
+  } else if (c->kind == 4) {
+    trace_d = c->kcut.trace;
+    len_d = c->kcut.trace_len;
   } else {
     return PDBO_OK;
   }

@@ -308,6 +308,39 @@ hipError_t launch_spmm_best(const SpmmDev& d, int parity, int advance, hipStream
 // node-major state <-> restart-major host layout helpers on the device
 hipError_t launch_spmm_init(const double* x0, const SpmmDev& d, float y0, uint64_t seed,
                             hipStream_t s);
+// ---- launchers (kcut.hip) ---------------------------------------------------
+//
+// Max-k-Cut through the softmax reparametrisation: logits Z, probabilities X,
+// node-major [n][B][k]; duals Y [n][B]; the same lane groups as SpmmDev.
+struct KcutDev {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const int32_t* w;       // symmetric edge weights, both directions stored
+  float* Z;
+  float* X[2];            // softmax(Z), ping-pong
+  float* Y;
+  int64_t* part;          // [grid][W] per-workgroup same-category weight (edges twice)
+  int64_t* Flast;
+  Incumbent* inc;
+  uint8_t* best_x;        // [n] categories of the incumbent
+  TraceRec* trace;
+  int32_t* trace_len;
+  int64_t* t_dev;
+  uint64_t* ts0;
+  int n, B, k, trace_cap;
+  int W, G, nslices, grid;
+  float tos;              // 2 / s
+  GdaP gp;
+};
+hipError_t launch_kcut(const KcutDev& d, int mode, int parity, float* G, hipStream_t s);
+hipError_t launch_kcut_best(const KcutDev& d, int parity, int advance, hipStream_t s);
+hipError_t launch_kcut_init(const double* z0, const KcutDev& d, float y0, uint64_t seed,
+                            hipStream_t s);
+hipError_t launch_kcut_set(const float* z, const float* y, const KcutDev& d, int parity,
+                           hipStream_t s);
+hipError_t launch_kcut_eval(const KcutDev& d, const uint8_t* cat, int nb, int64_t* F,
+                            hipStream_t s);
+
 // ---- launchers (cert.hip) ---------------------------------------------------
 //
 // Certified lower bound on min F from the Lagrangian at y = ybar * 1 with the

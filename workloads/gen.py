@@ -27,7 +27,7 @@ __all__ = [
     "Qubo", "MaxSat", "rng_for", "x0_uniform",
     "gnp_pm1", "qubo_c1", "qubo_c1_twin", "maxcut_c2", "qubo_c3", "batch_c4",
     "maxsat_c5", "random_dense_qubo", "random_asym_qubo", "random_maxsat",
-    "random_regular_graph", "mis_qubo",
+    "random_regular_graph", "mis_qubo", "Kcut", "kcut_graph",
 ]
 
 
@@ -215,6 +215,35 @@ def mis_qubo(n: int, d: int, rep: int = 0, lam: int = 4) -> Qubo:
     rp, col, val = _csr_from_upper(n, E[:, 0], E[:, 1], np.full(len(E), lam // 2, dtype=np.int64))
     return Qubo(n=n, row_ptr=rp, col_idx=col, vals=val, c=np.full(n, -1, dtype=np.int64),
                 name=f"mis_d{d}_n{n}", meta=dict(edges=E, d=d, lam=lam))
+
+
+@dataclass
+class Kcut:
+    n: int
+    k: int
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    w: np.ndarray
+    name: str = ""
+
+
+def kcut_graph(n: int, M: int, k: int, rep: int = 0, signed: bool = True) -> Kcut:
+    """Max-k-Cut instance on G(n, M): M distinct edges, weights +-1 with
+    probability 1/2 (or all 1), symmetric CSR with both directions."""
+    rng = rng_for(7, rep, 0, n, M, k)
+    keys = np.zeros(0, dtype=np.int64)
+    while len(keys) < M:  # distinct unordered pairs, drawn uniformly
+        a = rng.integers(0, n, size=2 * (M - len(keys)) + 16)
+        b = rng.integers(0, n, size=a.shape[0])
+        ok = a != b
+        new = np.minimum(a, b)[ok] * n + np.maximum(a, b)[ok]
+        keys = np.concatenate([keys, new])
+        _, first = np.unique(keys, return_index=True)
+        keys = keys[np.sort(first)][:M]
+    i, j = keys // n, keys % n
+    w = np.where(rng.random(M) < 0.5, 1, -1) if signed else np.ones(M, dtype=np.int64)
+    rp, col, val = _csr_from_upper(n, i, j, w.astype(np.int64))
+    return Kcut(n=n, k=k, row_ptr=rp, col_idx=col, w=val, name=f"kcut{k}_n{n}_m{M}")
 
 
 def qubo_c3(rep: int = 0, n: int = 10000) -> Qubo:
