@@ -312,6 +312,138 @@ def workload_c5(args, P):
     return out
 
 
+def _timed_run(ctx, T, steps_cls, P):
+    """Wall time of T iterations (HIP-event timed by the library per kernel
+    class as well), after one untimed warm-up call."""
+    import torch
+    ctx.step(2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.step(T)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
+
+
+def workload_mis(args, P):
+    """MIS on a d-regular graph (App. D): penalised QUBO with lam = 4, B = 10,
+    y0 = 5, alpha = beta = 0.02 (tab:hyper_parameters), row-parallel CSR path."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import mis as om
+    from oracle import qubo as oq
+    n, d, B = args.mis_n, args.mis_d, 10
+    T = args.T if args.T != 2000 else 10000  # the dual needs ~5000 iterations to reach y <= 0 at d = 100
+    q = W.mis_qubo(n, d, 0)
+    # the scale of the other dense-curvature workloads: with s = 1 the stiff
+    # all-ones direction (curvature lam d) makes the first steps clip every
+    # coordinate to 0 at d = 100, and the regular graph never breaks the symmetry
+    s = W.qubo_scale(q)
+    p = W.gda_params("qubo", B=B, T=T, scale=s, alpha=0.02, beta=0.02, y0=5.0, tile=2,
+                     graph_chunk=args.graph_chunk)
+    ctx = P.qubo_gda_init(q, p, None)
+    el = _timed_run(ctx, T, None, P)
+    # kernel times over a second run (timing on: launches recorded one by one)
+    ctx.restart(None)
+    ctx.timing(True, classes=[P.PDBO_K_STEP, P.PDBO_K_ARGMIN])
+    ctx.step(T)
+    k_step = ctx.kernel_time(P.PDBO_K_STEP)
+    k_best = ctx.kernel_time(P.PDBO_K_ARGMIN)
+    ctx.timing(False)
+    r = ctx.result()
+    E = q.meta["edges"]
+    size, inside = om.set_size(E, r["best_x"][None])
+    nnz = int(q.row_ptr[-1])
+    step_ms = k_step[0] / max(k_step[1], 1)
+    # compulsory bytes of one iteration: the CSR arrays once, x read and
+    # written, y read and written (node-major float32); the neighbour gathers
+    # (B floats per nonzero) are served by the caches
+    hbm = 8 * nnz + 4 * (n + 1) + 16 * n * B
+    gath = 4 * B * nnz
+    out = dict(metric="restart-iterations/s, MIS (penalised QUBO, lam = 4)", value=B * T / el,
+               unit=UNIT, workload=f"MIS d-regular n={n} d={d}, B={B}, T={T}, row-parallel CSR",
+               ms_per_step=1e3 * el / T, step_kernel_ms=step_ms, best_kernel_ms=k_best[0] / max(k_best[1], 1),
+               best_F=int(r["best_obj"]), iter_of_best=int(r["best_iter"]),
+               set_size=int(size[0]) if inside[0] == 0 else None, edges_inside=int(inside[0]),
+               exact=bool(r["best_obj"] == oq.objective(q, r["best_x"][None])[0]),
+               roofline=dict(bound="hbm", kernel="spmm_kernel<quad, step>",
+                             achieved=(hbm + gath) / (step_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                             unit="GB/s", frac=(hbm + gath) / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             compulsory_bytes=hbm, gathered_bytes=gath,
+                             note="achieved counts the gathered bytes as well (served from L2/MALL)"))
+    ctx.destroy()
+    if not args.no_cpu:
+        out["cpu_baseline"] = _cpu_rate(oq.QuboProblem(q, s), W.x0_uniform(6, 0, B, n), p, B,
+                                        args.cpu_seconds, T)
+    return out
+
+
+def workload_kcut(args, P):
+    """Max-3-Cut (App. B) on a G(n, M) graph with +-1 weights of the size of
+    Gset's G67/G72 (n = 10,000, 20,000 edges), B = 100, y0 = 6,
+    alpha = beta = 0.01 (tab:hyper_parameters)."""
+    import workloads as W
+    from oracle import kcut as ok
+    n, M, k, B, T = 10000, 20000, 3, 100, args.T
+    g = W.kcut_graph(n, M, k, rep=0)
+    G = ok.Graph(g)
+    p = dict(B=B, T=T, alpha=0.01, beta=0.01, y0=6.0, delta=2.0 ** -7, scale=1.0, g="quad",
+             graph_chunk=args.graph_chunk, seed=1)
+    ctx = P.kcut_gda_init(g, p, None)
+    el = _timed_run(ctx, T, None, P)
+    ctx.restart(None)
+    ctx.timing(True, classes=[P.PDBO_K_STEP, P.PDBO_K_ARGMIN])
+    ctx.step(T)
+    k_step = ctx.kernel_time(P.PDBO_K_STEP)
+    ctx.timing(False)
+    r = ctx.result()
+    nnz = int(g.row_ptr[-1])
+    step_ms = k_step[0] / max(k_step[1], 1)
+    hbm = 8 * nnz + 4 * (n + 1) + (4 * 4 * k + 8) * n * B  # Z r/w, X r/w, y r/w
+    gath = 4 * k * B * nnz
+    out = dict(metric="restart-iterations/s, Max-3-Cut (softmax)", value=B * T / el, unit=UNIT,
+               workload=f"Max-{k}-Cut G(n={n}, M={M}) +-1, B={B}, T={T}",
+               ms_per_step=1e3 * el / T, step_kernel_ms=step_ms, best_F=int(r["best_obj"]),
+               cut=int(G.total - r["best_obj"]), iter_of_best=int(r["best_iter"]),
+               exact=bool(r["best_obj"] == ok.objective(G, r["best_x"][None])[0]),
+               roofline=dict(bound="hbm", kernel="kcut_kernel<3, quad, step>",
+                             achieved=(hbm + gath) / (step_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                             unit="GB/s", frac=(hbm + gath) / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             compulsory_bytes=hbm, gathered_bytes=gath))
+    ctx.destroy()
+    return out
+
+
+def workload_dual(args, P):
+    """Dual certificate (App. D) on the dense n = 10,000 instance: projected
+    descent on L(., 6 * 1) through the INT8 step kernel, then the float64
+    bound; beside the best objective of a T-iteration run."""
+    import time as _t
+
+    import torch
+
+    import workloads as W
+    q = W.qubo_c3(0, n=args.n)
+    s = W.qubo_scale(q)
+    p = W.gda_params("qubo", B=args.B, T=args.T, scale=s, precision="i8")
+    ctx = P.qubo_gda_init(q, p, W.x0_uniform(3, 0, args.B, q.n))
+    ctx.step(args.T)
+    best = ctx.result()["best_obj"]
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    r = P.qubo_dual_bound(ctx, iters=args.dual_iters)
+    el = _t.perf_counter() - t0
+    ctx.destroy()
+    return dict(metric="dual certificate (lower bound on min F)", value=r["lower_bound"],
+                unit="objective", workload=f"dense QUBO n={q.n}, ybar=6, {args.dual_iters} descent "
+                                           f"iterations (INT8 step kernel, one point)",
+                seconds=el, best_F_at_T=int(best), gap_ratio=(best - r["lower_bound"]) / abs(best),
+                frank_wolfe_gap=r["gap"], rounding_bound=r["rounding"], s_L_x=r["value"],
+                higher_is_better=True)
+
+
 def workload_c4(args, P):
     """64 dense QUBOs of uneven n in [500, 5000], density 1-10%, B=128 each:
     grouped launches (optionally graph-captured) against per-instance launches."""
@@ -367,9 +499,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-restarts", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"],
+    ap.add_argument("--workload", default="c3",
+                    choices=["c3", "c2", "c4", "c5", "mis", "kcut", "dual"],
                     help="c3 (default) is the headline dense n=10k line; the others report "
-                         "the sparse, batched and MaxSAT configurations")
+                         "the sparse, batched, MaxSAT, MIS, Max-3-Cut and dual-certificate "
+                         "configurations")
+    ap.add_argument("--mis-n", type=int, default=50000)
+    ap.add_argument("--mis-d", type=int, default=100)
+    ap.add_argument("--dual-iters", type=int, default=300)
     ap.add_argument("--c4-prec", default="bf16")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (the reference for "
@@ -398,7 +535,8 @@ def main():
         return
     P.load()
     if args.workload != "c3":
-        fn = {"c2": workload_c2, "c4": workload_c4, "c5": workload_c5}[args.workload]
+        fn = {"c2": workload_c2, "c4": workload_c4, "c5": workload_c5, "mis": workload_mis,
+              "kcut": workload_kcut, "dual": workload_dual}[args.workload]
         res = fn(args, P)
         res.update(n_gpus=1, data="synthetic", higher_is_better=True)
         print(json.dumps(res), flush=True)

@@ -280,7 +280,8 @@ struct SpmmDev {
   const int64_t* cp;      // c'
   float* X[2];            // node-major ping-pong iterate
   float* Y;               // node-major dual iterate
-  int64_t* part;          // [grid][2][W]: per-workgroup partial sums S, C of its slice
+  int64_t* part;          // [nslices][2][W][grid / nslices]: partial sums S, C of each
+                          // restart from every workgroup of its slice
   int64_t* Flast;         // [B] objectives of the last evaluation
   Incumbent* inc;
   uint8_t* best_x;        // [n]
@@ -319,7 +320,8 @@ struct KcutDev {
   float* Z;
   float* X[2];            // softmax(Z), ping-pong
   float* Y;
-  int64_t* part;          // [grid][W] per-workgroup same-category weight (edges twice)
+  int64_t* part;          // [nslices][W][grid / nslices]: same-category weight (edges
+                          // twice) of each restart from every workgroup of its slice
   int64_t* Flast;
   Incumbent* inc;
   uint8_t* best_x;        // [n] categories of the incumbent

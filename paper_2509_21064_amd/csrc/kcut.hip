@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kKcutThreads) kcut_kernel(KcutDev D, int parit
     __syncthreads();
     if (bok && S) atomicAdd(&sred[bl], (unsigned long long)S);
     __syncthreads();
-    if (tid < W) D.part[(size_t)blockIdx.x * W + tid] = (int64_t)sred[tid];
+    if (tid < W) D.part[((size_t)slice * W + tid) * gpw + blockIdx.x / D.nslices] = (int64_t)sred[tid];
   }
 }
 
@@ -183,12 +183,15 @@ __global__ void __launch_bounds__(kKBestThreads) kcut_best_kernel(KcutDev D, int
   const int gpw = D.grid / D.nslices;
   int64_t bestF = LLONG_MAX;
   int bestb = INT_MAX;
-  for (int b = tid; b < D.B; b += kKBestThreads) {
+  for (int b = wid; b < D.B; b += kKBestThreads / 64) {  // one wave per restart, fixed order
     const int slice = b / D.W, bl = b - slice * D.W;
+    const int64_t* pS = D.part + ((size_t)slice * D.W + bl) * gpw;
     int64_t S = 0;
-    for (int q = 0; q < gpw; ++q) S += D.part[(size_t)(q * D.nslices + slice) * D.W + bl];
+    for (int q = lane; q < gpw; q += 64) S += pS[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
     const int64_t F = S / 2;
-    D.Flast[b] = F;
+    if (lane == 0) D.Flast[b] = F;
     if (F < bestF) {
       bestF = F;
       bestb = b;

@@ -100,10 +100,10 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parit
       if (C) atomicAdd(&sred[1][bl], (unsigned long long)C);
     }
     __syncthreads();
-    if (tid < W) {
-      int64_t* part = D.part + (size_t)blockIdx.x * 2 * W;
-      part[tid] = (int64_t)sred[0][tid];
-      part[W + tid] = (int64_t)sred[1][tid];
+    if (tid < W) {  // partials of restart (slice, tid) are contiguous over the workgroups
+      const int q = blockIdx.x / D.nslices;
+      D.part[((size_t)(slice * 2 + 0) * W + tid) * gpw + q] = (int64_t)sred[0][tid];
+      D.part[((size_t)(slice * 2 + 1) * W + tid) * gpw + q] = (int64_t)sred[1][tid];
     }
   }
 }
@@ -139,17 +139,25 @@ __global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int 
   const int gpw = D.grid / D.nslices;
   int64_t bestF = LLONG_MAX;
   int bestb = INT_MAX;
-  for (int b = tid; b < D.B; b += kBestThreads) {
+  // one wave per restart: the lanes add the workgroups' partials (contiguous)
+  // in a fixed order, so the totals are the same on every run
+  for (int b = wid; b < D.B; b += kBestThreads / 64) {
     const int slice = b / D.W, bl = b - slice * D.W;
+    const int64_t* pS = D.part + ((size_t)(slice * 2 + 0) * D.W + bl) * gpw;
+    const int64_t* pC = D.part + ((size_t)(slice * 2 + 1) * D.W + bl) * gpw;
     int64_t S = 0, C = 0;
-    for (int k = 0; k < gpw; ++k) {  // fixed order
-      const int64_t* part = D.part + (size_t)(k * D.nslices + slice) * 2 * D.W;
-      S += part[bl];
-      C += part[D.W + bl];
+    for (int q = lane; q < gpw; q += 64) {
+      S += pS[q];
+      C += pC[q];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      S += __shfl_xor(S, o);
+      C += __shfl_xor(C, o);
     }
     const int64_t F = (D.kappa == 2 ? S : S / 2) + C;
-    D.Flast[b] = F;
-    if (F < bestF) {  // increasing b per thread: the first minimum is kept
+    if (lane == 0) D.Flast[b] = F;
+    if (F < bestF) {  // increasing b per wave: the first minimum is kept
       bestF = F;
       bestb = b;
     }
