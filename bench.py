@@ -111,7 +111,7 @@ def run_form(P, q, s, x0s, form, args):
         torch.cuda.synchronize()
         t_loop = e0.elapsed_time(e1) * 1e-3
         rec = dict(seed=seed, t_loop_s=t_loop, restart_it_per_s=B * T / t_loop)
-        if seed == 0:
+        if seed == 0 and not args.quick:
             # the same run goes on until it has lasted 1 s, so that the best
             # objective at 1 s is read off a run that got there
             total = T
@@ -127,7 +127,7 @@ def run_form(P, q, s, x0s, form, args):
                        iterations_in_1s_run=total, best_at_end=int(r["best_obj"]),
                        time_to_best_s=float(r["time_to_best_s"]), iter_of_best=int(r["best_iter"]))
         else:
-            rec.update(best_at_T=int(ctx.result()["best_obj"]))
+            rec.update(best_at_T=int(ctx.result()["best_obj"]), best_at_1s=None)
         runs.append(rec)
         log(f"{form}: seed {seed} T={T} in {t_loop:.4f}s = {B * T / t_loop:.4g} restart-it/s, "
             f"best@T {rec['best_at_T']}")
@@ -446,32 +446,51 @@ def workload_dual(args, P):
 
 def workload_c4(args, P):
     """64 dense QUBOs of uneven n in [500, 5000], density 1-10%, B=128 each:
-    grouped launches (optionally graph-captured) against per-instance launches."""
+    grouped launches (tiles of all instances in one launch per kernel, longest
+    instances first) against per-instance launches, both replayed as hipGraphs
+    of graph_chunk iterations past the evaluation transient."""
     import torch
 
     import workloads as W
     qs = W.batch_c4(0)
     B = 128
+    gc = args.graph_chunk or 50
     ps = [W.gda_params("qubo", B=B, T=args.T, scale=W.qubo_scale(q), precision=args.c4_prec,
-                       graph_chunk=args.graph_chunk) for q in qs]
+                       graph_chunk=gc) for q in qs]
     x0s = [W.x0_uniform(4, 0, B, q.n, i) for i, q in enumerate(qs)]
+    flops = float(sum(2.0 * q.n * q.n * B for q in qs))
+    steps = max(args.steps, gc)
     out = dict(metric="restart-iterations/s, batched uneven QUBO", unit=UNIT,
                workload=f"64 QUBOs n~U{{500..5000}}, density U[1%,10%], w~U{{-10..10}}, B={B}, "
-                        f"{args.c4_prec}")
+                        f"{args.c4_prec}, hipGraph chunks of {gc}", flop_per_iteration=flops)
     for mode, grouped in (("grouped", 1), ("per_instance", 0)):
         ctx = P.qubo_gda_batch_init(qs, ps, x0s, grouped=grouped)
-        ctx.step(args.warmup)
+        ctx.step(max(args.warmup, 70))  # past the evaluation transient
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.step(args.steps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.step(steps)
+        e1.record()
         torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out[mode] = dict(value=len(qs) * B * args.steps / el, ms_per_step=1e3 * el / args.steps,
+        el = e0.elapsed_time(e1) * 1e-3
+        ctx.timing(True, classes=[P.PDBO_K_STEP])
+        ctx.step(20)
+        kms, kn = ctx.kernel_time(P.PDBO_K_STEP)
+        ctx.timing(False)
+        step_ms = kms / 20  # all step launches of one iteration
+        out[mode] = dict(value=len(qs) * B * steps / el, ms_per_step=1e3 * el / steps,
+                         step_kernels_ms_per_iteration=step_ms, step_launches_per_iteration=kn / 20,
                          tile=ctx.tile_name)
         ctx.destroy()
-        log(f"c4 {mode}: {out[mode]['value']:.4g} restart-it/s, {out[mode]['ms_per_step']:.3f} ms/step")
-    out["value"] = out["grouped"]["value"]
-    out["speedup_grouped"] = out["grouped"]["value"] / out["per_instance"]["value"]
+        log(f"c4 {mode}: {out[mode]['value']:.4g} restart-it/s, {out[mode]['ms_per_step']:.3f} ms/step, "
+            f"step kernels {step_ms:.3f} ms/iteration")
+    g = out["grouped"]
+    achieved = flops / (g["step_kernels_ms_per_iteration"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.c4_prec]
+    out["roofline"] = dict(bound="mfma", kernel="dense_gemm_dma (grouped STEP)", achieved=achieved,
+                           peak=peak, unit="TFLOP/s", frac=achieved / peak)
+    out["value"] = g["value"]
+    out["speedup_grouped"] = g["value"] / out["per_instance"]["value"]
     return out
 
 
@@ -508,6 +527,9 @@ def main():
     ap.add_argument("--mis-d", type=int, default=100)
     ap.add_argument("--dual-iters", type=int, default=300)
     ap.add_argument("--c4-prec", default="bf16")
+    ap.add_argument("--quick", action="store_true",
+                    help="no continuation of the first run to 1 s and no CPU baseline (for runs "
+                         "under the profiler)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (the reference for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
@@ -602,7 +624,7 @@ def main():
         line["rel_gap_best_at_T_vs_fp32"] = h["rel_gap_best_at_T_vs_fp32"]
         if f32.get("best_at_1s") is not None and h.get("best_at_1s") is not None:
             line["rel_gap_best_at_1s_vs_fp32"] = (h["best_at_1s"] - f32["best_at_1s"]) / abs(f32["best_at_1s"])
-    if not args.no_cpu:
+    if not args.no_cpu and not args.quick:
         line["cpu_baseline"] = cpu_baseline(q, s, x0s[0], args)
     print(json.dumps(line), flush=True)
 

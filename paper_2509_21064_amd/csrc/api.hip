@@ -688,21 +688,32 @@ void build_tiles(pdbo_ctx* c) {
     const char* e = std::getenv("PDBO_TILE_ORDER");
     return e ? std::atoi(e) : 0;
   }();
-  for (size_t k = 0; k < c->insts_h.size(); ++k) {
+  // Instances in decreasing order of n (longest-processing-time first): a
+  // tile's work is proportional to its instance's n (its K loop), and the
+  // grouped launch hands tiles to the CUs in list order, so the long tiles
+  // start first and the short ones fill in behind them.
+  const int ninst = (int)c->insts_h.size();
+  std::vector<int> by_cost(ninst);
+  for (int k = 0; k < ninst; ++k) by_cost[k] = k;
+  std::stable_sort(by_cost.begin(), by_cost.end(),
+                   [&](int a, int b) { return c->insts_h[a].n > c->insts_h[b].n; });
+  c->tile_off.assign(ninst, 0);
+  c->tile_cnt.assign(ninst, 0);
+  for (int k : by_cost) {
     InstDev& I = c->insts_h[k];
     I.mblocks = (I.n + cf.BM - 1) / cf.BM;
     const int nb = (I.B + cf.BN - 1) / cf.BN;
     if (order == 1) {
-      c->tile_off.push_back((int)c->tiles_h.size());
+      c->tile_off[k] = (int)c->tiles_h.size();
       for (int m = 0; m < I.mblocks; ++m)
         for (int j = 0; j < nb; ++j) c->tiles_h.push_back(TileDev{(int)k, m * cf.BM, j * cf.BN, m});
-      c->tile_cnt.push_back((int)c->tiles_h.size() - c->tile_off.back());
+      c->tile_cnt[k] = (int)c->tiles_h.size() - c->tile_off[k];
       continue;
     }
     std::vector<std::vector<TileDev>> q(8);
     for (int m = 0; m < I.mblocks; ++m)
       for (int j = 0; j < nb; ++j) q[m % 8].push_back(TileDev{(int)k, m * cf.BM, j * cf.BN, m});
-    c->tile_off.push_back((int)c->tiles_h.size());
+    c->tile_off[k] = (int)c->tiles_h.size();
     size_t longest = 0;
     for (auto& v : q) longest = std::max(longest, v.size());
     std::vector<TileDev> rest;
@@ -718,7 +729,7 @@ void build_tiles(pdbo_ctx* c) {
       }
     }
     c->tiles_h.insert(c->tiles_h.end(), rest.begin(), rest.end());
-    c->tile_cnt.push_back((int)c->tiles_h.size() - c->tile_off.back());
+    c->tile_cnt[k] = (int)c->tiles_h.size() - c->tile_off[k];
   }
 }
 

@@ -235,14 +235,25 @@ __global__ void __launch_bounds__(kKBestThreads) kcut_best_kernel(KcutDev D, int
     if (advance) *D.t_dev = t + 1;
   }
   __syncthreads();
-  if (win >= 0) {
+  if (win >= 0) {  // the winner's categories; four nodes' loads in flight per thread
     const float* X = D.X[parity];
-    for (int i = tid; i < D.n; i += kKBestThreads) {
-      const float* x = X + ((size_t)i * D.B + win) * D.k;
-      int c = 0;
-      for (int u = 1; u < D.k; ++u)
-        if (x[u] > x[c]) c = u;
-      D.best_x[i] = (uint8_t)c;
+    constexpr int U = 4;
+    for (int i0 = tid; i0 < D.n; i0 += U * kKBestThreads) {
+      float v[U][8];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const float* x = X + ((size_t)min(i0 + u * kKBestThreads, D.n - 1) * D.B + win) * D.k;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[u][c] = c < D.k ? x[c] : -INFINITY;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int c = 0;
+#pragma unroll
+        for (int cc = 1; cc < 8; ++cc)
+          if (v[u][cc] > v[u][c]) c = cc;
+        if (i0 + u * kKBestThreads < D.n) D.best_x[i0 + u * kKBestThreads] = (uint8_t)c;
+      }
     }
   }
 }

@@ -200,10 +200,20 @@ __global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int 
     if (advance) *D.t_dev = t + 1;
   }
   __syncthreads();
-  if (win >= 0) {
+  if (win >= 0) {  // eight strided loads in flight per thread
     const float* X = D.X[parity];
-    for (int i = tid; i < D.n; i += kBestThreads)
-      D.best_x[i] = (uint8_t)(X[(size_t)i * D.B + win] > 0.5f);
+    constexpr int U = 8;
+    for (int i0 = tid; i0 < D.n; i0 += U * kBestThreads) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = min(i0 + u * kBestThreads, D.n - 1);
+        v[u] = X[(size_t)i * D.B + win];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * kBestThreads < D.n) D.best_x[i0 + u * kBestThreads] = (uint8_t)(v[u] > 0.5f);
+    }
   }
 }
 
