@@ -76,7 +76,8 @@ class Incumbent:
     def offer(self, F_all, t, Xr):
         b = int(np.argmin(F_all))                    # first index of the minimum
         if self.F is None or F_all[b] < self.F:
-            self.F, self.t, self.b = F_all[b].item(), t, b
+            F = F_all[b]
+            self.F, self.t, self.b = (F.item() if hasattr(F, "item") else F), t, b
             self.x = np.array(Xr[b], dtype=np.uint8)
             return True
         return False

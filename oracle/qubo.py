@@ -19,8 +19,8 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-__all__ = ["dense_Q", "canonicalize", "objective", "objective_fsum",
-           "f_multilinear", "grad_f", "QuboProblem"]
+__all__ = ["dense_Q", "canonicalize", "objective", "objective_fsum", "objective_exact",
+           "f_multilinear", "grad_f", "QuboProblem", "RealQuboProblem"]
 
 _EXACT = 2.0 ** 53
 
@@ -97,6 +97,42 @@ def objective_fsum(Q, c, x) -> float:
     return math.fsum(terms)
 
 
+_SCALE_BITS = 1074   # every finite float64 is an integer multiple of 2**-1074
+
+
+def _exact_int(v) -> int:
+    """v * 2**1074 as a Python int (exact for every finite float64)."""
+    num, den = float(v).as_integer_ratio()
+    return num * ((1 << _SCALE_BITS) // den)
+
+
+def objective_exact(q, Xr) -> np.ndarray:
+    """Exact F(x) = sum_ij Q_ij x_i x_j + sum_i c_i x_i (Eq. 1) for real
+    (float64) weights, one value per row of the binary array Xr, as
+    fractions.Fraction in an object array.  Each selected term is taken as the
+    integer v * 2**1074 and the integers are added exactly, so the value is the
+    exact real sum; float() of it is the correctly rounded float64.  q is a
+    workloads.Qubo whose Q or vals (and c) hold float64."""
+    from fractions import Fraction
+    Xr = np.atleast_2d(np.asarray(Xr)).astype(bool)
+    n = q.n
+    c = [0] * n if q.c is None else [_exact_int(v) for v in np.asarray(q.c, dtype=np.float64)]
+    if q.Q is not None:
+        rows, cols = np.nonzero(np.asarray(q.Q) != 0)
+        vals = [_exact_int(q.Q[i, j]) for i, j in zip(rows, cols)]
+    else:
+        rows = np.repeat(np.arange(n), np.diff(q.row_ptr))
+        cols = np.asarray(q.col_idx)
+        vals = [_exact_int(v) for v in np.asarray(q.vals, dtype=np.float64)]
+    out = np.empty(Xr.shape[0], dtype=object)
+    for b in range(Xr.shape[0]):
+        x = Xr[b]
+        sel = np.nonzero(x[rows] & x[cols])[0]
+        total = sum(vals[k] for k in sel) + sum(c[i] for i in np.nonzero(x)[0])
+        out[b] = Fraction(total, 1 << _SCALE_BITS)
+    return out
+
+
 def f_multilinear(A, cp, X) -> np.ndarray:
     """f(x) = 1/2 x^T A x + c'^T x for each row of X (Prop. 2.4)."""
     X = np.atleast_2d(np.asarray(X, dtype=np.float64))
@@ -133,3 +169,12 @@ class QuboProblem:
         absA = abs(self.A)
         rows = np.asarray(absA.sum(axis=1)).ravel()
         return float(np.sum(rows + np.abs(self.cp)) / self.s)
+
+
+class RealQuboProblem(QuboProblem):
+    """QuboProblem for float64 weights: the gradient as for integers (float64),
+    the objective exact (Fractions), so that the incumbent's comparisons of
+    Alg. 1's best-of-B are exact."""
+
+    def objective(self, Xr):
+        return objective_exact(self.q, Xr)

@@ -192,6 +192,79 @@ def test_real_weight_objective_fsum():
     assert math.isfinite(oq.objective_fsum(Q, None, x))
 
 
+def _real_instance(g, n, wide):
+    """Dense float64 Q and c; wide: magnitudes spread over 2^-60 .. 2^40 with
+    subnormal and cancelling entries."""
+    Q = g.standard_normal((n, n))
+    c = g.standard_normal(n)
+    if wide:
+        Q = Q * np.exp2(g.integers(-60, 41, size=(n, n)))
+        c = c * np.exp2(g.integers(-60, 41, size=n))
+        Q[0, 1], Q[1, 0] = 1e300, -1e300          # cancel when x_0 = x_1 = 1
+        Q[2, 2] = 5e-324                          # smallest subnormal
+        c[3] = -3.0 * 2.0 ** -1070
+    return Q, c
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_real_weight_objective_exact(wide):
+    """objective_exact against Fraction sums of every selected term (the
+    definition of Eq. 1 in exact rationals) and against math.fsum (a correctly
+    rounded library sum); dense and CSR storage of the same Q agree."""
+    import math
+    from fractions import Fraction
+    g = np.random.default_rng(5 + wide)
+    n = 9
+    Q, c = _real_instance(g, n, wide)
+    X = g.integers(0, 2, size=(12, n)).astype(np.uint8)
+    X[0] = 1
+    X[1] = 0
+    X[2, :4] = 1
+    qd = W.Qubo(n=n, Q=Q, c=c)
+    rp = np.arange(0, n * n + 1, n, dtype=np.int32)
+    col = np.tile(np.arange(n, dtype=np.int32), n)
+    qs = W.Qubo(n=n, row_ptr=rp, col_idx=col, vals=Q.ravel().copy(), c=c)
+    Fd = oq.objective_exact(qd, X)
+    Fs = oq.objective_exact(qs, X)
+    for b in range(X.shape[0]):
+        S = [i for i in range(n) if X[b, i]]
+        exact = sum((Fraction(Q[i, j]) for i in S for j in S), Fraction(0)) + \
+            sum((Fraction(c[i]) for i in S), Fraction(0))
+        assert Fd[b] == exact and Fs[b] == exact
+        assert float(Fd[b]) == oq.objective_fsum(Q, c, X[b]) == math.fsum(
+            [Q[i, j] for i in S for j in S] + [c[i] for i in S])
+    assert Fd[1] == 0
+
+
+def test_real_weight_objective_exact_integers():
+    """Integer-valued float64 weights give the int64 objective of the same
+    integers."""
+    g = np.random.default_rng(8)
+    n = 30
+    Qi = g.integers(-1000, 1001, size=(n, n)).astype(np.int32)
+    ci = g.integers(-5000, 5001, size=n).astype(np.int64)
+    X = g.integers(0, 2, size=(16, n)).astype(np.uint8)
+    Fi = oq.objective(W.Qubo(n=n, Q=Qi, c=ci), X)
+    Fr = oq.objective_exact(W.Qubo(n=n, Q=Qi.astype(np.float64), c=ci.astype(np.float64)), X)
+    assert [int(v) for v in Fr] == Fi.tolist()
+    assert all(v.denominator == 1 for v in Fr)
+
+
+def test_real_weight_incumbent_exact_comparison():
+    """Two restarts whose objectives round to the same float64 (1 + 2^-60 and
+    1): the incumbent of Alg. 1's best of B takes the exactly smaller one, not
+    the first index."""
+    from oracle.gda import Incumbent
+    Q = np.zeros((3, 3))
+    c = np.array([1.0, 2.0 ** -60, 0.0])
+    q = W.Qubo(n=3, Q=Q, c=c)
+    X = np.array([[1, 1, 0], [1, 0, 1]], dtype=np.uint8)
+    F = oq.objective_exact(q, X)
+    assert float(F[0]) == float(F[1]) == 1.0 and F[1] < F[0]
+    inc = Incumbent()
+    assert inc.offer(F, 1, X) and inc.b == 1 and inc.F == 1
+
+
 @pytest.mark.parametrize("even", [False, True])
 def test_incremental_difference_identity(even):
     """The identity behind the incremental evaluation: for x' = x + d (d = +-1 on
