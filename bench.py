@@ -337,10 +337,10 @@ def workload_mis(args, P):
     n, d, B = args.mis_n, args.mis_d, 10
     T = args.T if args.T != 2000 else 10000  # the dual needs ~5000 iterations to reach y <= 0 at d = 100
     q = W.mis_qubo(n, d, 0)
-    # the scale of the other dense-curvature workloads: with s = 1 the stiff
-    # all-ones direction (curvature lam d) makes the first steps clip every
-    # coordinate to 0 at d = 100, and the regular graph never breaks the symmetry
-    s = W.qubo_scale(q)
+    # with s = 1 the stiff all-ones direction (curvature lam d) makes the first
+    # steps clip every coordinate to 0 at d = 100, and the regular graph never
+    # breaks the symmetry; mis_scale documents the choice
+    s = W.mis_scale(q)
     p = W.gda_params("qubo", B=B, T=T, scale=s, alpha=0.02, beta=0.02, y0=5.0, tile=2,
                      graph_chunk=args.graph_chunk)
     ctx = P.qubo_gda_init(q, p, None)
@@ -413,7 +413,27 @@ def workload_kcut(args, P):
                              unit="GB/s", frac=(hbm + gath) / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                              compulsory_bytes=hbm, gathered_bytes=gath))
     ctx.destroy()
+    if not args.no_cpu:
+        out["cpu_baseline"] = _kcut_cpu_rate(G, p, n, k, args.cpu_seconds, T)
     return out
+
+
+def _kcut_cpu_rate(G, p, n, k, seconds, T):
+    """Max-k-Cut oracle restart-iterations/s on 10 restarts from the library's
+    own start (the same Philox draws, seed 1), about `seconds` of host work."""
+    from oracle import kcut as ok
+    from oracle.philox import x0_philox
+    Bs = 10
+    Z0 = x0_philox(int(p["seed"]), Bs, n * k).reshape(Bs, n, k)
+    t0 = time.perf_counter()
+    ok.run(G, Z0, p, 1)
+    t1 = time.perf_counter() - t0
+    Ts = int(min(T, max(1, round(seconds / max(t1, 1e-3)))))
+    t0 = time.perf_counter()
+    ok.run(G, Z0, p, Ts)
+    el = time.perf_counter() - t0
+    return dict(value=Bs * Ts / el, unit=UNIT, cores=_cores(), kind="oracle",
+                sample=f"FP64 oracle, {Bs} restarts x {Ts} iterations, same graph and start; {el:.1f} s")
 
 
 def workload_dual(args, P):

@@ -59,17 +59,35 @@ enum { PDBO_DUAL_VECTOR = 0, PDBO_DUAL_SCALAR = 1 };
 /* values of pdbo_params.tile for CSR instances */
 enum { PDBO_CSR_AUTO = 0, PDBO_CSR_RESIDENT = 1, PDBO_CSR_ROWS = 2 };
 enum { PDBO_FP32 = 0, PDBO_BF16 = 1, PDBO_FP8 = 2, PDBO_I8 = 3 };
+/* values of pdbo_qubo.wtype */
+enum { PDBO_W_INT32 = 0, PDBO_W_F64 = 1 };
 
 /*
  * QUBO instance (Eq. 1 with quadratic F): minimise F(x) = x^T Q x + c^T x over
  * x in {0,1}^n.  Q may be asymmetric and may have a diagonal; the library works
  * on the multilinear extension f(x) = 1/2 x^T A x + c'^T x with
  * A = offdiag(Q + Q^T), c' = c + diag(Q) (Prop. 2.4), which equals F on {0,1}^n.
- *   format == PDBO_DENSE: q points to n*n int32, row-major (Q_ij at q[i*n+j]).
- *   format == PDBO_CSR:   row_ptr[n+1], col_idx[nnz], q = values[nnz] (int32),
- *                         rows sorted by column, no duplicate (i,j) in a row.
- *   c: n int64 linear coefficients, or NULL for c = 0.
- * All pointers are host pointers.
+ *   format == PDBO_DENSE: Q is n*n, row-major (Q_ij at element i*n+j).
+ *   format == PDBO_CSR:   row_ptr[n+1], col_idx[nnz], values[nnz], rows sorted
+ *                         by column, no duplicate (i,j) in a row.
+ *   wtype == PDBO_W_INT32: q holds Q (int32) and c holds n int64 linear
+ *                         coefficients or is NULL for c = 0.
+ *   wtype == PDBO_W_F64:  real weights: qd holds Q (float64, finite) and cd
+ *                         holds c (float64) or is NULL; q and c are ignored.
+ *                         The canonical A and c' are formed exactly (in fixed
+ *                         point, not in float64), objectives are the exact
+ *                         real sums compared exactly and reported correctly
+ *                         rounded to float64 (pdbo_result.best_obj_f64, the
+ *                         _f64 entry points).  Such instances run on the
+ *                         row-parallel CSR path whatever their format (a dense
+ *                         Q is stored as the CSR of its nonzeros); tile must be
+ *                         0 or PDBO_CSR_ROWS.  ERANGE when the weights' binary
+ *                         exponents span more than the 192 bits the exact
+ *                         evaluation carries (from the highest bit of the
+ *                         largest |weight| to the lowest set bit of any
+ *                         weight, the one of the canonical sums included).
+ * A zero-initialised struct is an int32 instance (wtype 0).  All pointers are
+ * host pointers.
  */
 typedef struct {
   int32_t n;
@@ -79,6 +97,10 @@ typedef struct {
   const int32_t* col_idx;
   int64_t nnz;
   const int64_t* c;
+  int32_t wtype;
+  int32_t _pad;
+  const double* qd;
+  const double* cd;
 } pdbo_qubo;
 
 /*
@@ -178,13 +200,17 @@ typedef struct {
 /* Incumbent of a run: the lexicographic minimum of (F, t, b) over all
  * evaluated rounded iterates x_r = [x^t > 1/2], t >= 1. */
 typedef struct {
-  int64_t best_obj;       /* exact F of best_x (weighted unsat count for MaxSAT) */
+  int64_t best_obj;       /* exact F of best_x (weighted unsat count for MaxSAT);
+                             0 for float64 weights                                */
   int32_t best_restart;   /* b, or -1 when nothing has been evaluated yet        */
   int32_t _pad;
   int64_t best_iter;      /* iteration t (1-based) at which it was first reached */
   double time_to_best_s;  /* device clock, from the start of the first step      */
   int64_t steps_done;     /* iterations run so far                               */
   uint8_t* best_x;        /* caller-owned host buffer of n bytes, or NULL        */
+  double best_obj_f64;    /* F of best_x correctly rounded to float64 (integer
+                             weights: best_obj converted); +inf before the first
+                             evaluation                                           */
 } pdbo_result;
 
 /* ---- QUBO (dense MFMA path or CSR persistent path) ------------------------ */
@@ -228,8 +254,14 @@ PDBO_API pdbo_status qubo_gda_set_state(pdbo_ctx* ctx, const float* x, const flo
  * Synchronises. */
 PDBO_API pdbo_status qubo_gda_restart(pdbo_ctx* ctx, const double* x0);
 
-/* Exact objectives (host int64[B]) of the rounded iterate evaluated last. */
+/* Exact objectives (host int64[B]) of the rounded iterate evaluated last.
+ * EUNSUPPORTED for float64 weights (use qubo_gda_objectives_f64). */
 PDBO_API pdbo_status qubo_gda_objectives(pdbo_ctx* ctx, int64_t* F);
+
+/* The same objectives (Eq. 1) correctly rounded to float64 (host double[B]);
+ * for float64 weights the exact real sums, for integer weights the int64
+ * values converted.  QUBO contexts (dense, CSR, row-parallel). */
+PDBO_API pdbo_status qubo_gda_objectives_f64(pdbo_ctx* ctx, double* F);
 
 /* Gradient of f/s, (A x + c')/s, at the host (B, n) float32 points x, written
  * to the host (B, n) float32 array G, computed by the same GEMM (dense: same
@@ -237,8 +269,14 @@ PDBO_API pdbo_status qubo_gda_objectives(pdbo_ctx* ctx, int64_t* F);
 PDBO_API pdbo_status qubo_gda_grad(pdbo_ctx* ctx, const float* x, float* G);
 
 /* Exact objectives F (host int64[nb]) of nb host binary vectors xr (nb, n)
- * bytes in {0,1}, nb <= B, through the step's evaluation kernels. */
+ * bytes in {0,1}, nb <= B, through the step's evaluation kernels.
+ * EUNSUPPORTED for float64 weights (use qubo_gda_eval_f64). */
 PDBO_API pdbo_status qubo_gda_eval(pdbo_ctx* ctx, const uint8_t* xr, int32_t nb, int64_t* F);
+
+/* Objectives (Eq. 1) of nb host binary vectors xr (nb, n) bytes in {0,1},
+ * 1 <= nb <= B, correctly rounded to float64 (host double[nb]): for float64
+ * weights the exact real sum of the selected terms, rounded once. */
+PDBO_API pdbo_status qubo_gda_eval_f64(pdbo_ctx* ctx, const uint8_t* xr, int32_t nb, double* F);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the exact
@@ -271,8 +309,8 @@ PDBO_API pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* ctx, const uint8_t* xr, int
  * L is convex; tight at the minimiser).  value (or NULL) receives s L(x), the
  * Frank-Wolfe gap s * max_z d.(x - z) >= 0 and the rounding bound subtracted;
  * x_out (host float[n] or NULL) the point.  ybar = 0 takes the parameters'
- * y0.  Dense (single instance) and CSR contexts with the quadratic g, else
- * EUNSUPPORTED.  The run's own iterate and incumbent are left untouched.
+ * y0.  Dense (single instance) and CSR contexts with the quadratic g and
+ * integer weights, else EUNSUPPORTED.  The run's own iterate and incumbent are left untouched.
  * Synchronises. */
 PDBO_API pdbo_status qubo_dual_bound(pdbo_ctx* ctx, double ybar, int32_t iters, double* lower_bound,
                                      double* value, float* x_out);
@@ -355,6 +393,11 @@ PDBO_API pdbo_status maxsat_lagrangian_bwd(pdbo_ctx* ctx, const float* x, const 
  * Synchronises. */
 PDBO_API pdbo_status qubo_gda_trace(pdbo_ctx* ctx, int32_t cap, int64_t* t, int64_t* F, int32_t* b,
                                     double* sec, int32_t* len);
+
+/* qubo_gda_trace with the objectives correctly rounded to float64 (the only
+ * form for float64 weights, where qubo_gda_trace returns EUNSUPPORTED). */
+PDBO_API pdbo_status qubo_gda_trace_f64(pdbo_ctx* ctx, int32_t cap, int64_t* t, double* F,
+                                        int32_t* b, double* sec, int32_t* len);
 
 /* Kernel classes of pdbo_kernel_time:
  *   PDBO_K_STEP        dense GEMM with the Alg. 1 update fused (one per iteration)

@@ -27,7 +27,9 @@ from ._abi import (PDBO_BF16, PDBO_CSR, PDBO_DENSE, PDBO_FP8, PDBO_FP32, PDBO_G_
 __all__ = [
     "load", "PdboError", "Context", "qubo_gda_init", "qubo_gda_step", "qubo_gda_result",
     "qubo_gda_get_state", "qubo_gda_set_state", "qubo_gda_restart", "qubo_gda_objectives", "qubo_gda_grad",
-    "qubo_gda_eval", "qubo_gda_eval_noalloc", "qubo_dual_bound", "qubo_gda_trace", "qubo_gda_solve", "qubo_gda_batch_init", "qubo_gda_batch_result",
+    "qubo_gda_eval", "qubo_gda_eval_noalloc", "qubo_dual_bound", "qubo_gda_trace", "qubo_gda_solve",
+    "qubo_gda_objectives_f64", "qubo_gda_eval_f64", "qubo_gda_trace_f64",
+    "qubo_gda_batch_init", "qubo_gda_batch_result",
     "qubo_gda_batch_solve", "kcut_gda_init", "maxsat_gda_init", "maxsat_gda_step", "maxsat_gda_result",
     "maxsat_gda_solve", "maxsat_lagrangian_fwd", "maxsat_lagrangian_bwd", "MaxSATLagrangian",
     "PDBO_FP32", "PDBO_BF16", "PDBO_FP8", "PDBO_I8", "PDBO_K_STEP", "PDBO_K_EVAL", "PDBO_K_ARGMIN",
@@ -67,21 +69,35 @@ class _Keep:
         return b
 
 
+def _is_real(q) -> bool:
+    """Float weights (Q or vals, or c, of a floating dtype) take PDBO_W_F64."""
+    w = q.Q if getattr(q, "Q", None) is not None else q.vals
+    c = getattr(q, "c", None)
+    return np.asarray(w).dtype.kind == "f" or (c is not None and np.asarray(c).dtype.kind == "f")
+
+
 def _qubo_struct(q, keep: _Keep) -> _abi.pdbo_qubo:
     s = _abi.pdbo_qubo()
     s.n = int(q.n)
+    real = _is_real(q)
+    s.wtype = _abi.PDBO_W_F64 if real else _abi.PDBO_W_INT32
+    wt = np.float64 if real else np.int32
     if getattr(q, "Q", None) is not None:
         s.format = PDBO_DENSE
-        s.q = _ptr(keep.arr(q.Q, np.int32))
+        w = _ptr(keep.arr(q.Q, wt))
         s.nnz = 0
     else:
         s.format = PDBO_CSR
         s.row_ptr = _ptr(keep.arr(q.row_ptr, np.int32))
         s.col_idx = _ptr(keep.arr(q.col_idx, np.int32))
-        s.q = _ptr(keep.arr(q.vals, np.int32))
+        w = _ptr(keep.arr(q.vals, wt))
         s.nnz = int(len(q.col_idx))
     c = getattr(q, "c", None)
-    s.c = _ptr(keep.arr(c, np.int64)) if c is not None else None
+    cp = None if c is None else _ptr(keep.arr(c, np.float64 if real else np.int64))
+    if real:
+        s.qd, s.cd = w, cp
+    else:
+        s.q, s.c = w, cp
     return s
 
 
@@ -112,9 +128,9 @@ def _params_struct(p: dict, x0, keep: _Keep) -> _abi.pdbo_params:
 
 
 def _result_dict(r: _abi.pdbo_result, best_x) -> dict:
-    return dict(best_obj=int(r.best_obj), best_restart=int(r.best_restart),
-                best_iter=int(r.best_iter), time_to_best_s=float(r.time_to_best_s),
-                steps_done=int(r.steps_done), best_x=best_x)
+    return dict(best_obj=int(r.best_obj), best_obj_f64=float(r.best_obj_f64),
+                best_restart=int(r.best_restart), best_iter=int(r.best_iter),
+                time_to_best_s=float(r.time_to_best_s), steps_done=int(r.steps_done), best_x=best_x)
 
 
 class Context:
@@ -148,6 +164,15 @@ class Context:
 
     def objectives(self):
         return qubo_gda_objectives(self)
+
+    def objectives_f64(self):
+        return qubo_gda_objectives_f64(self)
+
+    def eval_f64(self, xr):
+        return qubo_gda_eval_f64(self, xr)
+
+    def trace_f64(self, cap=4096):
+        return qubo_gda_trace_f64(self, cap)
 
     def restart(self, x0):
         return qubo_gda_restart(self, x0)
@@ -240,6 +265,12 @@ def qubo_gda_objectives(ctx: Context) -> np.ndarray:
     return F
 
 
+def qubo_gda_objectives_f64(ctx: Context) -> np.ndarray:
+    F = np.zeros(ctx.B, dtype=np.float64)
+    check(load().qubo_gda_objectives_f64(ctx.h, _ptr(F)), ctx.h)
+    return F
+
+
 def qubo_gda_grad(ctx: Context, x) -> np.ndarray:
     xa = np.ascontiguousarray(x, dtype=np.float32)
     G = np.zeros(_xshape(ctx), dtype=np.float32)
@@ -252,6 +283,14 @@ def qubo_gda_eval(ctx: Context, xr) -> np.ndarray:
     xa = xa.reshape(-1, ctx.n)
     F = np.zeros(xa.shape[0], dtype=np.int64)
     check(load().qubo_gda_eval(ctx.h, _ptr(xa), int(xa.shape[0]), _ptr(F)), ctx.h)
+    return F
+
+
+def qubo_gda_eval_f64(ctx: Context, xr) -> np.ndarray:
+    xa = np.ascontiguousarray(xr, dtype=np.uint8)
+    xa = xa.reshape(-1, ctx.n)
+    F = np.zeros(xa.shape[0], dtype=np.float64)
+    check(load().qubo_gda_eval_f64(ctx.h, _ptr(xa), int(xa.shape[0]), _ptr(F)), ctx.h)
     return F
 
 
@@ -287,6 +326,18 @@ def qubo_gda_trace(ctx: Context, cap: int = 4096) -> dict:
     ln = ctypes.c_int32()
     check(load().qubo_gda_trace(ctx.h, int(cap), _ptr(t), _ptr(F), _ptr(b), _ptr(sec),
                                 ctypes.byref(ln)), ctx.h)
+    k = ln.value
+    return dict(t=t[:k], F=F[:k], b=b[:k], sec=sec[:k])
+
+
+def qubo_gda_trace_f64(ctx: Context, cap: int = 4096) -> dict:
+    t = np.zeros(cap, dtype=np.int64)
+    F = np.zeros(cap, dtype=np.float64)
+    b = np.zeros(cap, dtype=np.int32)
+    sec = np.zeros(cap, dtype=np.float64)
+    ln = ctypes.c_int32()
+    check(load().qubo_gda_trace_f64(ctx.h, int(cap), _ptr(t), _ptr(F), _ptr(b), _ptr(sec),
+                                    ctypes.byref(ln)), ctx.h)
     k = ln.value
     return dict(t=t[:k], F=F[:k], b=b[:k], sec=sec[:k])
 

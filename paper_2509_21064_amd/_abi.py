@@ -17,12 +17,14 @@ PDBO_DENSE, PDBO_CSR = 0, 1
 PDBO_G_QUAD, PDBO_G_ENTROPY, PDBO_G_POLY = 0, 1, 2
 PDBO_DUAL_VECTOR, PDBO_DUAL_SCALAR = 0, 1
 PDBO_FP32, PDBO_BF16, PDBO_FP8, PDBO_I8 = 0, 1, 2, 3
+PDBO_W_INT32, PDBO_W_F64 = 0, 1
 PDBO_K_STEP, PDBO_K_EVAL, PDBO_K_ARGMIN, PDBO_K_PERSISTENT, PDBO_K_INCR = 0, 1, 2, 3, 4
 
 
 class pdbo_qubo(ctypes.Structure):
     _fields_ = [("n", c_int32), ("format", c_int32), ("q", c_void_p), ("row_ptr", c_void_p),
-                ("col_idx", c_void_p), ("nnz", c_int64), ("c", c_void_p)]
+                ("col_idx", c_void_p), ("nnz", c_int64), ("c", c_void_p), ("wtype", c_int32),
+                ("_pad", c_int32), ("qd", c_void_p), ("cd", c_void_p)]
 
 
 class pdbo_maxsat(ctypes.Structure):
@@ -44,7 +46,7 @@ class pdbo_params(ctypes.Structure):
 class pdbo_result(ctypes.Structure):
     _fields_ = [("best_obj", c_int64), ("best_restart", c_int32), ("_pad", c_int32),
                 ("best_iter", c_int64), ("time_to_best_s", c_double), ("steps_done", c_int64),
-                ("best_x", c_void_p)]
+                ("best_x", c_void_p), ("best_obj_f64", c_double)]
 
 
 _ctx = c_void_p
@@ -59,8 +61,10 @@ SIGNATURES = {
     "qubo_gda_set_state": (_st, [_ctx, c_void_p, c_void_p, c_int64]),
     "qubo_gda_restart": (_st, [_ctx, c_void_p]),
     "qubo_gda_objectives": (_st, [_ctx, c_void_p]),
+    "qubo_gda_objectives_f64": (_st, [_ctx, c_void_p]),
     "qubo_gda_grad": (_st, [_ctx, c_void_p, c_void_p]),
     "qubo_gda_eval": (_st, [_ctx, c_void_p, c_int32, c_void_p]),
+    "qubo_gda_eval_f64": (_st, [_ctx, c_void_p, c_int32, c_void_p]),
     "qubo_gda_eval_noalloc": (_st, [_ctx, c_void_p, c_int32, c_void_p, c_void_p]),
     "qubo_dual_bound": (_st, [_ctx, c_double, c_int32, POINTER(c_double), c_void_p, c_void_p]),
     "qubo_gda_solve": (_st, [POINTER(pdbo_qubo), POINTER(pdbo_params), c_int32, c_void_p,
@@ -81,6 +85,8 @@ SIGNATURES = {
                                     c_void_p, c_void_p]),
     "qubo_gda_trace": (_st, [_ctx, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                              POINTER(c_int32)]),
+    "qubo_gda_trace_f64": (_st, [_ctx, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 POINTER(c_int32)]),
     "pdbo_timing": (_st, [_ctx, c_int32]),
     "pdbo_timing_classes": (_st, [_ctx, c_uint32]),
     "pdbo_timing_stride": (_st, [_ctx, c_int32]),

@@ -43,6 +43,7 @@ UNITS = [
     ("spmm.hip", "spmm.o", []),
     ("cert.hip", "cert.o", []),
     ("kcut.hip", "kcut.o", []),
+    ("realw.hip", "realw.o", []),
     ("api.hip", "api.o", []),
 ]
 SOURCES = sorted({u[0] for u in UNITS})

@@ -260,15 +260,26 @@ pdbo_status check_params(const pdbo_params* p, int n, bool x0_required = true) {
 pdbo_status check_qubo(const pdbo_qubo* q) {
   if (!q) return fail(nullptr, PDBO_EINVAL, "problem is NULL");
   if (q->n < 1 || q->n > 65536) return fail(nullptr, PDBO_EINVAL, "n must be in [1, 65536]");
+  if (q->wtype != PDBO_W_INT32 && q->wtype != PDBO_W_F64)
+    return fail(nullptr, PDBO_EINVAL, "unknown wtype");
+  const bool real = q->wtype == PDBO_W_F64;
   const int n = q->n;
+  // weight checks: int32 entries below 2^30, float64 entries finite
+  auto bad_q = [&](size_t k) -> pdbo_status {
+    if (real) {
+      if (!std::isfinite(q->qd[k])) return fail(nullptr, PDBO_EINVAL, "Q_ij must be finite");
+    } else if (q->q[k] >= (1 << 30) || q->q[k] <= -(1 << 30)) {
+      return fail(nullptr, PDBO_ERANGE, "|Q_ij| must be below 2^30");
+    }
+    return PDBO_OK;
+  };
+  const bool have_q = real ? q->qd != nullptr : q->q != nullptr;
   if (q->format == PDBO_DENSE) {
-    if (!q->q) return fail(nullptr, PDBO_EINVAL, "dense Q is NULL");
+    if (!have_q) return fail(nullptr, PDBO_EINVAL, "dense Q is NULL");
     const size_t tot = (size_t)n * n;
-    for (size_t i = 0; i < tot; ++i)
-      if (q->q[i] >= (1 << 30) || q->q[i] <= -(1 << 30))
-        return fail(nullptr, PDBO_ERANGE, "|Q_ij| must be below 2^30");
+    for (size_t i = 0; i < tot; ++i) STCHK(bad_q(i));
   } else if (q->format == PDBO_CSR) {
-    if (!q->row_ptr || (q->nnz > 0 && (!q->col_idx || !q->q)))
+    if (!q->row_ptr || (q->nnz > 0 && (!q->col_idx || !have_q)))
       return fail(nullptr, PDBO_EINVAL, "CSR arrays are NULL");
     if (q->nnz < 0 || q->nnz > (int64_t)INT_MAX) return fail(nullptr, PDBO_EINVAL, "bad nnz");
     if (q->row_ptr[0] != 0 || (int64_t)q->row_ptr[n] != q->nnz)
@@ -281,17 +292,21 @@ pdbo_status check_qubo(const pdbo_qubo* q) {
         if (j < 0 || j >= n) return fail(nullptr, PDBO_EINVAL, "column index out of range");
         if (p > q->row_ptr[i] && j <= q->col_idx[p - 1])
           return fail(nullptr, PDBO_EINVAL, "columns of a row must be strictly increasing");
-        if (q->q[p] >= (1 << 30) || q->q[p] <= -(1 << 30))
-          return fail(nullptr, PDBO_ERANGE, "|Q_ij| must be below 2^30");
+        STCHK(bad_q((size_t)p));
       }
     }
   } else {
     return fail(nullptr, PDBO_EINVAL, "unknown format");
   }
-  if (q->c)
+  if (real) {
+    if (q->cd)
+      for (int i = 0; i < n; ++i)
+        if (!std::isfinite(q->cd[i])) return fail(nullptr, PDBO_EINVAL, "c_i must be finite");
+  } else if (q->c) {
     for (int i = 0; i < n; ++i)
       if (q->c[i] >= (int64_t(1) << 40) || q->c[i] <= -(int64_t(1) << 40))
         return fail(nullptr, PDBO_ERANGE, "|c_i| must be below 2^40");
+  }
   return PDBO_OK;
 }
 
@@ -436,6 +451,173 @@ pdbo_status canon_csr(const pdbo_qubo* q, CsrCanon& C) {
     C.rp[i + 1] += C.rp[i];
     if (rs[i] >= (int64_t(1) << 31)) return fail(nullptr, PDBO_ERANGE, "a row of |Ahat| sums to 2^31 or more");
     C.rowabs = std::max(C.rowabs, rs[i]);
+  }
+  return PDBO_OK;
+}
+
+// Float64 weights: the canonical A = offdiag(Q + Q^T) and c' = c + diag(Q)
+// (Prop. 2.4) in exact fixed point.  Every finite nonzero weight is m 2^e with
+// m odd; with elo the least such e over all weights, a weight is the integer
+// m 2^(e - elo) in units of 2^elo, written as ndig signed base-2^24 digits
+// (the digits of |m| 2^(e - elo), each carrying the weight's sign).  The two
+// weights that make up a canonical entry are added digit by digit, without
+// carries, so every digit stays below 2^25 in magnitude.  The gradient uses
+// A/s and c'/s rounded to float32.
+struct RealCanon {
+  int n = 0, ndig = 0, elo = 0;
+  std::vector<int32_t> rp, col;
+  std::vector<float> valf;     // A/s
+  std::vector<int32_t> Adig;   // [ndig][nnz]
+  std::vector<int32_t> Cdig;   // [ndig][n]
+  std::vector<float> cps;      // c'/s
+};
+
+struct OddPow {  // v = m 2^e, m odd (v != 0)
+  int64_t m;
+  int e;
+};
+
+OddPow odd_pow(double v) {
+  int E = 0;
+  const double f = std::frexp(v, &E);  // v = f 2^E, 1/2 <= |f| < 1
+  OddPow r{(int64_t)std::ldexp(f, 53), E - 53};
+  while ((r.m & 1) == 0) {
+    r.m /= 2;
+    ++r.e;
+  }
+  return r;
+}
+
+int bit_length(uint64_t a) { return a ? 64 - __builtin_clzll(a) : 0; }
+
+// dst[d * stride] += digit d of m 2^sh (digits of |m| 2^sh, sign of m)
+void add_digits(int32_t* dst, size_t stride, int ndig, int64_t m, int sh) {
+  const uint64_t a = (uint64_t)(m < 0 ? -m : m);
+  const int32_t sg = m < 0 ? -1 : 1;
+  for (int d = 0; d < ndig; ++d) {
+    const int lo = 24 * d - sh;  // bit of |m| that lands on bit 0 of digit d
+    uint64_t chunk;
+    if (lo >= 0)
+      chunk = lo >= 64 ? 0 : (a >> lo) & 0xFFFFFFu;
+    else
+      chunk = -lo >= 24 ? 0 : (a << -lo) & 0xFFFFFFu;
+    dst[(size_t)d * stride] += sg * (int32_t)chunk;
+  }
+}
+
+pdbo_status canon_real(const pdbo_qubo* q, double scale, RealCanon& R) {
+  const int n = q->n;
+  R.n = n;
+  const bool dense = q->format == PDBO_DENSE;
+  const size_t nq = dense ? (size_t)n * n : (size_t)q->nnz;
+  // the exponent range over all weights
+  int elo = INT_MAX, hi = INT_MIN;
+  auto scan = [&](double v) {
+    if (v == 0.0) return;
+    const OddPow o = odd_pow(v);
+    elo = std::min(elo, o.e);
+    hi = std::max(hi, o.e + bit_length((uint64_t)(o.m < 0 ? -o.m : o.m)) - 1);
+  };
+  for (size_t k = 0; k < nq; ++k) scan(q->qd[k]);
+  if (q->cd)
+    for (int i = 0; i < n; ++i) scan(q->cd[i]);
+  if (elo == INT_MAX) elo = hi = 0;  // all weights zero
+  R.elo = elo;
+  R.ndig = (hi - elo) / 24 + 1;
+  if (R.ndig > kMaxDigits)
+    return fail(nullptr, PDBO_ERANGE, "the weights' binary exponents span more than 192 bits");
+  const int nd = R.ndig;
+  // (i, j, weight index) contributions to canonical entries, i != j
+  struct E {
+    int32_t i, j;
+    int64_t k;
+  };
+  std::vector<E> e;
+  std::vector<double> cpd(n, 0.0);
+  std::vector<int32_t> Cd;
+  try {
+    R.Cdig.assign((size_t)nd * n, 0);
+    if (dense) {
+      e.reserve(nq);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          if (i == j) continue;
+          if (q->qd[(size_t)i * n + j] != 0.0) e.push_back({i, j, (int64_t)i * n + j});
+          if (q->qd[(size_t)j * n + i] != 0.0) e.push_back({i, j, (int64_t)j * n + i});
+        }
+    } else {
+      e.reserve(2 * nq);
+      for (int i = 0; i < n; ++i)
+        for (int p = q->row_ptr[i]; p < q->row_ptr[i + 1]; ++p) {
+          const int j = q->col_idx[p];
+          if (i == j || q->qd[p] == 0.0) continue;
+          e.push_back({i, j, p});
+          e.push_back({j, i, p});
+        }
+      std::stable_sort(e.begin(), e.end(),
+                       [](const E& a, const E& b) { return a.i != b.i ? a.i < b.i : a.j < b.j; });
+    }
+  } catch (...) {
+    return fail(nullptr, PDBO_ENOMEM, "host allocation failed");
+  }
+  // linear part: c' = c + diag(Q)
+  auto add_lin = [&](int i, double v) {
+    if (v == 0.0) return;
+    const OddPow o = odd_pow(v);
+    add_digits(R.Cdig.data() + i, (size_t)n, nd, o.m, o.e - elo);
+    cpd[i] += v;
+  };
+  for (int i = 0; i < n; ++i) {
+    if (q->cd) add_lin(i, q->cd[i]);
+    if (dense)
+      add_lin(i, q->qd[(size_t)i * n + i]);
+    else
+      for (int p = q->row_ptr[i]; p < q->row_ptr[i + 1]; ++p)
+        if (q->col_idx[p] == i) add_lin(i, q->qd[p]);
+  }
+  // canonical entries: runs of equal (i, j); an exact cancellation (all digits
+  // zero) leaves no entry
+  std::vector<int32_t> dig;  // [nnz][nd] while building
+  R.rp.assign(n + 1, 0);
+  std::vector<int32_t> cur(nd);
+  try {
+    for (size_t a = 0; a < e.size();) {
+      size_t b = a;
+      double v = 0.0;
+      std::fill(cur.begin(), cur.end(), 0);
+      while (b < e.size() && e[b].i == e[a].i && e[b].j == e[a].j) {
+        const double w = q->qd[e[b].k];
+        const OddPow o = odd_pow(w);
+        add_digits(cur.data(), 1, nd, o.m, o.e - elo);
+        v += w;
+        ++b;
+      }
+      bool any = false;
+      for (int d = 0; d < nd; ++d) any = any || cur[d] != 0;
+      if (any) {
+        R.rp[e[a].i + 1]++;
+        R.col.push_back(e[a].j);
+        R.valf.push_back((float)(v / scale));
+        dig.insert(dig.end(), cur.begin(), cur.end());
+      }
+      a = b;
+    }
+    const size_t nnz = R.col.size();
+    R.Adig.resize((size_t)nd * nnz);
+    for (size_t k = 0; k < nnz; ++k)
+      for (int d = 0; d < nd; ++d) R.Adig[(size_t)d * nnz + k] = dig[k * nd + d];
+  } catch (...) {
+    return fail(nullptr, PDBO_ENOMEM, "host allocation failed");
+  }
+  for (int i = 0; i < n; ++i) R.rp[i + 1] += R.rp[i];
+  R.cps.resize(n);
+  // the float32 gradient needs every row of |A/s| and |c'/s| within range
+  for (int i = 0; i < n; ++i) {
+    R.cps[i] = (float)(cpd[i] / scale);
+    double rs = std::fabs((double)R.cps[i]);
+    for (int p = R.rp[i]; p < R.rp[i + 1]; ++p) rs += std::fabs((double)R.valf[p]);
+    if (!(rs <= 3.0e38))
+      return fail(nullptr, PDBO_ERANGE, "a row of |A/s| exceeds the float32 range of the gradient");
   }
   return PDBO_OK;
 }
@@ -1160,6 +1342,8 @@ double clock_rate_hz() {
   return (double)khz * 1e3;
 }
 
+bool is_real(const pdbo_ctx* c) { return c->kind == 3 && c->spmm.ndig > 0; }
+
 pdbo_status fill_result(pdbo_ctx* c, const Incumbent* inc_d, const uint8_t* best_x_d, int n,
                         pdbo_result* r) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1170,12 +1354,19 @@ pdbo_status fill_result(pdbo_ctx* c, const Incumbent* inc_d, const uint8_t* best
   r->steps_done = c->t_host;
   if (inc.F == kI64Max) {
     r->best_obj = 0;
+    r->best_obj_f64 = HUGE_VAL;
     r->best_restart = -1;
     r->best_iter = -1;
     r->time_to_best_s = 0.0;
     return PDBO_OK;
   }
-  r->best_obj = inc.F;
+  if (is_real(c)) {  // the incumbent holds the bits of the rounded value
+    std::memcpy(&r->best_obj_f64, &inc.F, sizeof(double));
+    r->best_obj = 0;
+  } else {
+    r->best_obj = inc.F;
+    r->best_obj_f64 = (double)inc.F;
+  }
   r->best_restart = (int32_t)inc.b;
   r->best_iter = inc.t;
   r->time_to_best_s = (inc.ts >= ts0 && ts0) ? (double)(inc.ts - ts0) / clock_rate_hz() : 0.0;
@@ -1290,6 +1481,8 @@ static pdbo_status dense_init(int k, const pdbo_qubo* probs, const pdbo_params* 
   for (int i = 0; i < k; ++i) {
     STCHK(check_qubo(&probs[i]));
     STCHK(check_params(&pars[i], probs[i].n));
+    if (probs[i].wtype != PDBO_W_INT32)
+      return fail(nullptr, PDBO_EUNSUPPORTED, "batches and dense contexts take int32 weights");
     if (pars[i].B != pars[0].B || pars[i].precision != pars[0].precision ||
         pars[i].g_kind != pars[0].g_kind || pars[i].eval_every != pars[0].eval_every ||
         pars[i].dual_kind != pars[0].dual_kind)
@@ -1352,7 +1545,8 @@ static pdbo_status persistent_supported(const pdbo_params* p) {
   return PDBO_OK;
 }
 
-static pdbo_status spmm_init(const CsrCanon& C, const pdbo_params* p, void* stream, pdbo_ctx** out);
+static pdbo_status spmm_init(const CsrCanon* C, const RealCanon* R, const pdbo_params* p,
+                             void* stream, pdbo_ctx** out);
 
 static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stream, pdbo_ctx** out) {
   if (p->eval_every != 1) return fail(nullptr, PDBO_EUNSUPPORTED, "the CSR path evaluates every iteration");
@@ -1367,7 +1561,7 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
   int path = p->tile;
   if (path == PDBO_CSR_AUTO)
     path = (fits && p->B >= kResidentMinB && persistent_ok(p)) ? PDBO_CSR_RESIDENT : PDBO_CSR_ROWS;
-  if (path == PDBO_CSR_ROWS) return spmm_init(C, p, stream, out);
+  if (path == PDBO_CSR_ROWS) return spmm_init(&C, nullptr, p, stream, out);
   STCHK(persistent_supported(p));
   if (!fits)
     return fail(nullptr, PDBO_EUNSUPPORTED, "instance too large for the restart-resident CSR kernel");
@@ -1464,24 +1658,29 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
 }
 
 // Row-parallel CSR path (spmm.hip): node-major iterates, one launch per
-// iteration over all rows plus the best of B.
-static pdbo_status spmm_init(const CsrCanon& C, const pdbo_params* p, void* stream, pdbo_ctx** out) {
+// iteration over all rows plus the best of B.  C: integer weights; R: float64
+// weights (realw.hip).
+static pdbo_status spmm_init(const CsrCanon* C, const RealCanon* R, const pdbo_params* p,
+                             void* stream, pdbo_ctx** out) {
   if (p->dual_kind != PDBO_DUAL_VECTOR)
     return fail(nullptr, PDBO_EUNSUPPORTED, "the scalar dual is built for the dense path only");
-  const int n = C.n, B = p->B;
+  const int n = C ? C->n : R->n, B = p->B;
   pdbo_ctx* c = new pdbo_ctx();
   c->kind = 3;
   c->n_of.push_back(n);
   pdbo_status st = begin_ctx(c, stream, p);
   auto run = [&]() -> pdbo_status {
-    const int64_t nnz = (int64_t)C.col.size();
+    const std::vector<int32_t>& hrp = C ? C->rp : R->rp;
+    const std::vector<int32_t>& hcol = C ? C->col : R->col;
+    const int64_t nnz = (int64_t)hcol.size();
     SpmmDev& d = c->spmm;
     std::memset(&d, 0, sizeof(d));
     d.n = n;
     d.B = B;
-    d.kappa = C.kappa;
+    d.nnz = nnz;
+    d.kappa = C ? C->kappa : 1;
     d.trace_cap = kTraceCap;
-    d.kos = (float)((double)C.kappa / p->scale);
+    d.kos = C ? (float)((double)C->kappa / p->scale) : 1.f;
     d.gp = make_gp(p);
     d.W = std::min(B, 64);
     d.G = 64 / d.W;
@@ -1490,33 +1689,59 @@ static pdbo_status spmm_init(const CsrCanon& C, const pdbo_params* p, void* stre
     const int nrb = (n + rows_per_wg - 1) / rows_per_wg;
     const int gpw = std::max(1, std::min(nrb, std::max(1, 2048 / d.nslices)));
     d.grid = gpw * d.nslices;
-    int32_t *rp = nullptr, *col = nullptr, *val = nullptr;
+    int32_t *rp = nullptr, *col = nullptr;
     float* cps = nullptr;
-    int64_t* cp = nullptr;
     STCHK(dalloc(c, &rp, n + 1));
     STCHK(dalloc(c, &col, nnz));
-    STCHK(dalloc(c, &val, nnz));
     STCHK(dalloc(c, &cps, n));
-    STCHK(dalloc(c, &cp, n));
-    std::vector<float> hcps(n);
-    for (int i = 0; i < n; ++i) hcps[i] = (float)((double)C.cp[i] / p->scale);
-    HIPCHK(c, hipMemcpyAsync(rp, C.rp.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream));
-    if (nnz > 0) {
-      HIPCHK(c, hipMemcpyAsync(col, C.col.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
-      HIPCHK(c, hipMemcpyAsync(val, C.val.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
-    }
-    HIPCHK(c, hipMemcpyAsync(cps, hcps.data(), n * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(cp, C.cp.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(rp, hrp.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream));
+    if (nnz > 0)
+      HIPCHK(c, hipMemcpyAsync(col, hcol.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
     d.row_ptr = rp;
     d.col = col;
-    d.val = val;
     d.cps = cps;
-    d.cp = cp;
+    std::vector<float> hcps(n);
+    if (C) {
+      int32_t* val = nullptr;
+      int64_t* cp = nullptr;
+      STCHK(dalloc(c, &val, nnz));
+      STCHK(dalloc(c, &cp, n));
+      for (int i = 0; i < n; ++i) hcps[i] = (float)((double)C->cp[i] / p->scale);
+      if (nnz > 0)
+        HIPCHK(c, hipMemcpyAsync(val, C->val.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(cp, C->cp.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+      d.val = val;
+      d.cp = cp;
+    } else {
+      float* valf = nullptr;
+      int32_t *Adig = nullptr, *Cdig = nullptr;
+      d.ndig = R->ndig;
+      d.elo = R->elo;
+      STCHK(dalloc(c, &valf, nnz));
+      STCHK(dalloc(c, &Adig, (size_t)R->ndig * nnz));
+      STCHK(dalloc(c, &Cdig, (size_t)R->ndig * n));
+      hcps = R->cps;
+      if (nnz > 0) {
+        HIPCHK(c, hipMemcpyAsync(valf, R->valf.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(Adig, R->Adig.data(), (size_t)R->ndig * nnz * 4,
+                                 hipMemcpyHostToDevice, c->stream));
+      }
+      HIPCHK(c, hipMemcpyAsync(Cdig, R->Cdig.data(), (size_t)R->ndig * n * 4, hipMemcpyHostToDevice,
+                               c->stream));
+      d.valf = valf;
+      d.Adig = Adig;
+      d.Cdig = Cdig;
+      STCHK(dalloc(c, &d.incw, 4));
+      STCHK(dalloc(c, &d.Fd, B));
+      const uint64_t top[4] = {~0ull, ~0ull, ~0ull, ~0ull >> 1};
+      HIPCHK(c, hipMemcpyAsync(d.incw, top, sizeof(top), hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(cps, hcps.data(), n * 4, hipMemcpyHostToDevice, c->stream));
     const size_t sz = (size_t)n * B;
     STCHK(dalloc(c, &d.X[0], sz));
     STCHK(dalloc(c, &d.X[1], sz));
     STCHK(dalloc(c, &d.Y, sz));
-    STCHK(dalloc(c, &d.part, (size_t)d.grid * 2 * d.W));
+    STCHK(dalloc(c, &d.part, (size_t)d.grid * 2 * d.W * std::max(1, d.ndig)));
     STCHK(dalloc(c, &d.Flast, B));
     STCHK(dalloc(c, &d.inc, 1));
     STCHK(dalloc(c, &d.best_x, n));
@@ -1526,21 +1751,23 @@ static pdbo_status spmm_init(const CsrCanon& C, const pdbo_params* p, void* stre
     d.ts0 = c->ts0_d;
     Incumbent init{kI64Max, -1, -1, 0};
     HIPCHK(c, hipMemcpyAsync(d.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
-    // qubo_gda_eval of given vectors goes through the restart-major CSR kernel
-    CsrDev& e = c->csr;
-    std::memset(&e, 0, sizeof(e));
-    e.row_ptr = rp;
-    e.col = col;
-    e.val = val;
-    e.cps = cps;
-    e.cp = cp;
-    e.nnz = nnz;
-    e.n = n;
-    e.ld = roundup(n, kLdAlign);
-    e.B = B;
-    e.kappa = C.kappa;
-    e.kos = d.kos;
-    e.gp = d.gp;
+    if (C) {
+      // qubo_gda_eval of given vectors goes through the restart-major CSR kernel
+      CsrDev& e = c->csr;
+      std::memset(&e, 0, sizeof(e));
+      e.row_ptr = rp;
+      e.col = col;
+      e.val = d.val;
+      e.cps = cps;
+      e.cp = d.cp;
+      e.nnz = nnz;
+      e.n = n;
+      e.ld = roundup(n, kLdAlign);
+      e.B = B;
+      e.kappa = C->kappa;
+      e.kos = d.kos;
+      e.gp = d.gp;
+    }
     TempDev t;
     STCHK(upload_x0(c, t, p->x0, (size_t)B * n));
     HIPCHK(c, launch_spmm_init((const double*)t.p, d, (float)p->y0, p->seed, c->stream));
@@ -1556,6 +1783,18 @@ static pdbo_status spmm_init(const CsrCanon& C, const pdbo_params* p, void* stre
   }
   *out = c;
   return PDBO_OK;
+}
+
+// Float64 weights: exact fixed-point canonical form, row-parallel CSR path.
+static pdbo_status real_init(const pdbo_qubo* q, const pdbo_params* p, void* stream,
+                             pdbo_ctx** out) {
+  if (p->eval_every != 1) return fail(nullptr, PDBO_EUNSUPPORTED, "the CSR path evaluates every iteration");
+  if (p->tile != PDBO_CSR_AUTO && p->tile != PDBO_CSR_ROWS)
+    return fail(nullptr, PDBO_EUNSUPPORTED, "float64 weights run on the row-parallel CSR path "
+                                            "(tile 0 or 2)");
+  RealCanon R;
+  STCHK(canon_real(q, p->scale, R));
+  return spmm_init(nullptr, &R, p, stream, out);
 }
 
 pdbo_status spmm_one_step(pdbo_ctx* c) {
@@ -1660,6 +1899,7 @@ pdbo_status qubo_gda_init(const pdbo_qubo* prob, const pdbo_params* par, void* s
   *out = nullptr;
   STCHK(check_qubo(prob));
   STCHK(check_params(par, prob->n));
+  if (prob->wtype == PDBO_W_F64) return real_init(prob, par, stream, out);
   if (prob->format == PDBO_CSR) return csr_init(prob, par, stream, out);
   return dense_init(1, prob, par, 1, stream, out);
 }
@@ -1953,6 +2193,10 @@ pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
     HIPCHK(c, hipMemcpyAsync(d.t_dev, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(d.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_fill_i32(d.trace_len, 0, 1, c->stream));
+    if (d.incw) {
+      const uint64_t top[4] = {~0ull, ~0ull, ~0ull, ~0ull >> 1};
+      HIPCHK(c, hipMemcpyAsync(d.incw, top, sizeof(top), hipMemcpyHostToDevice, c->stream));
+    }
   } else {
     float* X = c->kind == 1 ? c->csr.X : c->sat.X;
     float* Y = c->kind == 1 ? c->csr.Y : c->sat.Y;
@@ -1974,9 +2218,24 @@ pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
   return PDBO_OK;
 }
 
+pdbo_status qubo_gda_objectives_f64(pdbo_ctx* c, double* F) {
+  if (!c || !F) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (c->kind == 2 || c->kind == 4) return fail(c, PDBO_ESTATE, "not a QUBO context");
+  if (!is_real(c)) {
+    std::vector<int64_t> Fi(c->B);
+    STCHK(qubo_gda_objectives(c, Fi.data()));
+    for (int b = 0; b < c->B; ++b) F[b] = (double)Fi[b];
+    return PDBO_OK;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(F, c->spmm.Fd, c->B * sizeof(double), hipMemcpyDeviceToHost));
+  return PDBO_OK;
+}
+
 pdbo_status qubo_gda_objectives(pdbo_ctx* c, int64_t* F) {
   if (!c || !F) return fail(c, PDBO_EINVAL, "NULL argument");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (is_real(c)) return fail(c, PDBO_EUNSUPPORTED, "float64 weights: use qubo_gda_objectives_f64");
   const int64_t* src = c->kind == 0   ? c->insts_h[0].Fall
                        : c->kind == 1 ? c->csr.Flast
                        : c->kind == 3 ? c->spmm.Flast
@@ -1992,8 +2251,10 @@ static pdbo_status ensure_scratch(pdbo_ctx* c) {
   int ld = 0;
   if (c->kind == 0)
     ld = c->insts_h[0].ld;
-  else if (c->kind == 1 || c->kind == 3)
+  else if (c->kind == 1)
     ld = c->csr.ld;
+  else if (c->kind == 3)
+    ld = roundup(c->spmm.n, kLdAlign);
   else if (c->kind == 4)
     ld = roundup(c->kcut.n, kLdAlign);
   else
@@ -2080,9 +2341,39 @@ pdbo_status qubo_gda_grad(pdbo_ctx* c, const float* x, float* G) {
   return PDBO_OK;
 }
 
+pdbo_status qubo_gda_eval_f64(pdbo_ctx* c, const uint8_t* xr, int32_t nb, double* F) {
+  if (!c || !xr || !F) return fail(c, PDBO_EINVAL, "NULL argument");
+  if (c->kind == 2 || c->kind == 4) return fail(c, PDBO_ESTATE, "not a QUBO context");
+  if (!is_real(c)) {
+    if (nb < 1 || nb > c->B) return fail(c, PDBO_EINVAL, "nb must be in [1, B]");
+    std::vector<int64_t> Fi(nb);
+    STCHK(qubo_gda_eval(c, xr, nb, Fi.data()));
+    for (int b = 0; b < nb; ++b) F[b] = (double)Fi[b];
+    return PDBO_OK;
+  }
+  if (nb < 1 || nb > c->B) return fail(c, PDBO_EINVAL, "nb must be in [1, B]");
+  const int n = c->n_of[0];
+  for (size_t i = 0; i < (size_t)nb * n; ++i)
+    if (xr[i] > 1) return fail(c, PDBO_EINVAL, "xr must be 0/1 bytes");
+  STCHK(ensure_scratch(c));
+  // X[parity ^ 1] holds the previous iterate, which the next step overwrites
+  // before reading: the vectors are evaluated there
+  SpmmDev& d = c->spmm;
+  const int q = c->parity ^ 1;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->xr_scratch, xr, (size_t)nb * n, hipMemcpyHostToDevice));
+  HIPCHK(c, launch_real_load_x((const uint8_t*)c->xr_scratch, nb, d, q, c->stream));
+  HIPCHK(c, launch_spmm_real(d, 1, q, nullptr, c->stream));
+  HIPCHK(c, launch_spmm_real_best(d, q, 0, (double*)c->f_scratch, nb, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(F, c->f_scratch, nb * sizeof(double), hipMemcpyDeviceToHost));
+  return PDBO_OK;
+}
+
 pdbo_status qubo_gda_eval(pdbo_ctx* c, const uint8_t* xr, int32_t nb, int64_t* F) {
   if (!c || !xr || !F) return fail(c, PDBO_EINVAL, "NULL argument");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (is_real(c)) return fail(c, PDBO_EUNSUPPORTED, "float64 weights: use qubo_gda_eval_f64");
   if (nb < 1 || nb > c->B) return fail(c, PDBO_EINVAL, "nb must be in [1, B]");
   const int n = c->n_of[0];
   const int vmax = c->kind == 4 ? c->kcut.k - 1 : 1;  // Max-k-Cut: categories 0..k-1
@@ -2127,6 +2418,7 @@ pdbo_status qubo_gda_eval_noalloc(pdbo_ctx* c, const uint8_t* xr, int32_t nb, in
                                   void* stream) {
   if (!c || !xr || !F) return fail(c, PDBO_EINVAL, "NULL argument");
   if (c->kind == 0 && c->insts_h.size() != 1) return fail(c, PDBO_ESTATE, "batched context");
+  if (is_real(c)) return fail(c, PDBO_EUNSUPPORTED, "float64 weights: no int64 objectives");
   if (nb < 1 || nb > c->B) return fail(c, PDBO_EINVAL, "nb must be in [1, B]");
   const hipStream_t s = (hipStream_t)stream;
   const int n = c->n_of[0];
@@ -2186,6 +2478,7 @@ pdbo_status qubo_dual_bound(pdbo_ctx* c, double ybar, int32_t iters, double* low
     return fail(c, PDBO_EUNSUPPORTED, "the dual certificate is built for QUBO contexts");
   if (c->par.g_kind != PDBO_G_QUAD)
     return fail(c, PDBO_EUNSUPPORTED, "the dual certificate is built for the quadratic g");
+  if (is_real(c)) return fail(c, PDBO_EUNSUPPORTED, "the dual certificate takes integer weights");
   if (ybar == 0.0) ybar = c->par.y0;
   if (!finite_pos(ybar)) return fail(c, PDBO_EINVAL, "ybar must be finite and > 0 (or 0 for y0)");
   if (iters < 0) return fail(c, PDBO_EINVAL, "iters must be >= 0");
@@ -2596,8 +2889,22 @@ pdbo_status maxsat_lagrangian_bwd(pdbo_ctx* c, const float* x, const float* y, c
   return PDBO_OK;
 }
 
+static pdbo_status trace_records(pdbo_ctx* c, int32_t cap, int64_t* t, int64_t* F, double* Fd,
+                                 int32_t* b, double* sec, int32_t* len);
+
 pdbo_status qubo_gda_trace(pdbo_ctx* c, int32_t cap, int64_t* t, int64_t* F, int32_t* b,
                            double* sec, int32_t* len) {
+  if (c && is_real(c)) return fail(c, PDBO_EUNSUPPORTED, "float64 weights: use qubo_gda_trace_f64");
+  return trace_records(c, cap, t, F, nullptr, b, sec, len);
+}
+
+pdbo_status qubo_gda_trace_f64(pdbo_ctx* c, int32_t cap, int64_t* t, double* F, int32_t* b,
+                               double* sec, int32_t* len) {
+  return trace_records(c, cap, t, nullptr, F, b, sec, len);
+}
+
+static pdbo_status trace_records(pdbo_ctx* c, int32_t cap, int64_t* t, int64_t* F, double* Fd,
+                                 int32_t* b, double* sec, int32_t* len) {
   if (!c || !len) return fail(c, PDBO_EINVAL, "NULL argument");
   if (cap < 0) return fail(c, PDBO_EINVAL, "cap must be >= 0");
   *len = 0;
@@ -2627,6 +2934,12 @@ pdbo_status qubo_gda_trace(pdbo_ctx* c, int32_t cap, int64_t* t, int64_t* F, int
   for (int i = 0; i < k; ++i) {
     if (t) t[i] = tr[i].t;
     if (F) F[i] = tr[i].F;
+    if (Fd) {  // float64 weights keep the bits of the rounded value
+      if (is_real(c))
+        std::memcpy(&Fd[i], &tr[i].F, sizeof(double));
+      else
+        Fd[i] = (double)tr[i].F;
+    }
     if (b) b[i] = (int32_t)tr[i].b;
     if (sec) sec[i] = (tr[i].ts >= ts0 && ts0) ? (double)(tr[i].ts - ts0) / hz : 0.0;
   }

@@ -296,7 +296,20 @@ struct SpmmDev {
   int grid;               // workgroups of a launch (a multiple of nslices)
   float kos;              // kappa / s
   GdaP gp;
+  // float64 weights (ndig > 0): the gradient reads valf = A/s in float32, the
+  // exact objective ndig signed base-2^24 digits of the canonical integers in
+  // units of 2^elo (A = sum_d 2^(24 d) Adig[d], c' likewise), with
+  // F = N 2^(elo - 1), N = S + 2 C (S over ordered pairs, C the linear part).
+  // part then holds [nslices][2 ndig][W][grid / nslices].
+  const float* valf;
+  const int32_t* Adig;    // [ndig][nnz]
+  const int32_t* Cdig;    // [ndig][n]
+  int64_t nnz;
+  int ndig, elo;
+  uint64_t* incw;         // [4] the incumbent's N, 256-bit two's complement
+  double* Fd;             // [B] objectives of the last evaluation, rounded to float64
 };
+constexpr int kMaxDigits = 8;  // 192 bits of fixed point
 // mode 0: gradient, Alg. 1 update into X[parity ^ 1] and Y, and the exact
 // objective of round(X[parity]) into the partials; mode 1: the objective only;
 // mode 2: the gradient only, into G (node-major)
@@ -306,6 +319,16 @@ hipError_t launch_spmm(const SpmmDev& d, int mode, int parity, float* G, hipStre
 // advance != 0, the iteration counter moves on.  The winning rounded vector
 // is read from X[parity].
 hipError_t launch_spmm_best(const SpmmDev& d, int parity, int advance, hipStream_t s);
+// float64-weight forms (realw.hip).  launch_spmm and launch_spmm_best call
+// these when d.ndig > 0.  With Fout != NULL, launch_spmm_real_best writes the
+// objectives of X[parity]'s first nb restarts, correctly rounded, into Fout,
+// without touching the incumbent (after a mode-1 pass over X[parity]).
+hipError_t launch_spmm_real(const SpmmDev& d, int mode, int parity, float* G, hipStream_t s);
+hipError_t launch_spmm_real_best(const SpmmDev& d, int parity, int advance, double* Fout, int nb,
+                                 hipStream_t s);
+// restart-major host bytes (nb, n) -> node-major 0/1 floats of X[parity], other restarts 0
+hipError_t launch_real_load_x(const uint8_t* xr, int nb, const SpmmDev& d, int parity,
+                              hipStream_t s);
 // node-major state <-> restart-major host layout helpers on the device
 hipError_t launch_spmm_init(const double* x0, const SpmmDev& d, float y0, uint64_t seed,
                             hipStream_t s);

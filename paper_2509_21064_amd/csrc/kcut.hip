@@ -169,10 +169,12 @@ hipError_t launch_kcut(const KcutDev& d, int mode, int parity, float* G, hipStre
 }
 
 constexpr int kKBestThreads = 1024;
+constexpr int kKPartUnroll = 16;  // partials per lane loaded in one batch
 
 // Objectives F_b = (sum of the rows' same-category weights) / 2 (each edge is
 // seen from both ends), first argmin, incumbent with strict improvement, and
 // the winner's categories copied from X[parity].
+template <int K>
 __global__ void __launch_bounds__(kKBestThreads) kcut_best_kernel(KcutDev D, int parity,
                                                                   int advance) {
   __shared__ int64_t sF[kKBestThreads / 64];
@@ -183,11 +185,27 @@ __global__ void __launch_bounds__(kKBestThreads) kcut_best_kernel(KcutDev D, int
   const int gpw = D.grid / D.nslices;
   int64_t bestF = LLONG_MAX;
   int bestb = INT_MAX;
+  // the incumbent and the trace length travel with the partials' loads
+  int64_t incF = 0;
+  int len = 0;
+  if (tid == 0) {
+    incF = D.inc->F;
+    len = *D.trace_len;
+  }
   for (int b = wid; b < D.B; b += kKBestThreads / 64) {  // one wave per restart, fixed order
     const int slice = b / D.W, bl = b - slice * D.W;
     const int64_t* pS = D.part + ((size_t)slice * D.W + bl) * gpw;
     int64_t S = 0;
-    for (int q = lane; q < gpw; q += 64) S += pS[q];
+    for (int q0 = lane; q0 < gpw; q0 += 64 * kKPartUnroll) {  // loads of a batch in flight together
+      int64_t a[kKPartUnroll];
+#pragma unroll
+      for (int u = 0; u < kKPartUnroll; ++u) {
+        const int q = q0 + u * 64;
+        a[u] = q < gpw ? pS[q] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kKPartUnroll; ++u) S += a[u];
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) S += __shfl_xor(S, o);
     const int64_t F = S / 2;
@@ -218,13 +236,12 @@ __global__ void __launch_bounds__(kKBestThreads) kcut_best_kernel(KcutDev D, int
         bestb = sb[w];
       }
     int improved = 0;
-    if (t >= 1 && bestb != INT_MAX && bestF < D.inc->F) {
+    if (t >= 1 && bestb != INT_MAX && bestF < incF) {
       const uint64_t ts = wall_clock();
       D.inc->F = bestF;
       D.inc->t = t;
       D.inc->b = bestb;
       D.inc->ts = ts;
-      const int len = *D.trace_len;
       if (len < D.trace_cap) {
         D.trace[len] = TraceRec{t, bestF, (int64_t)bestb, ts};
         *D.trace_len = len + 1;
@@ -235,31 +252,38 @@ __global__ void __launch_bounds__(kKBestThreads) kcut_best_kernel(KcutDev D, int
     if (advance) *D.t_dev = t + 1;
   }
   __syncthreads();
-  if (win >= 0) {  // the winner's categories; four nodes' loads in flight per thread
+  if (win >= 0) {  // the winner's categories; eight nodes' K loads in flight per thread
     const float* X = D.X[parity];
-    constexpr int U = 4;
+    constexpr int U = 8;
     for (int i0 = tid; i0 < D.n; i0 += U * kKBestThreads) {
-      float v[U][8];
+      float v[U][K];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const float* x = X + ((size_t)min(i0 + u * kKBestThreads, D.n - 1) * D.B + win) * D.k;
+        const float* x = X + ((size_t)min(i0 + u * kKBestThreads, D.n - 1) * D.B + win) * K;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[u][c] = c < D.k ? x[c] : -INFINITY;
+        for (int c = 0; c < K; ++c) v[u][c] = x[c];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        int c = 0;
-#pragma unroll
-        for (int cc = 1; cc < 8; ++cc)
-          if (v[u][cc] > v[u][c]) c = cc;
-        if (i0 + u * kKBestThreads < D.n) D.best_x[i0 + u * kKBestThreads] = (uint8_t)c;
-      }
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * kKBestThreads < D.n) D.best_x[i0 + u * kKBestThreads] = (uint8_t)argmax_k<K>(v[u]);
     }
   }
 }
 
 hipError_t launch_kcut_best(const KcutDev& d, int parity, int advance, hipStream_t s) {
-  hipLaunchKernelGGL(kcut_best_kernel, dim3(1), dim3(kKBestThreads), 0, s, d, parity, advance);
+#define PDBO_KB(KK) \
+  hipLaunchKernelGGL(kcut_best_kernel<KK>, dim3(1), dim3(kKBestThreads), 0, s, d, parity, advance)
+  switch (d.k) {
+    case 2: PDBO_KB(2); break;
+    case 3: PDBO_KB(3); break;
+    case 4: PDBO_KB(4); break;
+    case 5: PDBO_KB(5); break;
+    case 6: PDBO_KB(6); break;
+    case 7: PDBO_KB(7); break;
+    case 8: PDBO_KB(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PDBO_KB
   return hipGetLastError();
 }
 

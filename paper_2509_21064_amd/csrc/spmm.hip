@@ -109,6 +109,7 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parit
 }
 
 hipError_t launch_spmm(const SpmmDev& d, int mode, int parity, float* G, hipStream_t s) {
+  if (d.ndig > 0) return launch_spmm_real(d, mode, parity, G, s);
   const dim3 grid(d.grid), blk(kSpmmThreads);
 #define PDBO_S(GK, M) hipLaunchKernelGGL((spmm_kernel<GK, M>), grid, blk, 0, s, d, parity, G)
   const int gk = d.gp.gkind;
@@ -128,6 +129,7 @@ hipError_t launch_spmm(const SpmmDev& d, int mode, int parity, float* G, hipStre
 }
 
 constexpr int kBestThreads = 1024;
+constexpr int kPartUnroll = 16;  // partials per lane loaded in one batch
 
 __global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int parity,
                                                                  int advance) {
@@ -139,6 +141,13 @@ __global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int 
   const int gpw = D.grid / D.nslices;
   int64_t bestF = LLONG_MAX;
   int bestb = INT_MAX;
+  // the incumbent and the trace length travel with the partials' loads
+  int64_t incF = 0;
+  int len = 0;
+  if (tid == 0) {
+    incF = D.inc->F;
+    len = *D.trace_len;
+  }
   // one wave per restart: the lanes add the workgroups' partials (contiguous)
   // in a fixed order, so the totals are the same on every run
   for (int b = wid; b < D.B; b += kBestThreads / 64) {
@@ -146,9 +155,19 @@ __global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int 
     const int64_t* pS = D.part + ((size_t)(slice * 2 + 0) * D.W + bl) * gpw;
     const int64_t* pC = D.part + ((size_t)(slice * 2 + 1) * D.W + bl) * gpw;
     int64_t S = 0, C = 0;
-    for (int q = lane; q < gpw; q += 64) {
-      S += pS[q];
-      C += pC[q];
+    for (int q0 = lane; q0 < gpw; q0 += 64 * kPartUnroll) {  // loads of a batch in flight together
+      int64_t a[kPartUnroll], c[kPartUnroll];
+#pragma unroll
+      for (int u = 0; u < kPartUnroll; ++u) {
+        const int q = q0 + u * 64;
+        a[u] = q < gpw ? pS[q] : 0;
+        c[u] = q < gpw ? pC[q] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kPartUnroll; ++u) {
+        S += a[u];
+        C += c[u];
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -183,13 +202,12 @@ __global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int 
         bestb = sb[w];
       }
     int improved = 0;
-    if (t >= 1 && bestb != INT_MAX && bestF < D.inc->F) {
+    if (t >= 1 && bestb != INT_MAX && bestF < incF) {
       const uint64_t ts = wall_clock();
       D.inc->F = bestF;
       D.inc->t = t;
       D.inc->b = bestb;
       D.inc->ts = ts;
-      const int len = *D.trace_len;
       if (len < D.trace_cap) {
         D.trace[len] = TraceRec{t, bestF, (int64_t)bestb, ts};
         *D.trace_len = len + 1;
@@ -218,6 +236,7 @@ __global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int 
 }
 
 hipError_t launch_spmm_best(const SpmmDev& d, int parity, int advance, hipStream_t s) {
+  if (d.ndig > 0) return launch_spmm_real_best(d, parity, advance, nullptr, 0, s);
   hipLaunchKernelGGL(spmm_best_kernel, dim3(1), dim3(kBestThreads), 0, s, d, parity, advance);
   return hipGetLastError();
 }

@@ -48,7 +48,8 @@ def test_struct_layout_matches_c():
 int main(void) {
   printf("pdbo_qubo %zu\npdbo_maxsat %zu\npdbo_params %zu\npdbo_result %zu\n",
          sizeof(pdbo_qubo), sizeof(pdbo_maxsat), sizeof(pdbo_params), sizeof(pdbo_result));
-  P(pdbo_qubo, nnz) P(pdbo_qubo, c) P(pdbo_params, alpha) P(pdbo_params, scale)
+  P(pdbo_qubo, nnz) P(pdbo_qubo, c) P(pdbo_qubo, wtype) P(pdbo_qubo, qd) P(pdbo_qubo, cd)
+  P(pdbo_result, best_obj_f64) P(pdbo_params, alpha) P(pdbo_params, scale)
   P(pdbo_params, tile) P(pdbo_params, x0) P(pdbo_params, g_degree) P(pdbo_params, dual_kind)
   P(pdbo_params, seed) P(pdbo_result, best_iter) P(pdbo_result, best_x)
   P(pdbo_maxsat, lits) P(pdbo_maxsat, w)
@@ -125,6 +126,34 @@ def test_invalid_x0(lib):
     import torch
     if not torch.cuda.is_available():
         assert _init(lib, q, p, None) in (_abi.PDBO_EDEVICE, _abi.PDBO_ENOMEM)
+
+
+def test_real_weights_rejected_before_the_device(lib):
+    """Float64 weights: non-finite entries (EINVAL), an exponent span beyond
+    the 192 bits of the exact evaluation (ERANGE), the restart-resident tile and
+    batches (EUNSUPPORTED) are refused on the host."""
+    import paper_2509_21064_amd as P
+    _, p, _ = _base()
+    n = 12
+    g = np.random.default_rng(3)
+    Q = g.standard_normal((n, n))
+    x0 = W.x0_uniform(1, 0, 4, n, n)
+    bad = Q.copy()
+    bad[2, 3] = float("inf")
+    assert _init(lib, W.Qubo(n=n, Q=bad), p, x0) == _abi.PDBO_EINVAL
+    c = np.zeros(n)
+    c[4] = float("nan")
+    assert _init(lib, W.Qubo(n=n, Q=Q, c=c), p, x0) == _abi.PDBO_EINVAL
+    wide = Q.copy()
+    wide[0, 1] = 2.0 ** 100
+    wide[5, 6] = 2.0 ** -100          # bits 100 .. -152: 253 bits
+    assert _init(lib, W.Qubo(n=n, Q=wide), p, x0) == _abi.PDBO_ERANGE
+    assert _init(lib, W.Qubo(n=n, Q=Q), dict(p, tile=1), x0) == _abi.PDBO_EUNSUPPORTED
+    keep = P._Keep()
+    probs = (_abi.pdbo_qubo * 1)(P._qubo_struct(W.Qubo(n=n, Q=Q), keep))
+    pars = (_abi.pdbo_params * 1)(P._params_struct(p, x0, keep))
+    h = ctypes.c_void_p()
+    assert lib.qubo_gda_batch_init(1, probs, pars, 1, None, ctypes.byref(h)) == _abi.PDBO_EUNSUPPORTED
 
 
 def test_invalid_csr(lib):

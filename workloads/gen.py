@@ -27,7 +27,7 @@ __all__ = [
     "Qubo", "MaxSat", "rng_for", "x0_uniform",
     "gnp_pm1", "qubo_c1", "qubo_c1_twin", "maxcut_c2", "qubo_c3", "batch_c4",
     "maxsat_c5", "random_dense_qubo", "random_asym_qubo", "random_maxsat",
-    "random_regular_graph", "mis_qubo", "Kcut", "kcut_graph",
+    "random_regular_graph", "mis_qubo", "real_qubo", "Kcut", "kcut_graph",
 ]
 
 
@@ -215,6 +215,35 @@ def mis_qubo(n: int, d: int, rep: int = 0, lam: int = 4) -> Qubo:
     rp, col, val = _csr_from_upper(n, E[:, 0], E[:, 1], np.full(len(E), lam // 2, dtype=np.int64))
     return Qubo(n=n, row_ptr=rp, col_idx=col, vals=val, c=np.full(n, -1, dtype=np.int64),
                 name=f"mis_d{d}_n{n}", meta=dict(edges=E, d=d, lam=lam))
+
+
+def real_qubo(n: int, M: int, rep: int = 0, spread: int = 0, dense: bool = False) -> Qubo:
+    """QUBO with float64 weights (Eq. 1 with real Q, c): M distinct random
+    off-diagonal positions (i, j), i != j, each stored once (Q asymmetric),
+    plus a diagonal; values N(0, 1) times 2^U{-spread..spread}, c likewise times
+    10.  dense: the (n, n) array instead of CSR."""
+    g = rng_for(8, rep, 0, n, M, spread)
+    lin = g.choice(n * (n - 1), size=M, replace=False)
+    i = lin // (n - 1)
+    j = lin % (n - 1)
+    j = j + (j >= i)                                  # skip the diagonal
+    scale = lambda k: np.exp2(g.integers(-spread, spread + 1, size=k)) if spread else 1.0
+    w = g.standard_normal(M) * scale(M)
+    diag = g.standard_normal(n) * scale(n)
+    c = 10.0 * g.standard_normal(n) * scale(n)
+    ii = np.concatenate([i, np.arange(n)])
+    jj = np.concatenate([j, np.arange(n)])
+    ww = np.concatenate([w, diag])
+    if dense:
+        Q = np.zeros((n, n))
+        Q[ii, jj] = ww
+        return Qubo(n=n, Q=Q, c=c, name=f"real_dense_n{n}_m{M}_s{spread}")
+    order = np.lexsort((jj, ii))
+    ii, jj, ww = ii[order], jj[order], ww[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, ii + 1, 1)
+    return Qubo(n=n, row_ptr=np.cumsum(row_ptr).astype(np.int32), col_idx=jj.astype(np.int32),
+                vals=ww, c=c, name=f"real_csr_n{n}_m{M}_s{spread}")
 
 
 @dataclass
