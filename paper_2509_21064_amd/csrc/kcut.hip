@@ -23,6 +23,7 @@
 namespace pdbo {
 
 constexpr int kKcutThreads = 256;
+constexpr int kKcutUnroll = 4;  // neighbours whose loads are in flight together
 
 template <int K>
 __device__ __forceinline__ int argmax_k(const float (&x)[K]) {
@@ -94,16 +95,27 @@ __global__ void __launch_bounds__(kKcutThreads) kcut_kernel(KcutDev D, int parit
     }
     const int ci = argmax_k<K>(xi);
     int same = 0;
-    for (int p = D.row_ptr[i]; p < D.row_ptr[i + 1]; ++p) {
-      const int j = D.col[p];
-      const int wv = D.w[p];
-      const float* xj = Xc + ((size_t)j * B + b) * K;
-      float v[K];
+    const int pe = D.row_ptr[i + 1];
+    // groups of kKcutUnroll neighbours, the last one padded with the row's
+    // last entry at weight 0 (same addresses): their loads are in flight together
+    for (int p = D.row_ptr[i]; p < pe; p += kKcutUnroll) {
+      int wv[kKcutUnroll];
+      float v[kKcutUnroll][K];
 #pragma unroll
-      for (int u = 0; u < K; ++u) v[u] = xj[u];
+      for (int e = 0; e < kKcutUnroll; ++e) {
+        const int q = min(p + e, pe - 1);
+        const int j = D.col[q];
+        wv[e] = p + e < pe ? D.w[q] : 0;
+        const float* xj = Xc + ((size_t)j * B + b) * K;
 #pragma unroll
-      for (int u = 0; u < K; ++u) acc[u] = fmaf((float)wv, v[u], acc[u]);
-      same += argmax_k<K>(v) == ci ? wv : 0;
+        for (int u = 0; u < K; ++u) v[e][u] = xj[u];
+      }
+#pragma unroll
+      for (int e = 0; e < kKcutUnroll; ++e) {
+#pragma unroll
+        for (int u = 0; u < K; ++u) acc[u] = fmaf((float)wv[e], v[e][u], acc[u]);
+        same += argmax_k<K>(v[e]) == ci ? wv[e] : 0;
+      }
     }
     if constexpr (MODE != 2) S += same;
     if constexpr (MODE == 0) {

@@ -53,13 +53,25 @@ __global__ void __launch_bounds__(kRThreads) spmm_real_kernel(SpmmDev D, int par
     long long r[kMaxDigits];
 #pragma unroll
     for (int d = 0; d < kMaxDigits; ++d) r[d] = 0;
-    for (int p = D.row_ptr[i]; p < pe; ++p) {
-      const float xk = Xc[(size_t)D.col[p] * B + b];
-      acc = fmaf(D.valf[p], xk, acc);
-      if (MODE != 2 && xk > 0.5f) {
+    // groups of four entries, the last padded with the row's last entry
+    // (masked): their gathers are in flight together
+    for (int p = D.row_ptr[i]; p < pe; p += 4) {
+      float xk[4], a[4];
 #pragma unroll
-        for (int d = 0; d < kMaxDigits; ++d)
-          if (d < nd) r[d] += D.Adig[(size_t)d * D.nnz + p];
+      for (int u = 0; u < 4; ++u) {
+        const int q = min(p + u, pe - 1);
+        xk[u] = Xc[(size_t)D.col[q] * B + b];
+        a[u] = D.valf[q];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool in = p + u < pe;
+        acc = fmaf(in ? a[u] : 0.f, xk[u], acc);
+        if (MODE != 2 && in && xk[u] > 0.5f) {
+#pragma unroll
+          for (int d = 0; d < kMaxDigits; ++d)
+            if (d < nd) r[d] += D.Adig[(size_t)d * D.nnz + p + u];
+        }
       }
     }
     const size_t off = (size_t)i * B + b;

@@ -70,10 +70,22 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parit
         accr += xk[u] > 0.5f ? v[u] : 0;
       }
     }
-    for (; p < pe; ++p) {
-      const float xk = Xc[(size_t)col[p] * B + b];
-      acc = fmaf((float)val[p], xk, acc);
-      accr += xk > 0.5f ? val[p] : 0;
+    if (p < pe) {  // the rest of the row in one group, padded with its last entry at value 0
+      int c[kSpmmUnroll], v[kSpmmUnroll];
+      float xk[kSpmmUnroll];
+#pragma unroll
+      for (int u = 0; u < kSpmmUnroll; ++u) {
+        const int q = min(p + u, pe - 1);
+        c[u] = col[q];
+        v[u] = p + u < pe ? val[q] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kSpmmUnroll; ++u) xk[u] = Xc[(size_t)c[u] * B + b];
+#pragma unroll
+      for (int u = 0; u < kSpmmUnroll; ++u) {
+        acc = fmaf((float)v[u], xk[u], acc);
+        accr += xk[u] > 0.5f ? v[u] : 0;
+      }
     }
     const size_t off = (size_t)i * B + b;
     const float x = Xc[off];
