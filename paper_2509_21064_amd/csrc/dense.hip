@@ -15,9 +15,10 @@
 // Operands are both K-contiguous: row i of Ahat (Ahat is symmetric) and row b
 // of the restart-major shadow.  Every K step consumes one 128-byte chunk of
 // each row, whatever the element type, so a lane always reads 32 bytes per
-// 16-row fragment: row (lane % 16), bytes [32*(lane/16), +32) of the chunk.
-// The same lane->k mapping is used for both operands, which is all the MFMA
-// dot product needs.  Output layout of the 16x16 MFMA: lane holds rows
+// 16-row fragment: row (lane % 16), two 16-byte pieces of the chunk (bytes
+// [32*(lane/16), +32) in the register-staged kernel, pieces lane/16 and
+// lane/16 + 4 in the DMA kernel).  The same lane->k mapping is used for both
+// operands, which is all the MFMA dot product needs.  Output layout of the 16x16 MFMA: lane holds rows
 // 4*(lane/16)+r, r = 0..3, of column lane % 16.
 #include <climits>
 
@@ -794,9 +795,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
 // lane L of a wave writes 16 bytes at LDS base + 16 L), so no registers are
 // spent on staging and two K chunks are in flight while a third is consumed.
 // Rows are stored unpadded (128 bytes) with the 16-byte chunks XOR-swizzled by
-// (row / 2) mod 8: one DMA instruction fills 8 whole rows, and the 16 rows of
-// a fragment read (two rows per 256-byte bank period of the 64-bank LDS) land
-// on 16 distinct 16-byte bank groups.  The three stages are
+// (row / 2) mod 8: one DMA instruction fills 8 whole rows, and a fragment read
+// (16 rows, chunks q or q + 4 for the four quarter-waves q) is free of bank
+// conflicts.  The three stages are
 // distinct LDS objects and the K loop is unrolled by three, so every stage is
 // addressed statically.
 
@@ -838,11 +839,15 @@ __global__ void __launch_bounds__(64 * WM * WN)
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid % WM, wn = wid / WM;
-  // fragment read offsets: row (lane % 16) of a 16-row group, logical chunks
-  // 2q and 2q+1 (q = lane / 16) stored at physical chunk c ^ ((row / 2) mod 8)
+  // fragment read offsets: row (lane % 16) of a 16-row group, logical chunk q
+  // for the first half of the K step and q + 4 for the second (q = lane / 16),
+  // stored at physical chunk c ^ ((row / 2) mod 8).  Both operands pair the
+  // same k with the same lane slot, which is all the MFMA needs; with chunks
+  // q (not 2q) in one read the 64 lanes hit the LDS banks without conflicts
+  // (measured: 4 cycles per ds_read_b128 instead of 8 for chunks 2q, 2q + 1)
   const int sw = (lane & 15) >> 1, q = lane >> 4;
-  const int fo0 = (lane & 15) * 128 + (((2 * q) ^ sw) << 4);
-  const int fo1 = (lane & 15) * 128 + (((2 * q + 1) ^ sw) << 4);
+  const int fo0 = (lane & 15) * 128 + ((q ^ sw) << 4);
+  const int fo1 = (lane & 15) * 128 + (((q + 4) ^ sw) << 4);
 
   for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
     const TileDev td = tiles[w];
