@@ -1593,6 +1593,17 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
     STCHK(dalloc(c, &rp, n + 1));
     HIPCHK(c, hipMemcpyAsync(rp, C.rp.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream));
     d.row_ptr = rp;
+    // rows by decreasing degree (ties by index): a wave's rows then have
+    // nearly the same number of entries
+    std::vector<int32_t> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return C.rp[a + 1] - C.rp[a] > C.rp[b + 1] - C.rp[b];
+    });
+    int32_t* ord = nullptr;
+    STCHK(dalloc(c, &ord, n));
+    HIPCHK(c, hipMemcpyAsync(ord, order.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    d.order = ord;
     // host staging lives until the stream is synchronised at the end of init
     std::vector<uint32_t> pk;
     int32_t* col = nullptr;

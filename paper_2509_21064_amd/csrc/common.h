@@ -252,6 +252,8 @@ struct CsrDev {
   uint64_t* rbestTs;
   uint8_t* best_xr;       // [B][n]
   int64_t* Flast;         // [B]
+  const int32_t* order;   // [n] rows by decreasing degree: thread t of the
+                          // persistent kernel owns rows order[t + j * threads]
   int64_t nnz;
   int n, ld, B, kappa;
   int small32;            // 512 * max_i sum_j |Ahat_ij| and 512 * max_i |c'_i| are below 2^31

@@ -128,16 +128,22 @@ __global__ void __launch_bounds__(NT)
   constexpr bool CREG = RMAX <= 8;
   float xr[RMAX], yr[RMAX], xn[RMAX], cps[CREG ? RMAX : 1];
   Part cpr[CREG ? RMAX : 1];
+  // the thread's rows, taken in order of decreasing degree so that the 64 rows
+  // of a wave round have nearly the same length (fewer idle lanes in the
+  // gathers); -1 past the end
+  int rows[RMAX];
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) rows[j] = tid + j * NT < n ? D.order[tid + j * NT] : -1;
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
-    const int i = tid + j * NT;
+    const int i = rows[j];
     xr[j] = 0.f;
     yr[j] = 0.f;
     if constexpr (CREG) {
       cps[j] = 0.f;
       cpr[j] = 0;
     }
-    if (i < n) {
+    if (i >= 0) {
       xr[j] = D.X[(size_t)b * D.ld + i];
       yr[j] = D.Y[(size_t)b * D.ld + i];
       if constexpr (CREG) {
@@ -162,8 +168,8 @@ __global__ void __launch_bounds__(NT)
     Part S = 0, C = 0;
 #pragma unroll
     for (int j = 0; j < RMAX; ++j) {
-      const int i = tid + j * NT;
-      if (i < n) {
+      const int i = rows[j];
+      if (i >= 0) {
         float acc;
         int accr;
         row_gather<PACKED>(i, rp, ent, col, val, xcur, acc, accr);
@@ -205,8 +211,8 @@ __global__ void __launch_bounds__(NT)
         float* xnext = xs + ((s + 1) & 1) * xstride;
 #pragma unroll
         for (int j = 0; j < RMAX; ++j) {
-          const int i = tid + j * NT;
-          if (i < n) xnext[i] = xn[j];
+          const int i = rows[j];
+          if (i >= 0) xnext[i] = xn[j];
         }
       }
     }
@@ -227,16 +233,16 @@ __global__ void __launch_bounds__(NT)
         uint8_t* dst = D.best_xr + (size_t)b * n;
 #pragma unroll
         for (int j = 0; j < RMAX; ++j) {
-          const int i = tid + j * NT;
-          if (i < n) dst[i] = (uint8_t)(xr[j] > 0.5f);
+          const int i = rows[j];
+          if (i >= 0) dst[i] = (uint8_t)(xr[j] > 0.5f);
         }
       }
     }
     if (upd) {
 #pragma unroll
       for (int j = 0; j < RMAX; ++j) {
-        const int i = tid + j * NT;
-        if (i < n) {
+        const int i = rows[j];
+        if (i >= 0) {
           if constexpr (!DBUF) xs[i] = xn[j];
           xr[j] = xn[j];
         }
@@ -246,8 +252,8 @@ __global__ void __launch_bounds__(NT)
   }
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
-    const int i = tid + j * NT;
-    if (i < n) {
+    const int i = rows[j];
+    if (i >= 0) {
       D.X[(size_t)b * D.ld + i] = xr[j];
       D.Y[(size_t)b * D.ld + i] = yr[j];
     }
