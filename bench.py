@@ -505,10 +505,25 @@ def workload_c4(args, P):
         log(f"c4 {mode}: {out[mode]['value']:.4g} restart-it/s, {out[mode]['ms_per_step']:.3f} ms/step, "
             f"step kernels {step_ms:.3f} ms/iteration")
     g = out["grouped"]
-    achieved = flops / (g["step_kernels_ms_per_iteration"] * 1e-3) / 1e12
+    t_step = g["step_kernels_ms_per_iteration"] * 1e-3
+    achieved = flops / t_step / 1e12
     peak = PEAK_TFLOPS[args.c4_prec]
-    out["roofline"] = dict(bound="mfma", kernel="dense_gemm_dma (grouped STEP)", achieved=achieved,
-                           peak=peak, unit="TFLOP/s", frac=achieved / peak)
+    # algorithmic bytes of one iteration's step launches: every instance's
+    # operand copy of Ahat once (n^2 elements), and per (coordinate, restart)
+    # x and y read and written (16 B), the operand shadow read by the GEMM and
+    # written by the epilogue, and the rounded byte read and written
+    eb = {"fp32": 4, "bf16": 2, "fp8": 1, "i8": 1}[args.c4_prec]
+    nbytes = float(sum(q.n * q.n * eb + q.n * B * (16 + 2 * eb + 2) for q in qs))
+    # 2 B operations per byte of Ahat: below the chip's ratio of MFMA peak to HBM
+    # bandwidth, so the step launches are bound by HBM
+    gbs = nbytes / t_step / 1e9
+    out["roofline"] = dict(bound="hbm", kernel="dense_gemm_dma (grouped STEP)", achieved=gbs,
+                           peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                           bytes_per_iteration=nbytes, mfma_achieved_tflops=achieved,
+                           mfma_peak_tflops=peak, mfma_frac=achieved / peak,
+                           note=f"arithmetic intensity 2B/{eb} = {2 * B / eb:.0f} operations per byte of "
+                                f"Ahat, below the {peak * 1e3 / HBM_PEAK_GBS:.0f} of the chip's "
+                                f"{args.c4_prec} MFMA peak over its HBM bandwidth")
     out["value"] = g["value"]
     out["speedup_grouped"] = g["value"] / out["per_instance"]["value"]
     return out

@@ -2786,7 +2786,8 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
       inc[(size_t)e * k + (k - 1)] = meta;
     }
 
-  std::vector<uint64_t> inc3;  // host staging of the compact entries, alive until init syncs
+  std::vector<uint64_t> inc3, pinc3;  // host staging, alive until init syncs
+  std::vector<int32_t> ord, pptr, pinc;
   pdbo_ctx* c = new pdbo_ctx();
   c->kind = 2;
   c->n_of.push_back(n);
@@ -2830,6 +2831,54 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
       HIPCHK(c, hipMemcpyAsync(d3, inc3.data(), inc3.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
                                c->stream));
       d.inc3 = d3;
+    }
+    // position space of the persistent kernel: variables by decreasing
+    // occurrence count, their lists with the other literals' codes renamed
+    // to positions
+    ord.resize(n);
+    for (int v = 0; v < n; ++v) ord[v] = v;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b2) {
+      return ptr[a + 1] - ptr[a] > ptr[b2 + 1] - ptr[b2];
+    });
+    std::vector<int32_t> posv(n);
+    for (int q = 0; q < n; ++q) posv[ord[q]] = q;
+    pptr.assign(n + 1, 0);
+    for (int q = 0; q < n; ++q) pptr[q + 1] = pptr[q] + (ptr[ord[q] + 1] - ptr[ord[q]]);
+    pinc.resize(inc.size());
+    auto rename = [&](int32_t code) {
+      return (int32_t)(((uint32_t)code & 0x80000000u) | (uint32_t)posv[code & 0x7fffffff]);
+    };
+    for (int q = 0; q < n; ++q) {
+      const int v = ord[q];
+      for (int e = ptr[v], f = pptr[q]; e < ptr[v + 1]; ++e, ++f) {
+        for (int o = 0; o < k - 1; ++o) pinc[(size_t)f * k + o] = rename(inc[(size_t)e * k + o]);
+        pinc[(size_t)f * k + (k - 1)] = inc[(size_t)e * k + (k - 1)];
+      }
+    }
+    int32_t *dord = nullptr, *dpp = nullptr, *dpi = nullptr;
+    STCHK(dalloc(c, &dord, n));
+    STCHK(dalloc(c, &dpp, n + 1));
+    STCHK(dalloc(c, &dpi, pinc.size()));
+    HIPCHK(c, hipMemcpyAsync(dord, ord.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dpp, pptr.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dpi, pinc.data(), pinc.size() * 4, hipMemcpyHostToDevice, c->stream));
+    d.order = dord;
+    d.pinc_ptr = dpp;
+    d.pinc = dpi;
+    if (k == 3) {
+      pinc3.resize(pptr[n]);
+      auto c16 = [](int32_t code) {
+        return (uint32_t)(code & 0x7fffffff) | ((code < 0 ? 1u : 0u) << 15);
+      };
+      for (int e = 0; e < pptr[n]; ++e) {
+        const uint32_t lo = c16(pinc[(size_t)e * 3]) | (c16(pinc[(size_t)e * 3 + 1]) << 16);
+        pinc3[e] = (uint64_t)lo | ((uint64_t)(uint32_t)pinc[(size_t)e * 3 + 2] << 32);
+      }
+      uint64_t* d3 = nullptr;
+      STCHK(dalloc(c, &d3, pinc3.size()));
+      HIPCHK(c, hipMemcpyAsync(d3, pinc3.data(), pinc3.size() * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, c->stream));
+      d.pinc3 = d3;
     }
     STCHK(dalloc(c, &d.X, (size_t)B * ld));
     STCHK(dalloc(c, &d.Y, (size_t)B * ld));

@@ -190,6 +190,29 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
   return __builtin_amdgcn_readlane(v, 63);
 }
 
+// One step of a row reduction: v plus the value of the lane SHR lanes lower
+// in the same row of 16 lanes (0 for the first SHR lanes of a row), on the two
+// 32-bit halves of an int64 with the carry.
+template <int CTL>
+__device__ __forceinline__ int64_t row_shr_add_i64(int64_t v) {
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)((uint64_t)v >> 32);
+  const uint32_t slo = __builtin_amdgcn_update_dpp(0u, lo, CTL, 0xf, 0xf, true);
+  const uint32_t shi = __builtin_amdgcn_update_dpp(0u, hi, CTL, 0xf, 0xf, true);
+  return v + (int64_t)(((uint64_t)shi << 32) | slo);
+}
+
+// Sum of v over lanes 0..15 (row 0 of the wave), returned in every lane: row
+// shifts by 1, 2, 4 and 8 leave each row's total in its lane 15.  Exact in int64.
+__device__ __forceinline__ int64_t row16_sum_i64(int64_t v) {
+  v = row_shr_add_i64<0x111>(v);  // row_shr:1
+  v = row_shr_add_i64<0x112>(v);  // row_shr:2
+  v = row_shr_add_i64<0x114>(v);  // row_shr:4
+  v = row_shr_add_i64<0x118>(v);  // row_shr:8
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 15);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), 15);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // ---- launchers (dense.hip) --------------------------------------------------
 
 constexpr int kFlipMax = 32;
@@ -400,6 +423,14 @@ struct SatDev {
   uint64_t* rbestTs;
   uint8_t* best_xr;
   int64_t* Flast;
+  // the persistent kernel works on positions p = 0..n-1 holding the variables
+  // order[p] in order of decreasing occurrence count (the variables of a wave
+  // round then have lists of nearly the same length): its occurrence lists are
+  // indexed by position and their literal codes name positions
+  const int32_t* order;     // [n] variable at position p
+  const int32_t* pinc_ptr;  // [n+1]
+  const int32_t* pinc;      // as inc, codes in positions
+  const uint64_t* pinc3;    // as inc3, codes in positions
   int n, m, k, ld, B;
   float ios;                // 1/s
   GdaP gp;

@@ -103,8 +103,14 @@ __device__ __forceinline__ float sat3_adjoint(const SatDev& D, const float* __re
 // registers until the barrier.  Used when many variables fall to each thread
 // and both arrays fit, so that the per-variable state does not spill.
 template <bool K3, int NT, int RMAX, bool YLDS, int GK>
-__global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int nsteps) {
+__global__ void __launch_bounds__(NT) sat_persistent(SatDev Dv, int64_t t0, int nsteps) {
+  // position space (see SatDev::order): thread tid owns positions tid + j NT
+  SatDev D = Dv;
+  D.inc_ptr = Dv.pinc_ptr;
+  D.inc = Dv.pinc;
+  D.inc3 = Dv.pinc3;
   constexpr int NW = NT / 64;
+  static_assert(NW <= 16, "the partials of at most 16 waves are summed by one row of lanes");
   extern __shared__ __attribute__((aligned(16))) float xs[];
   __shared__ int64_t red[2][NW];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -119,7 +125,8 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
       yr[j] = 0.f;
     }
     if (i < n) {
-      const float x = D.X[(size_t)b * D.ld + i], y = D.Y[(size_t)b * D.ld + i];
+      const int v = D.order[i];
+      const float x = D.X[(size_t)b * D.ld + v], y = D.Y[(size_t)b * D.ld + v];
       xs[i] = x;
       if constexpr (YLDS) {
         ys[i] = y;
@@ -167,9 +174,9 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
     }
     __syncthreads();
     if (ev) {
-      int64_t F = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) F += red[s & 1][w];
+      // lane l of every wave takes wave (l mod 16)'s partial; a 16-lane row
+      // reduction gives the total to every lane (NW <= 16)
+      const int64_t F = row16_sum_i64((lane & 15) < NW ? red[s & 1][lane & 15] : 0);
       Flast = F;
       if (F < bF) {
         bF = F;
@@ -179,7 +186,7 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
 #pragma unroll
         for (int j = 0; j < RMAX; ++j) {
           const int i = tid + j * NT;
-          if (i < n) dst[i] = (uint8_t)(xold(j, i) > 0.5f);
+          if (i < n) dst[D.order[i]] = (uint8_t)(xold(j, i) > 0.5f);
         }
       }
     }
@@ -199,8 +206,9 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev D, int64_t t0, int n
   for (int j = 0; j < RMAX; ++j) {
     const int i = tid + j * NT;
     if (i < n) {
-      D.X[(size_t)b * D.ld + i] = xold(j, i);
-      D.Y[(size_t)b * D.ld + i] = YLDS ? ys[i] : yr[j];
+      const int v = D.order[i];
+      D.X[(size_t)b * D.ld + v] = xold(j, i);
+      D.Y[(size_t)b * D.ld + v] = YLDS ? ys[i] : yr[j];
     }
   }
   if (tid == 0) {

@@ -102,6 +102,7 @@ template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK>
 __global__ void __launch_bounds__(NT)
     csr_persistent(CsrDev D, int64_t t0, int nsteps) {
   constexpr int NW = NT / 64;
+  static_assert(NW <= 16, "the partials of at most 16 waves are summed by one row of lanes");
   using Part = typename std::conditional<SMALL, int32_t, int64_t>::type;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ Part red[2][NW][2];
@@ -218,12 +219,11 @@ __global__ void __launch_bounds__(NT)
     }
     __syncthreads();
     if (ev) {
-      int64_t St = 0, Ct = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        St += red[s & 1][w][0];
-        Ct += red[s & 1][w][1];
-      }
+      // lane l of every wave takes wave (l mod 16)'s partials; a 16-lane row
+      // reduction gives the totals to every lane (NW <= 16)
+      const int w = lane & 15;
+      const int64_t St = row16_sum_i64(w < NW ? (int64_t)red[s & 1][w][0] : 0);
+      const int64_t Ct = row16_sum_i64(w < NW ? (int64_t)red[s & 1][w][1] : 0);
       const int64_t F = (D.kappa == 2 ? St : St / 2) + Ct;
       Flast = F;
       if (F < bF) {
