@@ -373,6 +373,10 @@ struct KcutDev {
   int64_t* Flast;
   Incumbent* inc;
   uint8_t* best_x;        // [n] categories of the incumbent
+  int32_t* win;           // [1] restart whose rounded iterate became the incumbent
+                          // and still has to be copied into best_x, or -1: the
+                          // next step launch copies it while it overwrites that
+                          // iterate, the last best-of-B launch of a call at once
   TraceRec* trace;
   int32_t* trace_len;
   int64_t* t_dev;

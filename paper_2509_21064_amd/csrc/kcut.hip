@@ -82,6 +82,8 @@ __global__ void __launch_bounds__(kKcutThreads) kcut_kernel(KcutDev D, int parit
   const float* __restrict__ Xc = D.X[parity];
   float* __restrict__ Xn = D.X[parity ^ 1];
   if (MODE != 2 && tid < 64) sred[tid] = 0;
+  // the previous iteration's new incumbent, still in Xn (see KcutDev::win)
+  const int win = MODE == 0 ? *D.win : -1;
   long long S = 0;
   for (int rb = blockIdx.x / D.nslices; rb < nrb; rb += gpw) {
     const int i = rb * rows_per_wg + wid * G + g;
@@ -134,6 +136,12 @@ __global__ void __launch_bounds__(kKcutThreads) kcut_kernel(KcutDev D, int parit
         D.Z[off + u] = z[u];
       }
       softmax_k<K>(z, xn);
+      if (b == win) {  // this lane is about to overwrite the incumbent's probabilities
+        float xw[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) xw[u] = Xn[off + u];
+        D.best_x[i] = (uint8_t)argmax_k<K>(xw);
+      }
 #pragma unroll
       for (int u = 0; u < K; ++u) Xn[off + u] = xn[u];
       D.Y[(size_t)i * B + b] = fmaf(D.gp.beta, kg_value<GK, K>(xi), y);
@@ -191,9 +199,10 @@ __global__ void __launch_bounds__(kKBestThreads) kcut_best_kernel(KcutDev D, int
                                                                   int advance) {
   __shared__ int64_t sF[kKBestThreads / 64];
   __shared__ int sb[kKBestThreads / 64];
-  __shared__ int win;
+  __shared__ int win, pend;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int64_t t = *D.t_dev;
+  const int pend0 = *D.win;  // a winner the step launches have not copied yet
   const int gpw = D.grid / D.nslices;
   int64_t bestF = LLONG_MAX;
   int bestb = INT_MAX;
@@ -261,17 +270,29 @@ __global__ void __launch_bounds__(kKBestThreads) kcut_best_kernel(KcutDev D, int
       improved = 1;
     }
     win = improved ? bestb : -1;
-    if (advance) *D.t_dev = t + 1;
+    if (advance) {
+      // the next step launch copies the winner while it overwrites X[parity]
+      *D.t_dev = t + 1;
+      *D.win = win;
+    } else {
+      pend = pend0;
+      *D.win = -1;
+    }
   }
   __syncthreads();
-  if (win >= 0) {  // the winner's categories; eight nodes' K loads in flight per thread
-    const float* X = D.X[parity];
-    constexpr int U = 8;
+  // the last launch of a call copies at once: first a pending winner of the
+  // previous iteration (in the other buffer, which no step launch has
+  // overwritten yet), then its own
+  for (int pass = 0; pass < 2; ++pass) {
+    const int wb = pass == 0 ? pend : win;
+    if (advance || wb < 0) continue;
+    const float* X = D.X[pass == 0 ? parity ^ 1 : parity];
+    constexpr int U = 8;  // eight nodes' K loads in flight per thread
     for (int i0 = tid; i0 < D.n; i0 += U * kKBestThreads) {
       float v[U][K];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const float* x = X + ((size_t)min(i0 + u * kKBestThreads, D.n - 1) * D.B + win) * K;
+        const float* x = X + ((size_t)min(i0 + u * kKBestThreads, D.n - 1) * D.B + wb) * K;
 #pragma unroll
         for (int c = 0; c < K; ++c) v[u][c] = x[c];
       }
@@ -279,6 +300,7 @@ __global__ void __launch_bounds__(kKBestThreads) kcut_best_kernel(KcutDev D, int
       for (int u = 0; u < U; ++u)
         if (i0 + u * kKBestThreads < D.n) D.best_x[i0 + u * kKBestThreads] = (uint8_t)argmax_k<K>(v[u]);
     }
+    __syncthreads();  // the second copy overwrites the first
   }
 }
 
