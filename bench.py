@@ -247,6 +247,8 @@ def workload_c2(args, P):
     x0 = W.x0_uniform(2, 0, B, q.n)
     p = W.gda_params("maxcut", B=B, T=T)
     ctx = P.qubo_gda_init(q, p, x0)
+    ctx.step(T)  # warm-up run (first launch of the kernel), then the timed run from x0
+    ctx.restart(x0)
     ctx.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -283,6 +285,8 @@ def workload_c5(args, P):
     x0 = W.x0_uniform(5, 0, B, f.n)
     p = W.gda_params("maxsat", B=B, T=T, scale=s)
     ctx = P.maxsat_gda_init(f, p, x0)
+    ctx.step(T)  # warm-up run (first launch of the kernel), then the timed run from x0
+    ctx.restart(x0)
     ctx.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -454,7 +454,8 @@ PDBO_API pdbo_status pdbo_kernel_time(pdbo_ctx* ctx, int32_t which, double* tota
 PDBO_API pdbo_status pdbo_autotune_store(const char* key, int32_t cfg);
 PDBO_API pdbo_status pdbo_autotune_lookup(const char* key, int32_t* cfg);
 
-/* Name of the tile configuration the dense path uses (static string). */
+/* Name of the tile configuration the dense path uses, or of the kernel variant
+ * the restart-resident CSR path uses (static string; empty for other paths). */
 PDBO_API const char* pdbo_tile_name(const pdbo_ctx* ctx);
 
 PDBO_API void pdbo_destroy(pdbo_ctx* ctx);

@@ -1478,8 +1478,10 @@ const char* pdbo_last_error(const pdbo_ctx* ctx) { return ctx ? ctx->err.c_str()
 const char* pdbo_last_global_error(void) { return g_last_error.c_str(); }
 
 const char* pdbo_tile_name(const pdbo_ctx* ctx) {
-  if (!ctx || ctx->kind != 0) return "";
-  return dense_cfg(ctx->cfg).name;
+  if (!ctx) return "";
+  if (ctx->kind == 0) return dense_cfg(ctx->cfg).name;
+  if (ctx->kind == 1) return csr_variant_name(ctx->csr, ctx->compact);
+  return "";
 }
 
 void pdbo_destroy(pdbo_ctx* ctx) {
@@ -1598,12 +1600,13 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
     d.nnz = nnz;
     d.kos = (float)((double)C.kappa / p->scale);
     d.gp = make_gp(p);
+    int64_t cmax = 0;
+    for (int i = 0; i < n; ++i) cmax = std::max<int64_t>(cmax, C.cp[i] < 0 ? -C.cp[i] : C.cp[i]);
     {
       // a wave of the 1024-thread kernel sums at most 64 x 8 rows
-      int64_t cmax = 0;
-      for (int i = 0; i < n; ++i) cmax = std::max<int64_t>(cmax, C.cp[i] < 0 ? -C.cp[i] : C.cp[i]);
       const int64_t lim = int64_t(1) << 31;
       d.small32 = (512 * C.rowabs < lim && 512 * cmax < lim) ? 1 : 0;
+      d.tot32 = (d.small32 && (int64_t)n * C.rowabs < lim && (int64_t)n * cmax < lim) ? 1 : 0;
     }
     int32_t* rp = nullptr;
     STCHK(dalloc(c, &rp, n + 1));

@@ -280,10 +280,12 @@ struct CsrDev {
   int64_t nnz;
   int n, ld, B, kappa;
   int small32;            // 512 * max_i sum_j |Ahat_ij| and 512 * max_i |c'_i| are below 2^31
+  int tot32;              // n times each of those is below 2^31 too: a restart's totals fit int32
   float kos;
   GdaP gp;
 };
 bool csr_fits(int n, int64_t nnz, bool packed, size_t* lds_bytes);
+const char* csr_variant_name(const CsrDev& d, bool packed);
 hipError_t launch_csr_persistent(const CsrDev& d, bool packed, int64_t t0, int nsteps,
                                  hipStream_t s);
 hipError_t launch_csr_grad(const CsrDev& d, const float* X, float* G, int nb, hipStream_t s);

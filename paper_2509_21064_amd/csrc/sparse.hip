@@ -92,13 +92,25 @@ __device__ __forceinline__ void row_gather(int i, const int32_t* __restrict__ rp
   accr = r0 + r1;
 }
 
+// Sum of an int32 over lanes 0..15 (row 0 of the wave), in every lane: row
+// shifts by 1, 2, 4 and 8 leave the row's total in its lane 15.
+__device__ __forceinline__ int32_t row16_sum_i32(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
+  return __builtin_amdgcn_readlane(v, 15);
+}
+
 // DBUF: x is double-buffered in LDS (iteration t gathers from buffer t mod 2
 // and writes x^{t+1} into the other), so one barrier per iteration suffices;
 // otherwise x is updated in place between two barriers.
 // SMALL: the host has bounded every wave's partial sums of x_r^T Ahat x_r and
 // c'^T x_r below 2^31, so the wave reductions run in int32 (half the shuffles
-// of int64); the sum over waves is always taken in int64.
-template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK>
+// of int64).  TOT32 (with SMALL): the restart's totals are bounded below 2^31
+// too, so the sum over waves is taken in int32 as well (a quarter of the
+// instructions of the int64 row reduction); otherwise it is taken in int64.
+template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK, bool TOT32 = false>
 __global__ void __launch_bounds__(NT)
     csr_persistent(CsrDev D, int64_t t0, int nsteps) {
   constexpr int NW = NT / 64;
@@ -222,8 +234,15 @@ __global__ void __launch_bounds__(NT)
       // lane l of every wave takes wave (l mod 16)'s partials; a 16-lane row
       // reduction gives the totals to every lane (NW <= 16)
       const int w = lane & 15;
-      const int64_t St = row16_sum_i64(w < NW ? (int64_t)red[s & 1][w][0] : 0);
-      const int64_t Ct = row16_sum_i64(w < NW ? (int64_t)red[s & 1][w][1] : 0);
+      int64_t St, Ct;
+      if constexpr (TOT32) {
+        static_assert(SMALL, "int32 totals need int32 wave sums");
+        St = row16_sum_i32(w < NW ? (int32_t)red[s & 1][w][0] : 0);
+        Ct = row16_sum_i32(w < NW ? (int32_t)red[s & 1][w][1] : 0);
+      } else {
+        St = row16_sum_i64(w < NW ? (int64_t)red[s & 1][w][0] : 0);
+        Ct = row16_sum_i64(w < NW ? (int64_t)red[s & 1][w][1] : 0);
+      }
       const int64_t F = (D.kappa == 2 ? St : St / 2) + Ct;
       Flast = F;
       if (F < bF) {
@@ -266,9 +285,9 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK>
+template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK, bool TOT32 = false>
 static hipError_t launch_csr_k(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
-  auto kern = csr_persistent<PACKED, NT, RMAX, DBUF, SMALL, GK>;
+  auto kern = csr_persistent<PACKED, NT, RMAX, DBUF, SMALL, GK, TOT32>;
   const size_t lds = csr_lds_need(d.n, d.nnz, PACKED) + (DBUF ? align16((size_t)d.n * 4) : 0);
   hipError_t e =
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -280,6 +299,7 @@ static hipError_t launch_csr_k(const CsrDev& d, int64_t t0, int nsteps, hipStrea
 template <bool PACKED, int NT, int RMAX, int GK>
 static hipError_t launch_csr_v(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
   const bool dbuf = csr_lds_need(d.n, d.nnz, PACKED) + align16((size_t)d.n * 4) <= kLdsBudget;
+  if (dbuf && d.tot32) return launch_csr_k<PACKED, NT, RMAX, true, true, GK, true>(d, t0, nsteps, s);
   if (dbuf && d.small32) return launch_csr_k<PACKED, NT, RMAX, true, true, GK>(d, t0, nsteps, s);
   if (dbuf) return launch_csr_k<PACKED, NT, RMAX, true, false, GK>(d, t0, nsteps, s);
   if (d.small32) return launch_csr_k<PACKED, NT, RMAX, false, true, GK>(d, t0, nsteps, s);
@@ -301,6 +321,26 @@ static hipError_t launch_csr_r(const CsrDev& d, int64_t t0, int nsteps, hipStrea
   if (r2 <= 32) return launch_csr_k<PACKED, 512, 32, false, false, GK>(d, t0, nsteps, s);
   if (r2 <= 64) return launch_csr_k<PACKED, 512, 64, false, false, GK>(d, t0, nsteps, s);
   return hipErrorInvalidValue;
+}
+
+// The variant launch_csr_persistent takes for an instance, by the same rules:
+// packed (16-bit) entries in LDS or int32 arrays through L2, x double-buffered
+// or updated in place, int32 or int64 wave sums (and, double-buffered, int32
+// totals: "t32"), and beyond 8192 rows 512 threads with 32 or 64 rows each.
+const char* csr_variant_name(const CsrDev& d, bool packed) {
+  const bool pk = packed && csr_lds_need(d.n, d.nnz, true) <= kLdsBudget;
+  if ((d.n + 1023) / 1024 > 8) {
+    const bool r32 = (d.n + 511) / 512 <= 32;
+    return pk ? (r32 ? "csr_packed_rows32" : "csr_packed_rows64")
+              : (r32 ? "csr_l2_rows32" : "csr_l2_rows64");
+  }
+  const bool dbuf = csr_lds_need(d.n, d.nnz, pk) + align16((size_t)d.n * 4) <= kLdsBudget;
+  if (dbuf && d.tot32) return pk ? "csr_packed_dbuf_t32" : "csr_l2_dbuf_t32";
+  static const char* names[2][2][2] = {
+      {{"csr_l2_inplace_i64", "csr_l2_inplace_i32"}, {"csr_l2_dbuf_i64", "csr_l2_dbuf_i32"}},
+      {{"csr_packed_inplace_i64", "csr_packed_inplace_i32"},
+       {"csr_packed_dbuf_i64", "csr_packed_dbuf_i32"}}};
+  return names[pk][dbuf][d.small32 ? 1 : 0];
 }
 
 // One kernel variant per kind of g (GK): read at run time, the kind would make

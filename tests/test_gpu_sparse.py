@@ -40,20 +40,67 @@ def _big_weights(n=700, M=2100, seed=5, mag=1 << 20):
                   c=g.integers(-mag, mag, n).astype(np.int64))
 
 
-# Each case reaches a different variant of the persistent kernel:
-#   n2000        x double-buffered in LDS, packed CSR in LDS, int32 wave sums
-#   n301         one row per thread, ragged last wave
-#   wide_n900    int32 column/value arrays read through L2 (values beyond 16 bits)
-#   big_n700     int64 wave sums
-#   n8000        CSR in LDS but no room for a second x buffer: x updated in place
+def _l2_weights(n=2000, M=6000, seed=6, mag=1 << 17):
+    """Weights up to 2^17: beyond the 16-bit packed entries and too large for
+    the wide-entry kernel's int32 totals, but with int32 wave sums."""
+    base = W.maxcut_c2(rep=seed, n=n, M=M)
+    g = np.random.default_rng(seed)
+    vals = (g.integers(1, mag, size=base.vals.shape[0]) * np.sign(base.vals)).astype(np.int32)
+    return W.Qubo(n=n, row_ptr=base.row_ptr, col_idx=base.col_idx, vals=vals,
+                  c=g.integers(-mag, mag, n).astype(np.int64))
+
+
+def _hub_weights(n=2000, M=6000, seed=7, hub=70, w=32001):
+    """The C2-style graph plus one row with `hub` entries of weight w: packed
+    16-bit entries still apply and a wave's partial sums fit in 32 bits, but n
+    times the heaviest row does not, so the sum over waves runs in int64."""
+    import scipy.sparse as sp
+    base = W.maxcut_c2(rep=seed, n=n, M=M)
+    rows = np.repeat(np.arange(n), np.diff(base.row_ptr))
+    g = np.random.default_rng(seed)
+    nb = g.choice(np.arange(1, n), hub, replace=False)
+    r = np.concatenate([rows, np.zeros(hub, np.int64)])
+    c = np.concatenate([base.col_idx, nb])
+    v = np.concatenate([base.vals, np.full(hub, w)]).astype(np.int64)
+    S = sp.csr_matrix((v, (r, c)), shape=(n, n))
+    S.sum_duplicates()
+    S.sort_indices()
+    return W.Qubo(n=n, row_ptr=S.indptr.astype(np.int32), col_idx=S.indices.astype(np.int32),
+                  vals=S.data.astype(np.int32), c=g.integers(-100, 101, n).astype(np.int64))
+
+
+# Each case reaches a different variant of the persistent kernel (VARIANT):
+#   n2000        packed 16-bit entries in LDS, x double-buffered, int32 wave sums
+#                and int32 totals over the waves
+#   n301         the same, one row per thread, ragged last wave
+#   wide_n900    the same with weights up to ~1800, an asymmetric part and a diagonal
+#   n4000        the same with four rows per thread
+#   hub_n2000    packed entries, int32 wave sums, int64 totals (one heavy row)
+#   l2_n2000     int32 column/value arrays read through L2 (weights beyond 16 bits)
+#   big_n700     the same with int64 wave sums
+#   n8000        packed entries in LDS but no room for a second x buffer: x updated in place
 #   n12000       more than 8192 rows: 512 threads with 32 rows each, CSR through L2
 CASES = {
     "maxcut_n2000": (lambda: W.maxcut_c2(0), 256, 1.0),
     "maxcut_n301_ragged": (lambda: W.maxcut_c2(1, n=301, M=900), 37, 1.0),
     "wide_n900": (lambda: _wide_weights(), 20, None),
+    "maxcut_n4000_packed": (lambda: W.maxcut_c2(5, n=4000, M=8000), 24, 1.0),
+    "hub_n2000": (lambda: _hub_weights(), 16, None),
+    "l2_n2000": (lambda: _l2_weights(), 16, None),
     "big_n700": (lambda: _big_weights(), 24, None),
     "maxcut_n8000_inplace": (lambda: W.maxcut_c2(4, n=8000, M=8000), 24, 1.0),
     "maxcut_n12000_rows32": (lambda: W.maxcut_c2(3, n=12000, M=36000), 16, 1.0),
+}
+VARIANT = {
+    "maxcut_n2000": "csr_packed_dbuf_t32",
+    "maxcut_n301_ragged": "csr_packed_dbuf_t32",
+    "wide_n900": "csr_packed_dbuf_t32",
+    "maxcut_n4000_packed": "csr_packed_dbuf_t32",
+    "hub_n2000": "csr_packed_dbuf_i32",
+    "l2_n2000": "csr_l2_dbuf_i32",
+    "big_n700": "csr_l2_dbuf_i64",
+    "maxcut_n8000_inplace": "csr_packed_inplace_i32",
+    "maxcut_n12000_rows32": "csr_l2_rows32",
 }
 
 
@@ -68,8 +115,11 @@ def test_gradient_and_lockstep(name):
     X = g.random((B, q.n)).astype(np.float32)
     X[:, ::9] = 0.5
     Y = g.uniform(-2.0, 6.0, (B, q.n)).astype(np.float32)
-    p = W.gda_params("maxcut", B=B, T=1, scale=s)
+    # tile 1: the restart-resident kernel even for the few restarts of a test
+    # (automatic routing sends B < 128 to the row-parallel path)
+    p = W.gda_params("maxcut", B=B, T=1, scale=s, tile=1)
     ctx = P.qubo_gda_init(q, p, X.astype(np.float64))
+    assert ctx.tile_name == VARIANT[name]
     G64 = oq.grad_f(*oq.canonicalize(q), X.astype(np.float64), s)
     G = ctx.grad(X)
     assert normwise(G, G64) <= 1e-5
@@ -85,8 +135,8 @@ def test_gradient_and_lockstep(name):
     assert np.array_equal(ctx.objectives(), oq.objective(q, Xg > 0.5))
 
 
-@pytest.mark.parametrize("name", ["maxcut_n2000", "maxcut_n301_ragged", "maxcut_n8000_inplace",
-                                  "maxcut_n12000_rows32"])
+@pytest.mark.parametrize("name", ["maxcut_n2000", "maxcut_n301_ragged", "hub_n2000",
+                                  "maxcut_n8000_inplace", "maxcut_n12000_rows32"])
 def test_lockstep_entropy_g(name):
     """The persistent kernel's variant for the entropy g (the Max-Cut workloads
     use the quadratic one): one iteration against the oracle, with x at 0, 1/2
@@ -102,8 +152,9 @@ def test_lockstep_entropy_g(name):
     X[:, 4::13] = 0.0
     X[:, 7::17] = 1.0
     Y = g.uniform(-2.0, 6.0, (B, q.n)).astype(np.float32)
-    p = W.gda_params("maxcut", B=B, T=1, scale=s, g="entropy")
+    p = W.gda_params("maxcut", B=B, T=1, scale=s, g="entropy", tile=1)
     ctx = P.qubo_gda_init(q, p, X.astype(np.float64))
+    assert ctx.tile_name == VARIANT[name]
     ctx.set_state(X, Y, 0)
     ctx.step(1)
     Xg, Yg, t = ctx.get_state()
@@ -123,7 +174,9 @@ def test_eval_exact(name):
     P = require_gpu()
     mk, B, s = CASES[name]
     q = mk()
-    ctx = P.qubo_gda_init(q, W.gda_params("maxcut", B=B, T=1, scale=1.0), W.x0_uniform(2, 3, B, q.n))
+    ctx = P.qubo_gda_init(q, W.gda_params("maxcut", B=B, T=1, scale=1.0, tile=1),
+                          W.x0_uniform(2, 3, B, q.n))
+    assert ctx.tile_name == VARIANT[name]
     g = np.random.default_rng(4)
     xr = (g.random((B, q.n)) < 0.5).astype(np.uint8)
     assert np.array_equal(ctx.eval(xr), oq.objective(q, xr))
