@@ -316,11 +316,13 @@ def workload_c5(args, P):
     return out
 
 
-def _timed_run(ctx, T, steps_cls, P):
-    """Wall time of T iterations (HIP-event timed by the library per kernel
-    class as well), after one untimed warm-up call."""
+def _timed_run(ctx, T, steps_cls, P, warm=2):
+    """Wall time of T iterations from the starting point (HIP-event timed by
+    the library per kernel class as well), after an untimed warm-up of `warm`
+    iterations (one graph chunk records the graph) and a restart."""
     import torch
-    ctx.step(2)
+    ctx.step(warm)
+    ctx.restart(None)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -345,10 +347,13 @@ def workload_mis(args, P):
     # steps clip every coordinate to 0 at d = 100, and the regular graph never
     # breaks the symmetry; mis_scale documents the choice
     s = W.mis_scale(q)
+    # iterations replayed as hipGraphs of 50 (two short launches each) unless
+    # --graph-chunk says otherwise
+    gc = args.graph_chunk or 50
     p = W.gda_params("qubo", B=B, T=T, scale=s, alpha=0.02, beta=0.02, y0=5.0, tile=2,
-                     graph_chunk=args.graph_chunk)
+                     graph_chunk=gc)
     ctx = P.qubo_gda_init(q, p, None)
-    el = _timed_run(ctx, T, None, P)
+    el = _timed_run(ctx, T, None, P, warm=gc)
     # kernel times over a second run (timing on: launches recorded one by one)
     ctx.restart(None)
     ctx.timing(True, classes=[P.PDBO_K_STEP, P.PDBO_K_ARGMIN])
@@ -393,10 +398,11 @@ def workload_kcut(args, P):
     n, M, k, B, T = 10000, 20000, 3, 100, args.T
     g = W.kcut_graph(n, M, k, rep=0)
     G = ok.Graph(g)
+    gc = args.graph_chunk or 50  # hipGraphs of 50 iterations unless --graph-chunk says otherwise
     p = dict(B=B, T=T, alpha=0.01, beta=0.01, y0=6.0, delta=2.0 ** -7, scale=1.0, g="quad",
-             graph_chunk=args.graph_chunk, seed=1)
+             graph_chunk=gc, seed=1)
     ctx = P.kcut_gda_init(g, p, None)
-    el = _timed_run(ctx, T, None, P)
+    el = _timed_run(ctx, T, None, P, warm=gc)
     ctx.restart(None)
     ctx.timing(True, classes=[P.PDBO_K_STEP, P.PDBO_K_ARGMIN])
     ctx.step(T)
@@ -490,6 +496,7 @@ def workload_c4(args, P):
     for mode, grouped in (("grouped", 1), ("per_instance", 0)):
         ctx = P.qubo_gda_batch_init(qs, ps, x0s, grouped=grouped)
         ctx.step(max(args.warmup, 70))  # past the evaluation transient
+        ctx.step(gc)  # records the graph of the steady-state iterations
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()

@@ -1781,6 +1781,11 @@ static pdbo_status spmm_init(const CsrCanon* C, const RealCanon* R, const pdbo_p
     d.ts0 = c->ts0_d;
     Incumbent init{kI64Max, -1, -1, 0};
     HIPCHK(c, hipMemcpyAsync(d.inc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    d.win = nullptr;
+    if (C) {  // integer weights: the winner copy rides on the next step launch
+      STCHK(dalloc(c, &d.win, 1));
+      HIPCHK(c, launch_fill_i32(d.win, -1, 1, c->stream));
+    }
     if (C) {
       // qubo_gda_eval of given vectors goes through the restart-major CSR kernel
       CsrDev& e = c->csr;
@@ -2228,6 +2233,7 @@ pdbo_status qubo_gda_restart(pdbo_ctx* c, const double* x0) {
       const uint64_t top[4] = {~0ull, ~0ull, ~0ull, ~0ull >> 1};
       HIPCHK(c, hipMemcpyAsync(d.incw, top, sizeof(top), hipMemcpyHostToDevice, c->stream));
     }
+    if (d.win) HIPCHK(c, launch_fill_i32(d.win, -1, 1, c->stream));
   } else {
     float* X = c->kind == 1 ? c->csr.X : c->sat.X;
     float* Y = c->kind == 1 ? c->csr.Y : c->sat.Y;
@@ -2579,6 +2585,7 @@ pdbo_status qubo_dual_bound(pdbo_ctx* c, double ybar, int32_t iters, double* low
     HIPCHK(c, launch_cert_csr(c->csr, x0, c->par.scale, ybar, c->cert_rows, c->cert_res, c->stream));
   } else {
     SpmmDev d = c->spmm;
+    d.win = nullptr;  // no incumbent here: the step launches copy nothing
     d.B = 1;
     d.W = 1;
     d.G = 64;

@@ -312,6 +312,10 @@ struct SpmmDev {
   int64_t* Flast;         // [B] objectives of the last evaluation
   Incumbent* inc;
   uint8_t* best_x;        // [n]
+  int32_t* win;           // [1] integer weights: restart whose rounded iterate became the
+                          // incumbent and still has to be copied into best_x, or -1 (the
+                          // next step launch copies it while it overwrites that iterate,
+                          // the last best-of-B launch of a call at once); null: no deferral
   TraceRec* trace;
   int32_t* trace_len;
   int64_t* t_dev;         // completed iterations
@@ -344,7 +348,8 @@ hipError_t launch_spmm(const SpmmDev& d, int mode, int parity, float* G, hipStre
 // Objectives from the partials, first argmin over b, incumbent update for
 // evaluations of x^t with t >= 1 (label: the completed iterations), and, for
 // advance != 0, the iteration counter moves on.  The winning rounded vector
-// is read from X[parity].
+// is read from X[parity], at once or (integer weights, advance != 0) by the
+// next step launch.
 hipError_t launch_spmm_best(const SpmmDev& d, int parity, int advance, hipStream_t s);
 // float64-weight forms (realw.hip).  launch_spmm and launch_spmm_best call
 // these when d.ndig > 0.  With Fout != NULL, launch_spmm_real_best writes the

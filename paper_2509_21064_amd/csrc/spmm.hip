@@ -44,6 +44,8 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parit
   const int32_t* __restrict__ col = D.col;
   const int32_t* __restrict__ val = D.val;
   if (MODE != 2 && tid < 128) sred[tid >> 6][tid & 63] = 0;
+  // the previous iteration's new incumbent, still in Xn (see SpmmDev::win)
+  const int win = (MODE == 0 && D.win) ? *D.win : -1;
   GdaP gp = D.gp;
   gp.gkind = GK;
   long long S = 0, C = 0;
@@ -98,6 +100,7 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parit
     if constexpr (MODE == 0) {
       float xn, yn;
       gda_update(x, D.Y[off], fmaf(D.kos, acc, D.cps[i]), gp, xn, yn);
+      if (b == win) D.best_x[i] = (uint8_t)(Xn[off] > 0.5f);  // about to be overwritten
       Xn[off] = xn;
       D.Y[off] = yn;
     } else if constexpr (MODE == 2) {
@@ -147,9 +150,10 @@ __global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int 
                                                                  int advance) {
   __shared__ int64_t sF[kBestThreads / 64];
   __shared__ int sb[kBestThreads / 64];
-  __shared__ int win;
+  __shared__ int win, pend;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int64_t t = *D.t_dev;  // the evaluated iterate is x^t
+  const int pend0 = D.win ? *D.win : -1;  // a winner no step launch has copied yet
   const int gpw = D.grid / D.nslices;
   int64_t bestF = LLONG_MAX;
   int bestb = INT_MAX;
@@ -227,23 +231,38 @@ __global__ void __launch_bounds__(kBestThreads) spmm_best_kernel(SpmmDev D, int 
       improved = 1;
     }
     win = improved ? bestb : -1;
+    pend = -1;
     if (advance) *D.t_dev = t + 1;
+    if (D.win) {
+      if (advance) {  // the next step launch copies the winner while it overwrites X[parity]
+        *D.win = win;
+        win = -1;
+      } else {  // the last launch of a call: a pending winner too
+        pend = pend0;
+        *D.win = -1;
+      }
+    }
   }
   __syncthreads();
-  if (win >= 0) {  // eight strided loads in flight per thread
-    const float* X = D.X[parity];
-    constexpr int U = 8;
+  // copies made here: first a pending winner of the previous iteration (in the
+  // other buffer, which no step launch has overwritten yet), then this one's
+  for (int pass = 0; pass < 2; ++pass) {
+    const int wb = pass == 0 ? pend : win;
+    if (wb < 0) continue;
+    const float* X = D.X[pass == 0 ? parity ^ 1 : parity];
+    constexpr int U = 8;  // eight strided loads in flight per thread
     for (int i0 = tid; i0 < D.n; i0 += U * kBestThreads) {
       float v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = min(i0 + u * kBestThreads, D.n - 1);
-        v[u] = X[(size_t)i * D.B + win];
+        v[u] = X[(size_t)i * D.B + wb];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (i0 + u * kBestThreads < D.n) D.best_x[i0 + u * kBestThreads] = (uint8_t)(v[u] > 0.5f);
     }
+    __syncthreads();  // the second copy overwrites the first
   }
 }
 
