@@ -2801,6 +2801,22 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
     }
   }
   for (int i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  // Every clause is counted in the exact evaluation by one of its variables,
+  // its owner: the variable with the fewest clauses owned so far when the
+  // clause comes up, so that each variable owns about m/n of them (the
+  // evaluation work of the threads stays even).
+  std::vector<int32_t> owner(m);
+  {
+    std::vector<int32_t> owned(n, 0);
+    for (int j = 0; j < m; ++j) {
+      int best = 0;
+      for (int l = 1; l < k; ++l)
+        if (owned[codes[(size_t)j * k + l] & 0x7fffffff] < owned[codes[(size_t)j * k + best] & 0x7fffffff])
+          best = l;
+      owner[j] = best;
+      owned[codes[(size_t)j * k + best] & 0x7fffffff]++;
+    }
+  }
   std::vector<int32_t> inc((size_t)ptr[n] * k);
   std::vector<int32_t> fillp(ptr.begin(), ptr.end() - 1);
   for (int j = 0; j < m; ++j)
@@ -2811,11 +2827,11 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
       int o = 0;
       for (int l2 = 0; l2 < k; ++l2)
         if (l2 != l) inc[(size_t)e * k + o++] = codes[(size_t)j * k + l2];
-      const int32_t meta = wv[j] | ((code < 0 ? 1 : 0) << 30) | ((l == 0 ? 1 : 0) << 29);
+      const int32_t meta = wv[j] | ((code < 0 ? 1 : 0) << 30) | ((l == owner[j] ? 1 : 0) << 29);
       inc[(size_t)e * k + (k - 1)] = meta;
     }
 
-  std::vector<uint64_t> inc3, pinc3;  // host staging, alive until init syncs
+  std::vector<uint64_t> pinc3;  // host staging, alive until init syncs
   std::vector<int32_t> ord, pptr, pinc;
   pdbo_ctx* c = new pdbo_ctx();
   c->kind = 2;
@@ -2845,22 +2861,6 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
     d.inc = di;
     d.lits = dl;
     d.w = dw;
-    if (k == 3) {
-      // compact 3-SAT entries: 16-bit codes (variable | negated << 15), n <= 32768
-      inc3.resize(ptr[n]);
-      auto c16 = [](int32_t code) {
-        return (uint32_t)(code & 0x7fffffff) | ((code < 0 ? 1u : 0u) << 15);
-      };
-      for (int e = 0; e < ptr[n]; ++e) {
-        const uint32_t lo = c16(inc[(size_t)e * 3]) | (c16(inc[(size_t)e * 3 + 1]) << 16);
-        inc3[e] = (uint64_t)lo | ((uint64_t)(uint32_t)inc[(size_t)e * 3 + 2] << 32);
-      }
-      uint64_t* d3 = nullptr;
-      STCHK(dalloc(c, &d3, inc3.size()));
-      HIPCHK(c, hipMemcpyAsync(d3, inc3.data(), inc3.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
-                               c->stream));
-      d.inc3 = d3;
-    }
     // position space of the persistent kernel: variables by decreasing
     // occurrence count, their lists with the other literals' codes renamed
     // to positions
@@ -2895,13 +2895,21 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
     d.pinc_ptr = dpp;
     d.pinc = dpi;
     if (k == 3) {
+      // compact 8-byte entries (16-bit codes: position | negated << 15,
+      // n <= 32768), each position's owned clauses first
       pinc3.resize(pptr[n]);
       auto c16 = [](int32_t code) {
         return (uint32_t)(code & 0x7fffffff) | ((code < 0 ? 1u : 0u) << 15);
       };
-      for (int e = 0; e < pptr[n]; ++e) {
-        const uint32_t lo = c16(pinc[(size_t)e * 3]) | (c16(pinc[(size_t)e * 3 + 1]) << 16);
-        pinc3[e] = (uint64_t)lo | ((uint64_t)(uint32_t)pinc[(size_t)e * 3 + 2] << 32);
+      for (int q = 0; q < n; ++q) {
+        int f = pptr[q];
+        for (int pass = 0; pass < 2; ++pass)
+          for (int e = pptr[q]; e < pptr[q + 1]; ++e) {
+            const int32_t meta = pinc[(size_t)e * 3 + 2];
+            if ((((meta >> 29) & 1) != 0) != (pass == 0)) continue;
+            const uint32_t lo = c16(pinc[(size_t)e * 3]) | (c16(pinc[(size_t)e * 3 + 1]) << 16);
+            pinc3[f++] = (uint64_t)lo | ((uint64_t)(uint32_t)meta << 32);
+          }
       }
       uint64_t* d3 = nullptr;
       STCHK(dalloc(c, &d3, pinc3.size()));

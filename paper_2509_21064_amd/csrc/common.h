@@ -424,7 +424,6 @@ hipError_t launch_restart_best(const int64_t* rbestF, const int64_t* rbestT,
 struct SatDev {
   const int32_t* inc_ptr;   // [n+1] per-variable incidence ranges
   const int32_t* inc;       // entries of k int32: (k-1) other literal codes, then meta
-  const uint64_t* inc3;     // 3-SAT only: the same entries as (code | code << 16) | meta << 32
   const int32_t* lits;      // [m][k] literal codes (var | neg<<31)
   const int32_t* w;         // [m]
   float* X;                 // [B][ld]
@@ -441,7 +440,10 @@ struct SatDev {
   const int32_t* order;     // [n] variable at position p
   const int32_t* pinc_ptr;  // [n+1]
   const int32_t* pinc;      // as inc, codes in positions
-  const uint64_t* pinc3;    // as inc3, codes in positions
+  // 3-SAT: the entries in 8 bytes, the two other literals as 16-bit codes
+  // (position | negated << 15) in the low word, the meta word in the high
+  // word; each position's list starts with the clauses it owns
+  const uint64_t* pinc3;
   int n, m, k, ld, B;
   float ios;                // 1/s
   GdaP gp;

@@ -7,12 +7,13 @@
 // variable-major: every variable owns the list of its occurrences, each entry
 // carrying the codes of the clause's other literals and a meta word, so the
 // gradient is a deterministic gather with no atomics.  The meta word holds the
-// weight (bits 0-23), "this literal is negated" (bit 30) and "this is the first
-// literal of its clause" (bit 29); the exact weighted unsatisfied count of
-// round(x) is fused into the same pass by counting each clause at its first
-// literal.  Literal codes are (variable index) | (negated << 31); for 3-SAT the
-// persistent kernel reads a compact 8-byte copy of each entry (two 16-bit codes
-// and the meta word).
+// weight (bits 0-23), "this literal is negated" (bit 30) and "this variable
+// owns the clause" (bit 29; the host spreads the clauses so that every variable
+// owns about m/n of them); the exact weighted unsatisfied count of round(x) is
+// fused into the same pass by counting each clause at its owner.  Literal codes
+// are (variable index) | (negated << 31).  For 3-SAT the persistent kernel
+// reads a compact 8-byte copy of each entry (two 16-bit codes and the meta
+// word), a variable's owned clauses first.
 #include <climits>
 
 #include "common.h"
@@ -32,7 +33,7 @@ bool sat_fits(int n, size_t* lds_bytes) {
 }
 
 // Sum over the occurrences of variable i of the adjoint terms; also the
-// weighted count of clauses first-listed at i whose literals are all false.
+// weighted count of the clauses i owns whose literals are all false.
 __device__ __forceinline__ float sat_adjoint(const SatDev& D, const float* __restrict__ xsrc,
                                              int i, float xi, bool want_eval, int64_t& unsat) {
   const int k = D.k;
@@ -61,13 +62,14 @@ __device__ __forceinline__ float sat_adjoint(const SatDev& D, const float* __res
 }
 
 // 3-SAT occurrence entry in 8 bytes: the other two literals as 16-bit codes
-// (variable | negated << 15) in the low word, the meta word in the high word.
-__device__ __forceinline__ void sat3_term(uint64_t en, const float* __restrict__ xs, bool own_true,
+// (position | negated << 15) in the low word, the meta word in the high word.
+// Each position's list starts with the clauses it owns, so the count of
+// unsatisfied clauses (taken at the owner) is skipped by whole waves in the
+// later rounds of a list.
+__device__ __forceinline__ void sat3_term(uint64_t en, float xa, float xb, bool own_true,
                                           bool want_eval, float& g, int64_t& unsat) {
   const uint32_t codes = (uint32_t)en;
-  const uint32_t ca = codes & 0xffffu, cb = codes >> 16;
-  const float xa = xs[ca & 0x7fffu], xb = xs[cb & 0x7fffu];
-  const bool na = (ca >> 15) != 0, nb = (cb >> 15) != 0;
+  const bool na = (codes >> 15) & 1u, nb = (codes >> 31) != 0;
   const float prod = (na ? xa : 1.f - xa) * (nb ? xb : 1.f - xb);
   const int32_t meta = (int32_t)(en >> 32);
   const float w = (float)(meta & 0xffffff);
@@ -78,24 +80,35 @@ __device__ __forceinline__ void sat3_term(uint64_t en, const float* __restrict__
     unsat += (meta & 0xffffff);
 }
 
+// Adjoint of position i from its compact list, four entries per round: their
+// loads first, then their eight gathers, then the arithmetic.
 __device__ __forceinline__ float sat3_adjoint(const SatDev& D, const float* __restrict__ xs, int i,
                                               float xi, bool want_eval, int64_t& unsat) {
   const __attribute__((address_space(1))) uint64_t* E =
-      (const __attribute__((address_space(1))) uint64_t*)D.inc3;
-  const int pe = D.inc_ptr[i + 1];
-  int e = D.inc_ptr[i];
+      (const __attribute__((address_space(1))) uint64_t*)D.pinc3;
+  const int pe = D.pinc_ptr[i + 1];
+  int e = D.pinc_ptr[i];
   const bool own_true = xi > 0.5f;
-  // four entries per round, so that their loads and gathers are in flight together
-  float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+  float g[4] = {0.f, 0.f, 0.f, 0.f};
   for (; e + 4 <= pe; e += 4) {
-    const uint64_t a = E[e], b = E[e + 1], c = E[e + 2], d = E[e + 3];
-    sat3_term(a, xs, own_true, want_eval, g0, unsat);
-    sat3_term(b, xs, own_true, want_eval, g1, unsat);
-    sat3_term(c, xs, own_true, want_eval, g2, unsat);
-    sat3_term(d, xs, own_true, want_eval, g3, unsat);
+    uint64_t en[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) en[u] = E[e + u];
+    float xa[4], xb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xa[u] = xs[(uint32_t)en[u] & 0x7fffu];
+      xb[u] = xs[((uint32_t)en[u] >> 16) & 0x7fffu];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sat3_term(en[u], xa[u], xb[u], own_true, want_eval, g[u], unsat);
   }
-  for (; e < pe; ++e) sat3_term(E[e], xs, own_true, want_eval, g0, unsat);
-  return (g0 + g1) + (g2 + g3);
+  for (; e < pe; ++e) {
+    const uint64_t en = E[e];
+    sat3_term(en, xs[(uint32_t)en & 0x7fffu], xs[((uint32_t)en >> 16) & 0x7fffu], own_true, want_eval,
+              g[0], unsat);
+  }
+  return (g[0] + g[1]) + (g[2] + g[3]);
 }
 
 // YLDS: y lives in LDS beside x (both n floats), read and written in place by
@@ -108,7 +121,6 @@ __global__ void __launch_bounds__(NT) sat_persistent(SatDev Dv, int64_t t0, int 
   SatDev D = Dv;
   D.inc_ptr = Dv.pinc_ptr;
   D.inc = Dv.pinc;
-  D.inc3 = Dv.pinc3;
   constexpr int NW = NT / 64;
   static_assert(NW <= 16, "the partials of at most 16 waves are summed by one row of lanes");
   extern __shared__ __attribute__((aligned(16))) float xs[];
@@ -252,9 +264,9 @@ static hipError_t launch_sat_r(const SatDev& d, int64_t t0, int nsteps, hipStrea
 hipError_t launch_sat_persistent(const SatDev& d, int64_t t0, int nsteps, hipStream_t s) {
   if (nsteps <= 0) return hipSuccess;
   if (d.gp.gkind == 0)
-    return d.inc3 ? launch_sat_r<true, 0>(d, t0, nsteps, s)
+    return d.pinc3 ? launch_sat_r<true, 0>(d, t0, nsteps, s)
                   : launch_sat_r<false, 0>(d, t0, nsteps, s);
-  return d.inc3 ? launch_sat_r<true, 1>(d, t0, nsteps, s) : launch_sat_r<false, 1>(d, t0, nsteps, s);
+  return d.pinc3 ? launch_sat_r<true, 1>(d, t0, nsteps, s) : launch_sat_r<false, 1>(d, t0, nsteps, s);
 }
 
 // ---- adjoint at given points: gradient (mode 0) or Lagrangian backward (mode 1)
