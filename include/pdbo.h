@@ -225,7 +225,17 @@ typedef struct {
  * restart-resident kernel when that kernel is asked for, or the INT8 form with
  * |Ahat_ij| > 127.  The dense
  * instance is canonicalised before any HIP call, so its range errors come back
- * on any machine.  `stream` is a hipStream_t (NULL = default). */
+ * on any machine.  `stream` is a hipStream_t (NULL = default).
+ * Dense or CSR per instance: an int32 instance with n^2 B >= 2^30, tile 0,
+ * PDBO_FP32, eval_every 1 and the vector dual, given dense with at most 10%
+ * nonzeros or as CSR with n <= 16384, is built on both paths, each timed over
+ * 8 iterations after 70, and kept on the other representation's path when that
+ * is at least 10% faster; the context is then restarted from x0 (or the
+ * generator's points), so its run is that of a context built on the chosen
+ * path.  The choice is cached with the tile configurations under a key
+ * "route/<arch>/f<format>/n<n>/B<B>/nz<nnz rounded up to 1024>/p<precision>/g<g_kind>"
+ * (0 keeps the given representation, 1 takes the other); PDBO_ROUTE=0 turns
+ * the choice off.  pdbo_tile_name tells which path runs. */
 PDBO_API pdbo_status qubo_gda_init(const pdbo_qubo* prob, const pdbo_params* par, void* stream,
                           pdbo_ctx** out);
 
@@ -454,8 +464,9 @@ PDBO_API pdbo_status pdbo_kernel_time(pdbo_ctx* ctx, int32_t which, double* tota
 PDBO_API pdbo_status pdbo_autotune_store(const char* key, int32_t cfg);
 PDBO_API pdbo_status pdbo_autotune_lookup(const char* key, int32_t* cfg);
 
-/* Name of the tile configuration the dense path uses, or of the kernel variant
- * the restart-resident CSR path uses (static string; empty for other paths). */
+/* Name of the tile configuration the dense path uses, of the kernel variant
+ * the restart-resident CSR path uses, or "csr_rows" for the row-parallel CSR
+ * path (static string; empty for the other paths). */
 PDBO_API const char* pdbo_tile_name(const pdbo_ctx* ctx);
 
 PDBO_API void pdbo_destroy(pdbo_ctx* ctx);

@@ -1481,6 +1481,7 @@ const char* pdbo_tile_name(const pdbo_ctx* ctx) {
   if (!ctx) return "";
   if (ctx->kind == 0) return dense_cfg(ctx->cfg).name;
   if (ctx->kind == 1) return csr_variant_name(ctx->csr, ctx->compact);
+  if (ctx->kind == 3) return "csr_rows";
   return "";
 }
 
@@ -1928,6 +1929,86 @@ pdbo_status rowpar_steps(pdbo_ctx* c, int nsteps, pdbo_status (*one)(pdbo_ctx*))
   return PDBO_OK;
 }
 
+// ---------------------------------------------------------------- dense or CSR per instance
+//
+// A large single instance (n^2 B >= 2^30) given with tile 0 and FP32 operands
+// may run on the path of the other representation when that is faster: a dense
+// matrix with at most 10% nonzeros on the CSR paths, a CSR matrix with
+// n <= 16384 on the dense one.  Both compute with exact integer weights and
+// FP32 iterates; only the order of the FP32 sums differs.
+// Both contexts are built and timed over 8 iterations past the dense path's
+// evaluation transient; the faster (the other only when at least 10% faster)
+// is restarted from x0 and kept.  The choice is cached beside the tile
+// configurations, under "route/<arch>/f<format>/n<n>/B<B>/nz<nnz bucket>/p<precision>/g<g kind>"
+// with 0 for the given representation and 1 for the other.  PDBO_ROUTE=0 keeps
+// the given representation.
+
+struct HostQubo {
+  pdbo_qubo q{};
+  std::vector<int32_t> vals, rp, ci;
+};
+
+// dense row-major -> CSR of the nonzero entries, rows sorted by column
+static void host_to_csr(const pdbo_qubo* in, HostQubo& h) {
+  const int n = in->n;
+  h.rp.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      const int32_t v = in->q[(size_t)i * n + j];
+      if (v) {
+        h.ci.push_back(j);
+        h.vals.push_back(v);
+      }
+    }
+    h.rp[i + 1] = (int32_t)h.ci.size();
+  }
+  h.q = *in;
+  h.q.format = PDBO_CSR;
+  h.q.q = h.vals.data();
+  h.q.row_ptr = h.rp.data();
+  h.q.col_idx = h.ci.data();
+  h.q.nnz = (int64_t)h.ci.size();
+}
+
+// CSR -> dense row-major
+static void host_to_dense(const pdbo_qubo* in, HostQubo& h) {
+  const int n = in->n;
+  h.vals.assign((size_t)n * n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int p = in->row_ptr[i]; p < in->row_ptr[i + 1]; ++p)
+      h.vals[(size_t)i * n + in->col_idx[p]] = in->q[p];
+  h.q = *in;
+  h.q.format = PDBO_DENSE;
+  h.q.q = h.vals.data();
+  h.q.row_ptr = nullptr;
+  h.q.col_idx = nullptr;
+  h.q.nnz = 0;
+}
+
+static pdbo_status init_as_given(const pdbo_qubo* prob, const pdbo_params* par, void* stream,
+                                 pdbo_ctx** out) {
+  if (prob->format == PDBO_CSR) return csr_init(prob, par, stream, out);
+  return dense_init(1, prob, par, 1, stream, out);
+}
+
+// Milliseconds of k iterations after `warm` untimed ones.
+static pdbo_status time_iterations(pdbo_ctx* c, int warm, int k, float* ms) {
+  STCHK(qubo_gda_step(c, warm));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+  pdbo_status st = e == hipSuccess ? qubo_gda_step(c, k) : PDBO_OK;
+  if (e == hipSuccess && st == PDBO_OK) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess && st == PDBO_OK) e = hipEventSynchronize(e1);
+  if (e == hipSuccess && st == PDBO_OK) e = hipEventElapsedTime(ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != PDBO_OK) return st;
+  HIPCHK(c, e);
+  return PDBO_OK;
+}
+
 pdbo_status qubo_gda_init(const pdbo_qubo* prob, const pdbo_params* par, void* stream,
                           pdbo_ctx** out) {
   if (!out) return fail(nullptr, PDBO_EINVAL, "out is NULL");
@@ -1935,8 +2016,73 @@ pdbo_status qubo_gda_init(const pdbo_qubo* prob, const pdbo_params* par, void* s
   STCHK(check_qubo(prob));
   STCHK(check_params(par, prob->n));
   if (prob->wtype == PDBO_W_F64) return real_init(prob, par, stream, out);
-  if (prob->format == PDBO_CSR) return csr_init(prob, par, stream, out);
-  return dense_init(1, prob, par, 1, stream, out);
+  const int n = prob->n;
+  const char* env = std::getenv("PDBO_ROUTE");
+  const bool may = par->tile == 0 && !(env && std::atoi(env) == 0) &&
+                   (double)n * n * par->B >= (double)(1 << 30) && par->precision == PDBO_FP32 &&
+                   par->eval_every == 1 && par->dual_kind == PDBO_DUAL_VECTOR;
+  if (!may) return init_as_given(prob, par, stream, out);
+  int64_t nnz = 0;
+  if (prob->format == PDBO_DENSE) {
+    const size_t tot = (size_t)n * n;
+    for (size_t e = 0; e < tot; ++e) nnz += prob->q[e] != 0;
+    if (nnz > (int64_t)(tot / 10)) return init_as_given(prob, par, stream, out);
+  } else {
+    nnz = prob->nnz;
+    if (n > 16384) return init_as_given(prob, par, stream, out);
+  }
+  std::string arch = "unknown";
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+  }
+  char key[256];
+  std::snprintf(key, sizeof(key), "route/%s/f%d/n%d/B%d/nz%lld/p%d/g%d", arch.c_str(), prob->format, n,
+                par->B, (long long)((nnz + 1023) / 1024 * 1024), par->precision, par->g_kind);
+  const int cached = autotune_lookup(key);
+  if (cached == 0) return init_as_given(prob, par, stream, out);
+  HostQubo h;
+  if (prob->format == PDBO_DENSE)
+    host_to_csr(prob, h);
+  else
+    host_to_dense(prob, h);
+  const std::string err0 = g_last_error;  // a refusal of the other path is no error of the call
+  if (cached == 1) {
+    if (init_as_given(&h.q, par, stream, out) == PDBO_OK) return PDBO_OK;
+    g_last_error = err0;
+    return init_as_given(prob, par, stream, out);
+  }
+  pdbo_ctx* a = nullptr;
+  STCHK(init_as_given(prob, par, stream, &a));
+  pdbo_ctx* b = nullptr;
+  if (init_as_given(&h.q, par, stream, &b) != PDBO_OK) {
+    g_last_error = err0;
+    *out = a;
+    return PDBO_OK;
+  }
+  float ma = 0.f, mb = 0.f;
+  pdbo_status st = time_iterations(a, 70, 8, &ma);
+  if (st == PDBO_OK) st = time_iterations(b, 70, 8, &mb);
+  if (st != PDBO_OK) {
+    pdbo_destroy(a);
+    pdbo_destroy(b);
+    return st;
+  }
+  const bool other = mb < 0.9f * ma;
+  (void)autotune_store(key, other ? 1 : 0);  // an unwritable cache only costs a re-measurement
+  pdbo_ctx* keep = other ? b : a;
+  pdbo_destroy(other ? a : b);
+  st = qubo_gda_restart(keep, par->x0);
+  if (st != PDBO_OK) {
+    pdbo_destroy(keep);
+    return st;
+  }
+  *out = keep;
+  return PDBO_OK;
 }
 
 pdbo_status qubo_gda_batch_init(int32_t k, const pdbo_qubo* probs, const pdbo_params* par,

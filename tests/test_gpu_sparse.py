@@ -78,6 +78,8 @@ def _hub_weights(n=2000, M=6000, seed=7, hub=70, w=32001):
 #   hub_n2000    packed entries, int32 wave sums, int64 totals (one heavy row)
 #   l2_n2000     int32 column/value arrays read through L2 (weights beyond 16 bits)
 #   big_n700     the same with int64 wave sums
+#   l2t_n2000    +-1 weights with too many entries for LDS: CSR through L2, int32
+#                wave sums and int32 totals
 #   n8000        packed entries in LDS but no room for a second x buffer: x updated in place
 #   n12000       more than 8192 rows: 512 threads with 32 rows each, CSR through L2
 CASES = {
@@ -88,6 +90,7 @@ CASES = {
     "hub_n2000": (lambda: _hub_weights(), 16, None),
     "l2_n2000": (lambda: _l2_weights(), 16, None),
     "big_n700": (lambda: _big_weights(), 24, None),
+    "l2t_n2000": (lambda: W.maxcut_c2(6, n=2000, M=30000), 20, 1.0),
     "maxcut_n8000_inplace": (lambda: W.maxcut_c2(4, n=8000, M=8000), 24, 1.0),
     "maxcut_n12000_rows32": (lambda: W.maxcut_c2(3, n=12000, M=36000), 16, 1.0),
 }
@@ -99,6 +102,7 @@ VARIANT = {
     "hub_n2000": "csr_packed_dbuf_i32",
     "l2_n2000": "csr_l2_dbuf_i32",
     "big_n700": "csr_l2_dbuf_i64",
+    "l2t_n2000": "csr_l2_dbuf_t32",
     "maxcut_n8000_inplace": "csr_packed_inplace_i32",
     "maxcut_n12000_rows32": "csr_l2_rows32",
 }
@@ -135,7 +139,7 @@ def test_gradient_and_lockstep(name):
     assert np.array_equal(ctx.objectives(), oq.objective(q, Xg > 0.5))
 
 
-@pytest.mark.parametrize("name", ["maxcut_n2000", "maxcut_n301_ragged", "hub_n2000",
+@pytest.mark.parametrize("name", ["maxcut_n2000", "maxcut_n301_ragged", "hub_n2000", "l2t_n2000",
                                   "maxcut_n8000_inplace", "maxcut_n12000_rows32"])
 def test_lockstep_entropy_g(name):
     """The persistent kernel's variant for the entropy g (the Max-Cut workloads
