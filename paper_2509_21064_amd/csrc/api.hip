@@ -2978,6 +2978,7 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
     }
 
   std::vector<uint64_t> pinc3;  // host staging, alive until init syncs
+  std::vector<int32_t> slice;
   std::vector<int32_t> ord, pptr, pinc;
   pdbo_ctx* c = new pdbo_ctx();
   c->kind = 2;
@@ -3042,26 +3043,44 @@ pdbo_status maxsat_gda_init(const pdbo_maxsat* prob, const pdbo_params* p, void*
     d.pinc = dpi;
     if (k == 3) {
       // compact 8-byte entries (16-bit codes: position | negated << 15,
-      // n <= 32768), each position's owned clauses first
-      pinc3.resize(pptr[n]);
+      // n <= 32768), each position's owned clauses first, interleaved by
+      // slices of 64 positions; a slice is as long as its longest list (its
+      // first: positions are in decreasing count order), shorter lists leave
+      // zero slots that are never read
+      const int ns = (n + 63) / 64;
+      slice.assign(ns, 0);
+      int64_t tot = 0;
+      for (int s = 0; s < ns; ++s) {
+        slice[s] = (int32_t)tot;
+        int lmax = 0;
+        for (int q = s * 64; q < std::min(n, s * 64 + 64); ++q) lmax = std::max(lmax, pptr[q + 1] - pptr[q]);
+        tot += (int64_t)64 * lmax;
+        if (tot > INT32_MAX) return fail(c, PDBO_ERANGE, "3-SAT occurrence slices exceed 2^31 entries");
+      }
+      pinc3.assign((size_t)tot, 0);
       auto c16 = [](int32_t code) {
         return (uint32_t)(code & 0x7fffffff) | ((code < 0 ? 1u : 0u) << 15);
       };
       for (int q = 0; q < n; ++q) {
-        int f = pptr[q];
+        size_t f = (size_t)slice[q / 64] + (q % 64);
         for (int pass = 0; pass < 2; ++pass)
           for (int e = pptr[q]; e < pptr[q + 1]; ++e) {
             const int32_t meta = pinc[(size_t)e * 3 + 2];
             if ((((meta >> 29) & 1) != 0) != (pass == 0)) continue;
             const uint32_t lo = c16(pinc[(size_t)e * 3]) | (c16(pinc[(size_t)e * 3 + 1]) << 16);
-            pinc3[f++] = (uint64_t)lo | ((uint64_t)(uint32_t)meta << 32);
+            pinc3[f] = (uint64_t)lo | ((uint64_t)(uint32_t)meta << 32);
+            f += 64;
           }
       }
       uint64_t* d3 = nullptr;
-      STCHK(dalloc(c, &d3, pinc3.size()));
+      int32_t* dsl = nullptr;
+      STCHK(dalloc(c, &d3, std::max<size_t>(pinc3.size(), 1)));
+      STCHK(dalloc(c, &dsl, ns));
       HIPCHK(c, hipMemcpyAsync(d3, pinc3.data(), pinc3.size() * sizeof(uint64_t),
                                hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(dsl, slice.data(), (size_t)ns * 4, hipMemcpyHostToDevice, c->stream));
       d.pinc3 = d3;
+      d.pinc3_slice = dsl;
     }
     STCHK(dalloc(c, &d.X, (size_t)B * ld));
     STCHK(dalloc(c, &d.Y, (size_t)B * ld));

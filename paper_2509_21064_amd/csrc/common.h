@@ -442,8 +442,13 @@ struct SatDev {
   const int32_t* pinc;      // as inc, codes in positions
   // 3-SAT: the entries in 8 bytes, the two other literals as 16-bit codes
   // (position | negated << 15) in the low word, the meta word in the high
-  // word; each position's list starts with the clauses it owns
+  // word; each position's list starts with the clauses it owns.  Interleaved
+  // by slices of 64 positions (the positions of one wave): entry r of
+  // position p is pinc3[pinc3_slice[p / 64] + 64 r + p % 64], so a wave's
+  // load of entry r reads 512 contiguous bytes; a position's count is
+  // pinc_ptr[p + 1] - pinc_ptr[p]
   const uint64_t* pinc3;
+  const int32_t* pinc3_slice;  // [ceil(n / 64)]
   int n, m, k, ld, B;
   float ios;                // 1/s
   GdaP gp;

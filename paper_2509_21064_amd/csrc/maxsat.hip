@@ -13,7 +13,9 @@
 // fused into the same pass by counting each clause at its owner.  Literal codes
 // are (variable index) | (negated << 31).  For 3-SAT the persistent kernel
 // reads a compact 8-byte copy of each entry (two 16-bit codes and the meta
-// word), a variable's owned clauses first.
+// word), a variable's owned clauses first, interleaved by slices of 64
+// positions so that the 64 lanes of a wave read entry r of their lists from
+// one contiguous 512-byte block.
 #include <climits>
 
 #include "common.h"
@@ -81,19 +83,20 @@ __device__ __forceinline__ void sat3_term(uint64_t en, float xa, float xb, bool 
 }
 
 // Adjoint of position i from its compact list, four entries per round: their
-// loads first, then their eight gathers, then the arithmetic.
+// loads first (each a contiguous 512-byte read of the wave's slice), then their
+// eight gathers, then the arithmetic.
 __device__ __forceinline__ float sat3_adjoint(const SatDev& D, const float* __restrict__ xs, int i,
                                               float xi, bool want_eval, int64_t& unsat) {
   const __attribute__((address_space(1))) uint64_t* E =
-      (const __attribute__((address_space(1))) uint64_t*)D.pinc3;
-  const int pe = D.pinc_ptr[i + 1];
-  int e = D.pinc_ptr[i];
+      (const __attribute__((address_space(1))) uint64_t*)D.pinc3 + D.pinc3_slice[i >> 6] + (i & 63);
+  const int len = D.pinc_ptr[i + 1] - D.pinc_ptr[i];
   const bool own_true = xi > 0.5f;
   float g[4] = {0.f, 0.f, 0.f, 0.f};
-  for (; e + 4 <= pe; e += 4) {
+  int r = 0;
+  for (; r + 4 <= len; r += 4) {
     uint64_t en[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) en[u] = E[e + u];
+    for (int u = 0; u < 4; ++u) en[u] = E[(r + u) * 64];
     float xa[4], xb[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -103,8 +106,8 @@ __device__ __forceinline__ float sat3_adjoint(const SatDev& D, const float* __re
 #pragma unroll
     for (int u = 0; u < 4; ++u) sat3_term(en[u], xa[u], xb[u], own_true, want_eval, g[u], unsat);
   }
-  for (; e < pe; ++e) {
-    const uint64_t en = E[e];
+  for (; r < len; ++r) {
+    const uint64_t en = E[r * 64];
     sat3_term(en, xs[(uint32_t)en & 0x7fffu], xs[((uint32_t)en >> 16) & 0x7fffu], own_true, want_eval,
               g[0], unsat);
   }
