@@ -274,22 +274,44 @@ hipError_t launch_sat_persistent(const SatDev& d, int64_t t0, int nsteps, hipStr
 
 // ---- adjoint at given points: gradient (mode 0) or Lagrangian backward (mode 1)
 
+// One workgroup of kAdjNT threads per restart (sixteen waves per CU).
+constexpr int kAdjNT = 1024;
 template <int MODE>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(kAdjNT)
     sat_adjoint_kernel(SatDev D, const float* __restrict__ X, int ldx, const float* __restrict__ Yv,
                        const float* __restrict__ dL, float* __restrict__ dx,
                        float* __restrict__ dy, int ldo, int use_lds) {
   extern __shared__ __attribute__((aligned(16))) float xs[];
   const int b = blockIdx.x, tid = threadIdx.x, n = D.n;
   const float* xb = X + (size_t)b * ldx;
+  const float scale = MODE == 1 ? dL[b] : 1.f;
+  if (use_lds && D.pinc3) {
+    // 3-SAT: the persistent kernel's position space and interleaved lists,
+    // x permuted into position order in LDS, results written by variable
+    for (int p = tid; p < n; p += kAdjNT) xs[p] = xb[D.order[p]];
+    __syncthreads();
+    for (int p = tid; p < n; p += kAdjNT) {
+      int64_t unused = 0;
+      const int i = D.order[p];
+      const float xi = xs[p];
+      const float g = sat3_adjoint(D, xs, p, xi, false, unused) * D.ios;
+      if (MODE == 0) {
+        dx[(size_t)b * ldo + i] = g;
+      } else {
+        const float yi = Yv[(size_t)b * ldx + i];
+        dx[(size_t)b * ldo + i] = scale * fmaf(yi, g_deriv(xi, D.gp.gkind, D.gp.deg), g);
+        dy[(size_t)b * ldo + i] = scale * g_value(xi, D.gp.gkind, D.gp.deg);
+      }
+    }
+    return;
+  }
   const float* src = xb;
   if (use_lds) {
-    for (int i = tid; i < n; i += 512) xs[i] = xb[i];
+    for (int i = tid; i < n; i += kAdjNT) xs[i] = xb[i];
     __syncthreads();
     src = xs;
   }
-  const float scale = MODE == 1 ? dL[b] : 1.f;
-  for (int i = tid; i < n; i += 512) {
+  for (int i = tid; i < n; i += kAdjNT) {
     int64_t unused = 0;
     const float xi = src[i];
     const float g = sat_adjoint(D, src, i, xi, false, unused) * D.ios;
@@ -315,13 +337,13 @@ static hipError_t launch_adjoint(int mode, const SatDev& d, const float* X, int 
     e = hipFuncSetAttribute((const void*)sat_adjoint_kernel<0>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sat_adjoint_kernel<0>, dim3(nb), dim3(512), lds, s, d, X, ldx, Y, dL, dx,
+    hipLaunchKernelGGL(sat_adjoint_kernel<0>, dim3(nb), dim3(kAdjNT), lds, s, d, X, ldx, Y, dL, dx,
                        dy, ldo, use_lds);
   } else {
     e = hipFuncSetAttribute((const void*)sat_adjoint_kernel<1>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sat_adjoint_kernel<1>, dim3(nb), dim3(512), lds, s, d, X, ldx, Y, dL, dx,
+    hipLaunchKernelGGL(sat_adjoint_kernel<1>, dim3(nb), dim3(kAdjNT), lds, s, d, X, ldx, Y, dL, dx,
                        dy, ldo, use_lds);
   }
   return hipGetLastError();
@@ -339,34 +361,54 @@ hipError_t launch_sat_bwd(const SatDev& d, const float* x, const float* y, const
 
 // ---- clause-major passes: Lagrangian value and exact unsatisfied weight ----
 
-__global__ void __launch_bounds__(256)
+// One workgroup of kFwdNT threads per restart; x of the restart is staged in
+// LDS (use_lds) for the clauses' gathers.
+constexpr int kFwdNT = 1024;
+__global__ void __launch_bounds__(kFwdNT)
     sat_fwd_kernel(SatDev D, const float* __restrict__ x, const float* __restrict__ y,
-                   float* __restrict__ L) {
-  __shared__ double red[4];
+                   float* __restrict__ L, int use_lds) {
+  extern __shared__ __attribute__((aligned(16))) float xs[];
+  __shared__ double red[kFwdNT / 64];
   const int b = blockIdx.x, tid = threadIdx.x;
   const float* xb = x + (size_t)b * D.n;
   const float* yb = y + (size_t)b * D.n;
+  const float* src = xb;
+  if (use_lds) {
+    for (int i = tid; i < D.n; i += kFwdNT) xs[i] = xb[i];
+    __syncthreads();
+    src = xs;
+  }
   double acc = 0.0;
-  for (int j = tid; j < D.m; j += 256) {
+  for (int j = tid; j < D.m; j += kFwdNT) {
     float prod = 1.f;
     for (int l = 0; l < D.k; ++l) {
       const int32_t code = D.lits[(size_t)j * D.k + l];
-      const float xv = xb[code & 0x7fffffff];
+      const float xv = src[code & 0x7fffffff];
       prod *= code < 0 ? xv : 1.f - xv;
     }
     acc += (double)D.w[j] * (double)prod * (double)D.ios;
   }
-  for (int i = tid; i < D.n; i += 256) acc += (double)yb[i] * (double)g_value(xb[i], D.gp.gkind, D.gp.deg);
+  for (int i = tid; i < D.n; i += kFwdNT) acc += (double)yb[i] * (double)g_value(xb[i], D.gp.gkind, D.gp.deg);
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();
-  if (tid == 0) L[b] = (float)(red[0] + red[1] + red[2] + red[3]);
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < kFwdNT / 64; ++w) tot += red[w];
+    L[b] = (float)tot;
+  }
 }
 
 hipError_t launch_sat_fwd(const SatDev& d, const float* x, const float* y, int nb, float* L,
                           hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sat_fwd_kernel, dim3(nb), dim3(256), 0, s, d, x, y, L);
+  size_t lds = 0;
+  const int use_lds = sat_fits(d.n, &lds) ? 1 : 0;
+  if (!use_lds) lds = 0;
+  hipError_t e = hipFuncSetAttribute((const void*)sat_fwd_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sat_fwd_kernel, dim3(nb), dim3(kFwdNT), lds, s, d, x, y, L, use_lds);
   return hipGetLastError();
 }
 
