@@ -1625,7 +1625,8 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
     HIPCHK(c, hipMemcpyAsync(ord, order.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
     d.order = ord;
     // host staging lives until the stream is synchronised at the end of init
-    std::vector<uint32_t> pk;
+    std::vector<uint32_t> pk, psl;
+    std::vector<int32_t> slo;
     int32_t* col = nullptr;
     int32_t* val = nullptr;
     STCHK(dalloc(c, &col, nnz));
@@ -1642,6 +1643,39 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
       STCHK(dalloc(c, &dp, nnz));
       HIPCHK(c, hipMemcpyAsync(dp, pk.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
       d.packed = dp;
+    }
+    if (compact && n <= 8192) {
+      // the interleaved layout of the 1024-thread kernels (slices of 64
+      // positions, each as long as its longest row), used when it takes no
+      // more LDS than row_ptr and the entries in CSR order
+      const int ns = (n + 63) / 64;
+      slo.assign(ns, 0);
+      int64_t tot = 0;
+      for (int s = 0; s < ns; ++s) {
+        slo[s] = (int32_t)tot;
+        int lmax = 0;
+        for (int q = s * 64; q < std::min(n, s * 64 + 64); ++q)
+          lmax = std::max(lmax, (int)(C.rp[order[q] + 1] - C.rp[order[q]]));
+        tot += (int64_t)64 * lmax;
+      }
+      auto a16 = [](int64_t v) { return (v + 15) / 16 * 16; };
+      if (a16(4 * tot) <= a16(4 * (int64_t)(n + 1)) + a16(4 * nnz)) {
+        psl.assign((size_t)tot, 0u);
+        for (int q = 0; q < n; ++q) {
+          const int i = order[q];
+          size_t f = (size_t)slo[q / 64] + (q % 64);
+          for (int64_t e = C.rp[i]; e < C.rp[i + 1]; ++e, f += 64) psl[f] = pk[e];
+        }
+        uint32_t* dsl = nullptr;
+        int32_t* dso = nullptr;
+        STCHK(dalloc(c, &dsl, std::max<int64_t>(tot, 1)));
+        STCHK(dalloc(c, &dso, ns));
+        HIPCHK(c, hipMemcpyAsync(dsl, psl.data(), (size_t)tot * 4, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(dso, slo.data(), (size_t)ns * 4, hipMemcpyHostToDevice, c->stream));
+        d.psl = dsl;
+        d.slice = dso;
+        d.nsl = tot;
+      }
     }
     std::vector<float> hcps(ld, 0.f);
     std::vector<int64_t> hcp(ld, 0);

@@ -277,6 +277,14 @@ struct CsrDev {
   int64_t* Flast;         // [B]
   const int32_t* order;   // [n] rows by decreasing degree: thread t of the
                           // persistent kernel owns rows order[t + j * threads]
+  // the packed entries interleaved by slices of 64 positions (the rows
+  // order[q] of one wave round): entry r of row order[q] is
+  // psl[slice[q / 64] + 64 r + q % 64], so a wave's LDS reads of entry r hit
+  // consecutive words; null when the layout is not used (1024-thread packed
+  // kernels only, and only when it takes no more LDS than row_ptr + entries)
+  const uint32_t* psl;
+  const int32_t* slice;   // [ceil(n / 64)]
+  int64_t nsl;            // words of psl
   int64_t nnz;
   int n, ld, B, kappa;
   int small32;            // 512 * max_i sum_j |Ahat_ij| and 512 * max_i |c'_i| are below 2^31

@@ -92,6 +92,43 @@ __device__ __forceinline__ void row_gather(int i, const int32_t* __restrict__ rp
   accr = r0 + r1;
 }
 
+// The same sums over a row of the interleaved layout: entry r at
+// ent[base + 64 r], accumulated in the same order as row_gather.
+__device__ __forceinline__ void row_gather_sl(int base, int len, const uint32_t* __restrict__ ent,
+                                              const float* __restrict__ xs, float& acc, int& accr) {
+  const uint32_t* e0 = ent + base;
+  float a0 = 0.f, a1 = 0.f;
+  int r0 = 0, r1 = 0;
+  int p = 0;
+  for (; p + 4 <= len; p += 4) {
+    int c[4], v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t e = e0[(p + u) * 64];
+      c[u] = (int)(e & 0xffffu);
+      v[u] = (int)(int16_t)(e >> 16);
+    }
+    float xk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xk[u] = xs[c[u]];
+    a0 = fmaf((float)v[0], xk[0], a0);
+    a1 = fmaf((float)v[1], xk[1], a1);
+    a0 = fmaf((float)v[2], xk[2], a0);
+    a1 = fmaf((float)v[3], xk[3], a1);
+    r0 += (xk[0] > 0.5f ? v[0] : 0) + (xk[2] > 0.5f ? v[2] : 0);
+    r1 += (xk[1] > 0.5f ? v[1] : 0) + (xk[3] > 0.5f ? v[3] : 0);
+  }
+  for (; p < len; ++p) {
+    const uint32_t e = e0[p * 64];
+    const int c = (int)(e & 0xffffu), v = (int)(int16_t)(e >> 16);
+    const float xk = xs[c];
+    a0 = fmaf((float)v, xk, a0);
+    r0 += xk > 0.5f ? v : 0;
+  }
+  acc = a0 + a1;
+  accr = r0 + r1;
+}
+
 // Sum of an int32 over lanes 0..15 (row 0 of the wave), in every lane: row
 // shifts by 1, 2, 4 and 8 leave the row's total in its lane 15.
 __device__ __forceinline__ int32_t row16_sum_i32(int32_t v) {
@@ -110,9 +147,14 @@ __device__ __forceinline__ int32_t row16_sum_i32(int32_t v) {
 // of int64).  TOT32 (with SMALL): the restart's totals are bounded below 2^31
 // too, so the sum over waves is taken in int32 as well (a quarter of the
 // instructions of the int64 row reduction); otherwise it is taken in int64.
-template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK, bool TOT32 = false>
+// SL (with PACKED): the entries are staged in the interleaved layout (psl)
+// instead of row_ptr + CSR order; each row's start and length stay in
+// registers.
+template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK, bool TOT32 = false,
+          bool SL = false>
 __global__ void __launch_bounds__(NT)
     csr_persistent(CsrDev D, int64_t t0, int nsteps) {
+  static_assert(!SL || PACKED, "the interleaved layout holds packed entries");
   constexpr int NW = NT / 64;
   static_assert(NW <= 16, "the partials of at most 16 waves are summed by one row of lanes");
   using Part = typename std::conditional<SMALL, int32_t, int64_t>::type;
@@ -125,7 +167,12 @@ __global__ void __launch_bounds__(NT)
   const int32_t* rp = D.row_ptr;
   const uint32_t* ent = D.packed;
   const size_t xbytes = align16((size_t)n * 4) * (DBUF ? 2 : 1);
-  if constexpr (PACKED) {
+  if constexpr (SL) {
+    uint32_t* entl = (uint32_t*)(lds + xbytes);
+    const int nsl = (int)D.nsl;
+    for (int q = tid; q < nsl; q += NT) entl[q] = D.psl[q];
+    ent = entl;
+  } else if constexpr (PACKED) {
     int32_t* rpl = (int32_t*)(lds + xbytes);
     uint32_t* entl = (uint32_t*)((uint8_t*)rpl + align16((size_t)(n + 1) * 4));
     const int nnz = (int)D.nnz;
@@ -147,6 +194,15 @@ __global__ void __launch_bounds__(NT)
   int rows[RMAX];
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) rows[j] = tid + j * NT < n ? D.order[tid + j * NT] : -1;
+  int rbase[SL ? RMAX : 1], rlen[SL ? RMAX : 1];
+  if constexpr (SL) {
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+      const int q = tid + j * NT, i = rows[j];
+      rbase[j] = i >= 0 ? D.slice[q >> 6] + (q & 63) : 0;
+      rlen[j] = i >= 0 ? D.row_ptr[i + 1] - D.row_ptr[i] : 0;
+    }
+  }
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
     const int i = rows[j];
@@ -185,7 +241,10 @@ __global__ void __launch_bounds__(NT)
       if (i >= 0) {
         float acc;
         int accr;
-        row_gather<PACKED>(i, rp, ent, col, val, xcur, acc, accr);
+        if constexpr (SL)
+          row_gather_sl(rbase[j], rlen[j], ent, xcur, acc, accr);
+        else
+          row_gather<PACKED>(i, rp, ent, col, val, xcur, acc, accr);
         if (ev && xr[j] > 0.5f) {
           S += (Part)accr;
           if constexpr (CREG)
@@ -285,10 +344,18 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK, bool TOT32 = false>
+// LDS of the interleaved layout: x and the entries (the host builds it only
+// when this is no more than csr_lds_need with packed entries).
+static size_t csr_lds_need_sl(const CsrDev& d) {
+  return align16((size_t)d.n * 4) + align16((size_t)d.nsl * 4);
+}
+
+template <bool PACKED, int NT, int RMAX, bool DBUF, bool SMALL, int GK, bool TOT32 = false,
+          bool SL = false>
 static hipError_t launch_csr_k(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
-  auto kern = csr_persistent<PACKED, NT, RMAX, DBUF, SMALL, GK, TOT32>;
-  const size_t lds = csr_lds_need(d.n, d.nnz, PACKED) + (DBUF ? align16((size_t)d.n * 4) : 0);
+  auto kern = csr_persistent<PACKED, NT, RMAX, DBUF, SMALL, GK, TOT32, SL>;
+  const size_t lds = (SL ? csr_lds_need_sl(d) : csr_lds_need(d.n, d.nnz, PACKED)) +
+                     (DBUF ? align16((size_t)d.n * 4) : 0);
   hipError_t e =
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -296,14 +363,23 @@ static hipError_t launch_csr_k(const CsrDev& d, int64_t t0, int nsteps, hipStrea
   return hipGetLastError();
 }
 
+template <bool PACKED, int NT, int RMAX, int GK, bool SL>
+static hipError_t launch_csr_v2(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
+  const bool dbuf = csr_lds_need(d.n, d.nnz, PACKED) + align16((size_t)d.n * 4) <= kLdsBudget;
+  if (dbuf && d.tot32)
+    return launch_csr_k<PACKED, NT, RMAX, true, true, GK, true, SL>(d, t0, nsteps, s);
+  if (dbuf && d.small32)
+    return launch_csr_k<PACKED, NT, RMAX, true, true, GK, false, SL>(d, t0, nsteps, s);
+  if (dbuf) return launch_csr_k<PACKED, NT, RMAX, true, false, GK, false, SL>(d, t0, nsteps, s);
+  if (d.small32) return launch_csr_k<PACKED, NT, RMAX, false, true, GK, false, SL>(d, t0, nsteps, s);
+  return launch_csr_k<PACKED, NT, RMAX, false, false, GK, false, SL>(d, t0, nsteps, s);
+}
+
 template <bool PACKED, int NT, int RMAX, int GK>
 static hipError_t launch_csr_v(const CsrDev& d, int64_t t0, int nsteps, hipStream_t s) {
-  const bool dbuf = csr_lds_need(d.n, d.nnz, PACKED) + align16((size_t)d.n * 4) <= kLdsBudget;
-  if (dbuf && d.tot32) return launch_csr_k<PACKED, NT, RMAX, true, true, GK, true>(d, t0, nsteps, s);
-  if (dbuf && d.small32) return launch_csr_k<PACKED, NT, RMAX, true, true, GK>(d, t0, nsteps, s);
-  if (dbuf) return launch_csr_k<PACKED, NT, RMAX, true, false, GK>(d, t0, nsteps, s);
-  if (d.small32) return launch_csr_k<PACKED, NT, RMAX, false, true, GK>(d, t0, nsteps, s);
-  return launch_csr_k<PACKED, NT, RMAX, false, false, GK>(d, t0, nsteps, s);
+  if constexpr (PACKED)
+    if (d.psl) return launch_csr_v2<true, NT, RMAX, GK, true>(d, t0, nsteps, s);
+  return launch_csr_v2<PACKED, NT, RMAX, GK, false>(d, t0, nsteps, s);
 }
 
 // 1024 threads per restart (sixteen waves keep enough LDS gathers in flight)
@@ -335,12 +411,15 @@ const char* csr_variant_name(const CsrDev& d, bool packed) {
               : (r32 ? "csr_l2_rows32" : "csr_l2_rows64");
   }
   const bool dbuf = csr_lds_need(d.n, d.nnz, pk) + align16((size_t)d.n * 4) <= kLdsBudget;
-  if (dbuf && d.tot32) return pk ? "csr_packed_dbuf_t32" : "csr_l2_dbuf_t32";
-  static const char* names[2][2][2] = {
+  const bool sl = pk && d.psl;
+  if (dbuf && d.tot32) return sl ? "csr_sliced_dbuf_t32" : pk ? "csr_packed_dbuf_t32" : "csr_l2_dbuf_t32";
+  static const char* names[3][2][2] = {
       {{"csr_l2_inplace_i64", "csr_l2_inplace_i32"}, {"csr_l2_dbuf_i64", "csr_l2_dbuf_i32"}},
       {{"csr_packed_inplace_i64", "csr_packed_inplace_i32"},
-       {"csr_packed_dbuf_i64", "csr_packed_dbuf_i32"}}};
-  return names[pk][dbuf][d.small32 ? 1 : 0];
+       {"csr_packed_dbuf_i64", "csr_packed_dbuf_i32"}},
+      {{"csr_sliced_inplace_i64", "csr_sliced_inplace_i32"},
+       {"csr_sliced_dbuf_i64", "csr_sliced_dbuf_i32"}}};
+  return names[sl ? 2 : pk ? 1 : 0][dbuf][d.small32 ? 1 : 0];
 }
 
 // One kernel variant per kind of g (GK): read at run time, the kind would make

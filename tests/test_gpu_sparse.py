@@ -70,17 +70,20 @@ def _hub_weights(n=2000, M=6000, seed=7, hub=70, w=32001):
 
 
 # Each case reaches a different variant of the persistent kernel (VARIANT):
-#   n2000        packed 16-bit entries in LDS, x double-buffered, int32 wave sums
-#                and int32 totals over the waves
-#   n301         the same, one row per thread, ragged last wave
-#   wide_n900    the same with weights up to ~1800, an asymmetric part and a diagonal
-#   n4000        the same with four rows per thread
-#   hub_n2000    packed entries, int32 wave sums, int64 totals (one heavy row)
+#   n2000        packed 16-bit entries in LDS, interleaved by slices of 64 rows
+#                (a wave's reads of entry r hit consecutive words), x
+#                double-buffered, int32 wave sums and int32 totals over the waves
+#   n301         the same in CSR order (the slices' padding would take more LDS
+#                than row_ptr), one row per thread, ragged last wave
+#   wide_n900    interleaved, with weights up to ~1800, an asymmetric part and a diagonal
+#   n4000        interleaved, four rows per thread
+#   hub_n2000    packed entries in CSR order (one heavy row), int32 wave sums, int64 totals
 #   l2_n2000     int32 column/value arrays read through L2 (weights beyond 16 bits)
 #   big_n700     the same with int64 wave sums
 #   l2t_n2000    +-1 weights with too many entries for LDS: CSR through L2, int32
 #                wave sums and int32 totals
-#   n8000        packed entries in LDS but no room for a second x buffer: x updated in place
+#   n8000        interleaved packed entries in LDS, no room for a second x buffer
+#                (by the CSR-order size): x updated in place
 #   n12000       more than 8192 rows: 512 threads with 32 rows each, CSR through L2
 CASES = {
     "maxcut_n2000": (lambda: W.maxcut_c2(0), 256, 1.0),
@@ -95,15 +98,15 @@ CASES = {
     "maxcut_n12000_rows32": (lambda: W.maxcut_c2(3, n=12000, M=36000), 16, 1.0),
 }
 VARIANT = {
-    "maxcut_n2000": "csr_packed_dbuf_t32",
+    "maxcut_n2000": "csr_sliced_dbuf_t32",
     "maxcut_n301_ragged": "csr_packed_dbuf_t32",
-    "wide_n900": "csr_packed_dbuf_t32",
-    "maxcut_n4000_packed": "csr_packed_dbuf_t32",
+    "wide_n900": "csr_sliced_dbuf_t32",
+    "maxcut_n4000_packed": "csr_sliced_dbuf_t32",
     "hub_n2000": "csr_packed_dbuf_i32",
     "l2_n2000": "csr_l2_dbuf_i32",
     "big_n700": "csr_l2_dbuf_i64",
     "l2t_n2000": "csr_l2_dbuf_t32",
-    "maxcut_n8000_inplace": "csr_packed_inplace_i32",
+    "maxcut_n8000_inplace": "csr_sliced_inplace_i32",
     "maxcut_n12000_rows32": "csr_l2_rows32",
 }
 
