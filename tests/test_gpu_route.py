@@ -78,14 +78,17 @@ def test_sparse_dense_matrix_runs_on_csr(cache, monkeypatch):
     _same(again, direct)
 
 
-def test_dense_csr_matrix_runs_dense(cache, monkeypatch):
+@pytest.mark.parametrize("gc", [0, 8])
+def test_dense_csr_matrix_runs_dense(cache, monkeypatch, gc):
     """A QUBO with two thirds of its entries nonzero handed over as CSR: the
-    dense path takes it.  x0 NULL: the generator's points of the seed."""
+    dense path takes it.  x0 NULL: the generator's points of the seed.  With
+    hipGraph chunks the timing iterations record a graph before the restart,
+    and the replays after it must still match a fresh context."""
     P = require_gpu()
     q = W.random_dense_qubo(N, -1, 1, np.random.default_rng(11))
     csr = _csr_of(q.Q, q.c)
-    p = W.gda_params("maxcut", B=B, T=T, precision="fp32", seed=77)
-    say("route csr->dense", N, B, csr.col_idx.size)
+    p = W.gda_params("maxcut", B=B, T=T, precision="fp32", seed=77, graph_chunk=gc)
+    say("route csr->dense", N, B, csr.col_idx.size, "graph_chunk", gc)
     routed = _run(P, csr, p, None)
     assert not routed[0].startswith("csr") and routed[0], routed[0]
     assert list(_route_keys(cache).values()) == [1]
