@@ -163,7 +163,11 @@ typedef struct {
  *              iterations, x in LDS; n <= 32768, quadratic or entropy g),
  *              PDBO_CSR_ROWS (one launch per iteration over all rows, the
  *              restarts of a row in adjacent lanes; any n, any g), or
- *              PDBO_CSR_AUTO (resident when it fits and B >= 128).
+ *              PDBO_CSR_AUTO (resident when it fits and B >= 128).  With
+ *              n <= 8192 the resident kernel stages its packed entries
+ *              interleaved by slices of 64 rows when that takes no more LDS
+ *              than CSR order (same sums in the same order, so the same
+ *              results); PDBO_CSR_SLICED=0 keeps CSR order.
  *   graph_chunk  dense and row-parallel CSR paths: 0 = eager launches;
  *              K > 0 (even) = capture K iterations in one hipGraph and replay it.
  *   g_degree   d of PDBO_G_POLY, in [1, 16]; ignored for the other kinds.

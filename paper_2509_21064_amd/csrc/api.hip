@@ -1644,7 +1644,8 @@ static pdbo_status csr_init(const pdbo_qubo* q, const pdbo_params* p, void* stre
       HIPCHK(c, hipMemcpyAsync(dp, pk.data(), nnz * 4, hipMemcpyHostToDevice, c->stream));
       d.packed = dp;
     }
-    if (compact && n <= 8192) {
+    const char* sl_env = std::getenv("PDBO_CSR_SLICED");
+    if (compact && n <= 8192 && !(sl_env && std::atoi(sl_env) == 0)) {
       // the interleaved layout of the 1024-thread kernels (slices of 64
       // positions, each as long as its longest row), used when it takes no
       // more LDS than row_ptr and the entries in CSR order

@@ -228,3 +228,30 @@ def test_oracle_trajectory_short_horizon():
     X, Y, _ = ctx.get_state()
     ref = gda.run(oq.QuboProblem(q, 1.0), x0, p, T=5)
     assert np.max(np.abs(X - ref.X)) < 1e-4 and np.max(np.abs(Y - ref.Y)) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["maxcut_n2000", "wide_n900", "maxcut_n8000_inplace"])
+def test_interleaved_layout_same_bits_as_csr_order(name, monkeypatch):
+    """The interleaved entries (csr_sliced_*) run the same sums in the same order
+    as the entries in CSR order: a run of 300 iterations ends in the same state
+    and incumbent, bit for bit."""
+    P = require_gpu()
+    mk, B, s = CASES[name]
+    q = mk()
+    s = W.qubo_scale(q) if s is None else s
+    p = W.gda_params("maxcut", B=B, T=300, scale=s, tile=1)
+    x0 = W.x0_uniform(2, 9, B, q.n)
+    say(f"[csr layouts] case={name} n={q.n} B={B}")
+    out = []
+    for sliced in ("1", "0"):
+        monkeypatch.setenv("PDBO_CSR_SLICED", sliced)
+        ctx = P.qubo_gda_init(q, p, x0)
+        out.append(ctx.tile_name)
+        ctx.step(300)
+        out.append((ctx.get_state(), ctx.result()))
+    assert out[0] == VARIANT[name] and out[2] == VARIANT[name].replace("sliced", "packed")
+    (xa, ya, ta), ra = out[1]
+    (xb, yb, tb), rb = out[3]
+    assert ta == tb == 300 and np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    assert (ra["best_obj"], ra["best_restart"], ra["best_iter"]) == (rb["best_obj"], rb["best_restart"], rb["best_iter"])
+    assert np.array_equal(ra["best_x"], rb["best_x"])
