@@ -366,10 +366,13 @@ def workload_mis(args, P):
     size, inside = om.set_size(E, r["best_x"][None])
     nnz = int(q.row_ptr[-1])
     step_ms = k_step[0] / max(k_step[1], 1)
-    # compulsory bytes of one iteration: the CSR arrays once, x read and
-    # written, y read and written (node-major float32); the neighbour gathers
-    # (B floats per nonzero) are served by the caches
-    hbm = 8 * nnz + 4 * (n + 1) + 16 * n * B
+    # compulsory bytes of one iteration: the CSR arrays once (one packed
+    # 4-byte word per entry when n <= 65536 and |Ahat_ij| < 2^15, |Ahat_ij| at
+    # most 2 max|Q_ij|; else column and value, 8 bytes), x read and written, y
+    # read and written (node-major float32); the neighbour gathers (B floats
+    # per nonzero) are served by the caches
+    packed = n <= 65536 and 2 * int(np.abs(q.vals).max(initial=0)) < 32768
+    hbm = (4 if packed else 8) * nnz + 4 * (n + 1) + 16 * n * B
     gath = 4 * B * nnz
     out = dict(metric="restart-iterations/s, MIS (penalised QUBO, lam = 4)", value=B * T / el,
                unit=UNIT, workload=f"MIS d-regular n={n} d={d}, B={B}, T={T}, row-parallel CSR",

@@ -1739,6 +1739,7 @@ static pdbo_status spmm_init(const CsrCanon* C, const RealCanon* R, const pdbo_p
     const std::vector<int32_t>& hrp = C ? C->rp : R->rp;
     const std::vector<int32_t>& hcol = C ? C->col : R->col;
     const int64_t nnz = (int64_t)hcol.size();
+    std::vector<uint32_t> hpk;  // host staging, alive until init syncs
     SpmmDev& d = c->spmm;
     std::memset(&d, 0, sizeof(d));
     d.n = n;
@@ -1778,6 +1779,16 @@ static pdbo_status spmm_init(const CsrCanon* C, const RealCanon* R, const pdbo_p
       HIPCHK(c, hipMemcpyAsync(cp, C->cp.data(), n * 8, hipMemcpyHostToDevice, c->stream));
       d.val = val;
       d.cp = cp;
+      if (n <= 65536 && C->amax <= 32767 && nnz > 0) {
+        // one 4-byte word per entry (16-bit column, 16-bit value)
+        hpk.resize((size_t)nnz);
+        for (int64_t q = 0; q < nnz; ++q)
+          hpk[q] = (uint32_t)hcol[q] | ((uint32_t)(uint16_t)(int16_t)C->val[q] << 16);
+        uint32_t* dpk = nullptr;
+        STCHK(dalloc(c, &dpk, nnz));
+        HIPCHK(c, hipMemcpyAsync(dpk, hpk.data(), (size_t)nnz * 4, hipMemcpyHostToDevice, c->stream));
+        d.packed = dpk;
+      }
     } else {
       float* valf = nullptr;
       int32_t *Adig = nullptr, *Cdig = nullptr;

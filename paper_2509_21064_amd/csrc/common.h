@@ -311,6 +311,8 @@ struct SpmmDev {
   const int32_t* row_ptr;
   const int32_t* col;
   const int32_t* val;     // canonical Ahat
+  const uint32_t* packed; // column | value << 16 when n <= 65536 and |Ahat_ij| < 2^15 (integer
+                          // weights), read instead of col and val; else null
   const float* cps;       // c'/s
   const int64_t* cp;      // c'
   float* X[2];            // node-major ping-pong iterate

@@ -26,7 +26,8 @@ namespace pdbo {
 constexpr int kSpmmThreads = 256;  // four waves
 constexpr int kSpmmUnroll = 8;     // gathers in flight per lane
 
-template <int GK, int MODE>
+// PK: the entries are read as packed words (D.packed), one load instead of two.
+template <int GK, int MODE, bool PK>
 __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parity, float* Gout) {
   __shared__ unsigned long long sred[2][64];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -43,6 +44,7 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parit
   const int32_t* __restrict__ rp = D.row_ptr;
   const int32_t* __restrict__ col = D.col;
   const int32_t* __restrict__ val = D.val;
+  const uint32_t* __restrict__ pk = D.packed;
   if (MODE != 2 && tid < 128) sred[tid >> 6][tid & 63] = 0;
   // the previous iteration's new incumbent, still in Xn (see SpmmDev::win)
   const int win = (MODE == 0 && D.win) ? *D.win : -1;
@@ -61,8 +63,14 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parit
       float xk[kSpmmUnroll];
 #pragma unroll
       for (int u = 0; u < kSpmmUnroll; ++u) {
-        c[u] = col[p + u];
-        v[u] = val[p + u];
+        if constexpr (PK) {
+          const uint32_t e = pk[p + u];
+          c[u] = (int)(e & 0xffffu);
+          v[u] = (int)(int16_t)(e >> 16);
+        } else {
+          c[u] = col[p + u];
+          v[u] = val[p + u];
+        }
       }
 #pragma unroll
       for (int u = 0; u < kSpmmUnroll; ++u) xk[u] = Xc[(size_t)c[u] * B + b];
@@ -78,8 +86,14 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parit
 #pragma unroll
       for (int u = 0; u < kSpmmUnroll; ++u) {
         const int q = min(p + u, pe - 1);
-        c[u] = col[q];
-        v[u] = p + u < pe ? val[q] : 0;
+        if constexpr (PK) {
+          const uint32_t e = pk[q];
+          c[u] = (int)(e & 0xffffu);
+          v[u] = p + u < pe ? (int)(int16_t)(e >> 16) : 0;
+        } else {
+          c[u] = col[q];
+          v[u] = p + u < pe ? val[q] : 0;
+        }
       }
 #pragma unroll
       for (int u = 0; u < kSpmmUnroll; ++u) xk[u] = Xc[(size_t)c[u] * B + b];
@@ -126,7 +140,11 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmDev D, int parit
 hipError_t launch_spmm(const SpmmDev& d, int mode, int parity, float* G, hipStream_t s) {
   if (d.ndig > 0) return launch_spmm_real(d, mode, parity, G, s);
   const dim3 grid(d.grid), blk(kSpmmThreads);
-#define PDBO_S(GK, M) hipLaunchKernelGGL((spmm_kernel<GK, M>), grid, blk, 0, s, d, parity, G)
+#define PDBO_S(GK, M)                                                                  \
+  if (d.packed)                                                                        \
+    hipLaunchKernelGGL((spmm_kernel<GK, M, true>), grid, blk, 0, s, d, parity, G);     \
+  else                                                                                 \
+    hipLaunchKernelGGL((spmm_kernel<GK, M, false>), grid, blk, 0, s, d, parity, G)
   const int gk = d.gp.gkind;
   if (mode == 1) {
     PDBO_S(0, 1);
